@@ -296,8 +296,8 @@ def calibrate(g, *, seed=1, omega_: float, delta=0.1, sigma_mode=SIGMA_AUTO):
 
 
 def uniform_delta(n: int, delta: float):
-    """delta_L = delta_U = delta / (4n): a valid allocation (sum = delta / 2)."""
-    L = np.full(n, -np.log(delta / (4.0 * n)))
+    """delta_L = delta_U = 0.999 delta / (4n): a valid allocation (sum below delta / 2)."""
+    L = np.full(n, -np.log(0.999 * delta / (4.0 * n)))
     return L, L.copy()
 
 

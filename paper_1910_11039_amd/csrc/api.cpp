@@ -1,0 +1,984 @@
+// Host driver behind the C-ABI (include/kadabra.h): contexts, graph upload,
+// sampler state, the epoch loop and the phases of a run (Sec. III-A:
+// diameter -> omega, calibration of delta_L/delta_U, adaptive sampling).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "kad_internal.h"
+
+using namespace kad;
+
+namespace {
+
+thread_local std::string g_err;
+
+kad_status fail(kad_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(KAD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct kad_ctx {
+    int device;
+    hipStream_t stream;
+    bool own_stream;
+    int cu_count;
+};
+
+struct kad_graph {
+    kad_ctx *ctx;
+    int device;
+    int32_t n;
+    int64_t nnz;
+    int64_t *d_rp;
+    int32_t *d_ci;
+    DevGraph dev() const { return DevGraph{n, nnz, d_rp, d_ci}; }
+};
+
+struct kad_sampler {
+    kad_ctx *ctx;
+    int device;
+    const kad_graph *g;
+    kad_opts o;
+    double omega;
+    int64_t vd_lo, vd_hi;
+    unsigned long long cap;
+    uint32_t E;
+    int slots, block, inflight;
+    // device state
+    uint32_t *c, *sf[2], *cprime, *scratch_counts;
+    double *LL, *LU, *lo_hi, *partials, *prior;
+    Rec *recs;
+    int32_t *queues, *mbufs;
+    uint32_t *stamps;
+    unsigned long long *work_ctr;
+    SampleStats *stats;
+    EpochState *es;
+    void *hist;
+    int32_t hist_cap;
+    EpochState *h_es;   // pinned mirror
+    // phases
+    bool delta_ready, ran_alloc;
+    uint64_t tau0;
+    double C;
+    std::vector<float> mlp_params, mlp_norm;
+    bool have_mlp;
+    kad_result res;
+    double t_kernel_ms;
+    uint32_t launches;
+    hipGraphExec_t gexec;
+    bool have_graph;
+};
+
+extern "C" const char *kad_last_error(void) { return g_err.c_str(); }
+
+extern "C" kad_status kad_create(int device, void *hip_stream, kad_ctx **out)
+{
+    if (!out) return fail(KAD_EINVAL, "out is null");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(KAD_EINVAL, "no such device");
+    HIPCHK(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
+    if (std::string(prop.gcnArchName).find("gfx950") == std::string::npos)
+        return fail(KAD_EDEVICE, std::string("kernels are built for gfx950, device is ") + prop.gcnArchName);
+    kad_ctx *c = new kad_ctx();
+    c->device = device;
+    c->cu_count = prop.multiProcessorCount;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    } else {
+        hipError_t e = hipStreamCreate(&c->stream);
+        if (e != hipSuccess) { delete c; return fail(KAD_EDEVICE, hipGetErrorString(e)); }
+        c->own_stream = true;
+    }
+    *out = c;
+    return KAD_OK;
+}
+
+extern "C" void kad_destroy(kad_ctx *ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    if (ctx->own_stream) {
+        hipStreamSynchronize(ctx->stream);
+        hipStreamDestroy(ctx->stream);
+    }
+    delete ctx;
+}
+
+static kad_status validate_graph(int32_t n, int64_t nnz, const int64_t *rp, const int32_t *ci)
+{
+    if (rp[0] != 0 || rp[n] != nnz) return fail(KAD_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] = nnz");
+    for (int32_t v = 0; v < n; ++v) {
+        if (rp[v + 1] < rp[v]) return fail(KAD_EINVAL, "row_ptr not monotone");
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
+            const int32_t u = ci[e];
+            if (u < 0 || u >= n) return fail(KAD_EINVAL, "column index out of range");
+            if (u == v) return fail(KAD_EINVAL, "self loop");
+            if (e > rp[v] && ci[e - 1] >= u) return fail(KAD_EINVAL, "row not strictly ascending");
+            if (!std::binary_search(ci + rp[u], ci + rp[u + 1], v))
+                return fail(KAD_EINVAL, "graph not symmetric");
+        }
+    }
+    std::vector<int32_t> queue;
+    std::vector<char> seen(n, 0);
+    queue.reserve(n);
+    queue.push_back(0);
+    seen[0] = 1;
+    for (size_t h = 0; h < queue.size(); ++h) {
+        const int32_t u = queue[h];
+        for (int64_t e = rp[u]; e < rp[u + 1]; ++e)
+            if (!seen[ci[e]]) { seen[ci[e]] = 1; queue.push_back(ci[e]); }
+    }
+    if ((int32_t)queue.size() != n) return fail(KAD_ENOTCONNECTED, "graph is not connected");
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_graph_upload(kad_ctx *ctx, int32_t n, int64_t nnz, const int64_t *h_row_ptr,
+                                       const int32_t *h_col_idx, uint32_t flags, kad_graph **out)
+{
+    if (!ctx || !out || !h_row_ptr || (nnz > 0 && !h_col_idx)) return fail(KAD_EINVAL, "null argument");
+    if (n < 2) return fail(KAD_EINVAL, "need at least two vertices");
+    if (nnz < 0 || nnz >= (int64_t)1 << 31) return fail(KAD_EOVERFLOW, "nnz must be below 2^31");
+    if (h_row_ptr[n] != nnz) return fail(KAD_EINVAL, "row_ptr[n] != nnz");
+    if (flags & KAD_GRAPH_VALIDATE) {
+        kad_status st = validate_graph(n, nnz, h_row_ptr, h_col_idx);
+        if (st != KAD_OK) return st;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    kad_graph *g = new kad_graph();
+    g->ctx = ctx;
+    g->device = ctx->device;
+    g->n = n;
+    g->nnz = nnz;
+    if (hipMalloc((void **)&g->d_rp, sizeof(int64_t) * ((size_t)n + 1)) != hipSuccess ||
+        hipMalloc((void **)&g->d_ci, sizeof(int32_t) * std::max<int64_t>(nnz, 1)) != hipSuccess) {
+        delete g;
+        return fail(KAD_ENOMEM, "graph allocation failed");
+    }
+    HIPCHK(hipMemcpyAsync(g->d_rp, h_row_ptr, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice,
+                          ctx->stream));
+    if (nnz > 0)
+        HIPCHK(hipMemcpyAsync(g->d_ci, h_col_idx, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice,
+                              ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *out = g;
+    return KAD_OK;
+}
+
+extern "C" void kad_graph_free(kad_graph *g)
+{
+    if (!g) return;
+    hipSetDevice(g->device);
+    hipFree(g->d_rp);
+    hipFree(g->d_ci);
+    delete g;
+}
+
+extern "C" double kad_omega(int64_t vd_lo, int64_t vd_hi, double eps, double delta)
+{
+    auto om = [&](int64_t vd) {
+        double lg = 0.0;
+        if (vd - 2 >= 1) {
+            int64_t x = vd - 2, fl = 0;
+            while (x > 1) { x >>= 1; ++fl; }
+            lg = (double)fl;
+        }
+        return 0.5 / (eps * eps) * (lg + 1.0 + log(2.0 / delta));
+    };
+    const double lo = om(vd_lo), hi = om(vd_hi);
+    return lo == hi ? lo : hi;
+}
+
+extern "C" kad_status kad_vd_bracket(kad_ctx *ctx, const kad_graph *g, int64_t *vd_lo, int64_t *vd_hi)
+{
+    if (!ctx || !g || !vd_lo || !vd_hi) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(device_vd_bracket(g->dev(), ctx->stream, vd_lo, vd_hi));
+    return KAD_OK;
+}
+
+static void free_sampler(kad_sampler *s)
+{
+    if (s->have_graph) hipGraphExecDestroy(s->gexec);
+    void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->cprime, s->scratch_counts, s->LL, s->LU, s->lo_hi,
+                    s->partials, s->prior, s->recs, s->queues, s->mbufs, s->stamps, s->work_ctr,
+                    s->stats, s->es, s->hist};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    if (s->h_es) hipHostFree(s->h_es);
+    delete s;
+}
+
+extern "C" void kad_sampler_free(kad_sampler *s)
+{
+    if (!s) return;
+    hipSetDevice(s->device);
+    hipDeviceSynchronize();
+    free_sampler(s);
+}
+
+static kad_status reset_epochs(kad_sampler *s)
+{
+    hipStream_t st = s->ctx->stream;
+    EpochState init;
+    memset(&init, 0, sizeof(init));
+    init.all_ok = 1;
+    const double inf = INFINITY;
+    memcpy(&init.min_margin_bits, &inf, sizeof(double));
+    init.range[0] = 0;
+    init.range[1] = std::min<unsigned long long>(s->E, s->cap);
+    init.range[2] = 0;
+    HIPCHK(hipMemcpyAsync(s->es, &init, sizeof(init), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(s->c, 0, sizeof(uint32_t) * s->g->n, st));
+    HIPCHK(hipMemsetAsync(s->sf[0], 0, sizeof(uint32_t) * s->g->n, st));
+    HIPCHK(hipMemsetAsync(s->sf[1], 0, sizeof(uint32_t) * s->g->n, st));
+    HIPCHK(hipMemsetAsync(s->work_ctr, 0, sizeof(unsigned long long), st));
+    HIPCHK(hipMemsetAsync(s->stats, 0, sizeof(SampleStats), st));
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const kad_opts *o,
+                                       kad_sampler **out)
+{
+    if (!ctx || !g || !o || !out) return fail(KAD_EINVAL, "null argument");
+    if (!(o->epsilon > 0.0 && o->epsilon < 1.0)) return fail(KAD_EINVAL, "epsilon must lie in (0, 1)");
+    if (!(o->delta > 0.0 && o->delta < 1.0)) return fail(KAD_EINVAL, "delta must lie in (0, 1)");
+    if (o->alloc_mode < 0 || o->alloc_mode > 2) return fail(KAD_EINVAL, "bad alloc_mode");
+    if (o->sigma_mode < 0 || o->sigma_mode > 1) return fail(KAD_EINVAL, "bad sigma_mode");
+    const int block = o->block_size ? o->block_size : 256;
+    if (block != 64 && block != 128 && block != 256 && block != 512)
+        return fail(KAD_EINVAL, "block_size must be 64, 128, 256 or 512");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    kad_sampler *s = new kad_sampler();
+    memset(&s->res, 0, sizeof(s->res));
+    s->ctx = ctx;
+    s->device = ctx->device;
+    s->g = g;
+    s->o = *o;
+    s->block = block;
+    const int32_t n = g->n;
+
+    // Phase 1 (Sec. III-A): omega from the vertex-diameter bracket.
+    const double t0 = now_ms();
+    if (o->omega_override > 0.0) {
+        s->omega = o->omega_override;
+        s->vd_lo = s->vd_hi = 0;
+    } else {
+        hipError_t e = device_vd_bracket(g->dev(), st, &s->vd_lo, &s->vd_hi);
+        if (e != hipSuccess) { delete s; return fail(KAD_EDEVICE, hipGetErrorString(e)); }
+        s->omega = kad_omega(s->vd_lo, s->vd_hi, o->epsilon, o->delta);
+    }
+    s->res.t_omega_ms = now_ms() - t0;
+    s->cap = (unsigned long long)ceil(s->omega);
+
+    // Slots: as many concurrent samples as fit the visited-state budget.
+    const size_t per_slot = (size_t)n * (sizeof(Rec) + 2 * sizeof(int32_t));
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    size_t budget = o->visited_budget_bytes ? (size_t)o->visited_budget_bytes : free_b / 2;
+    // Persistent workgroups: more slots than can be resident would only
+    // start once resident ones exit, so the default is one full wave of them.
+    int want = o->slots > 0 ? o->slots : ctx->cu_count * sampler_blocks_per_cu(block);
+    int fit = (int)std::min<size_t>(budget / per_slot, 1 << 16);
+    s->slots = std::max(1, std::min(want, fit));
+    if (o->slots > 0 && s->slots < o->slots) {
+        delete s;
+        return fail(KAD_ENOMEM, "requested slots exceed the visited-state budget");
+    }
+    if (o->epoch_size) s->E = o->epoch_size;
+    else s->E = (uint32_t)std::min<unsigned long long>(std::max<unsigned long long>(4ull * s->slots, 1024ull), 16384ull);
+    s->inflight = o->epochs_in_flight > 0 ? o->epochs_in_flight : 4;
+    s->hist_cap = (int32_t)((s->cap + s->E - 1) / s->E + 2);
+
+    auto alloc = [&](void **p, size_t bytes) {
+        return hipMalloc(p, std::max<size_t>(bytes, 16)) == hipSuccess;
+    };
+    bool ok = alloc((void **)&s->c, 4ull * n) && alloc((void **)&s->sf[0], 4ull * n) &&
+              alloc((void **)&s->sf[1], 4ull * n) && alloc((void **)&s->cprime, 4ull * n) &&
+              alloc((void **)&s->scratch_counts, 4ull * n) && alloc((void **)&s->LL, 8ull * n) &&
+              alloc((void **)&s->LU, 8ull * n) && alloc((void **)&s->lo_hi, 64) &&
+              alloc((void **)&s->partials, 8 * alloc_partials(n)) && alloc((void **)&s->prior, 8ull * n) &&
+              alloc((void **)&s->recs, sizeof(Rec) * (size_t)n * s->slots) &&
+              alloc((void **)&s->queues, 4ull * n * s->slots) && alloc((void **)&s->mbufs, 4ull * n * s->slots) &&
+              alloc((void **)&s->stamps, 4ull * s->slots) && alloc((void **)&s->work_ctr, 8) &&
+              alloc((void **)&s->stats, sizeof(SampleStats)) && alloc((void **)&s->es, sizeof(EpochState)) &&
+              alloc((void **)&s->hist, epoch_hist_bytes() * s->hist_cap);
+    if (!ok || hipHostMalloc((void **)&s->h_es, sizeof(EpochState), 0) != hipSuccess) {
+        free_sampler(s);
+        return fail(KAD_ENOMEM, "sampler allocation failed");
+    }
+    HIPCHK(hipMemsetAsync(s->recs, 0, sizeof(Rec) * (size_t)n * s->slots, st));
+    HIPCHK(hipMemsetAsync(s->stamps, 0, 4ull * s->slots, st));
+    kad_status rs = reset_epochs(s);
+    if (rs != KAD_OK) { free_sampler(s); return rs; }
+    HIPCHK(hipStreamSynchronize(st));
+    s->res.omega = s->omega;
+    s->res.vd_lo = s->vd_lo;
+    s->res.vd_hi = s->vd_hi;
+    s->res.epoch_size = s->E;
+    s->res.slots = s->slots;
+    *out = s;
+    return KAD_OK;
+}
+
+static SampleLaunch base_launch(kad_sampler *s)
+{
+    SampleLaunch a;
+    memset(&a, 0, sizeof(a));
+    a.g = s->g->dev();
+    a.seed = s->o.seed;
+    a.stream = KAD_STREAM_ADS;
+    a.sf[0] = s->sf[0];
+    a.sf[1] = s->sf[1];
+    a.recs = s->recs;
+    a.queues = s->queues;
+    a.mbufs = s->mbufs;
+    a.stamps = s->stamps;
+    a.work_ctr = s->work_ctr;
+    a.stats = s->stats;
+    a.sigma_fp = s->o.sigma_mode == KAD_SIGMA_FP;
+    return a;
+}
+
+// Non-adaptive samples [first, first+count) of `stream` counted into `target`.
+static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, uint64_t count,
+                             uint32_t *target, int32_t *paths, int64_t *info, int32_t max_len)
+{
+    if (count == 0) return KAD_OK;
+    hipStream_t st = s->ctx->stream;
+    SampleLaunch a = base_launch(s);
+    a.stream = stream;
+    a.first = first;
+    a.count = count;
+    a.sf[0] = target;
+    a.sf[1] = target;
+    a.paths = paths;
+    a.info = info;
+    a.max_len = max_len;
+    HIPCHK(hipMemsetAsync(s->work_ctr, 0, sizeof(unsigned long long), st));
+    const int slots = (int)std::min<uint64_t>(s->slots, count);
+    HIPCHK(launch_sampler(a, slots, s->block, st));
+    // the epoch loop expects the sample counter at zero
+    HIPCHK(hipMemsetAsync(s->work_ctr, 0, sizeof(unsigned long long), st));
+    return KAD_OK;
+}
+
+static kad_status check_stats_error(kad_sampler *s)
+{
+    SampleStats h;
+    HIPCHK(hipMemcpyAsync(&h, s->stats, sizeof(h), hipMemcpyDeviceToHost, s->ctx->stream));
+    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    if (h.error == 1) return fail(KAD_ENOTCONNECTED, "a sampled pair has no path: graph not connected");
+    if (h.error == 2) return fail(KAD_EOVERFLOW, "a path is longer than max_len - 1");
+    if (h.error == 3) return fail(KAD_EDEVICE, "internal error: a path choice found no candidate");
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_set_delta(kad_sampler *s, const double *h_delta_L, const double *h_delta_U)
+{
+    if (!s || !h_delta_L || !h_delta_U) return fail(KAD_EINVAL, "null argument");
+    const int32_t n = s->g->n;
+    long double sum = 0.0L;
+    for (int32_t v = 0; v < n; ++v) {
+        if (!(h_delta_L[v] > 0.0 && h_delta_L[v] < 1.0 && h_delta_U[v] > 0.0 && h_delta_U[v] < 1.0))
+            return fail(KAD_EINVAL, "delta values must lie in (0, 1)");
+        sum += (long double)h_delta_L[v] + (long double)h_delta_U[v];
+    }
+    if (!(sum < 0.5L * (long double)s->o.delta))
+        return fail(KAD_EINVAL, "sum of delta_L + delta_U must stay below delta / 2");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    hipStream_t st = s->ctx->stream;
+    HIPCHK(hipMemcpyAsync(s->prior, h_delta_L, 8ull * n, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_neglog(n, s->prior, s->LL, st));
+    HIPCHK(hipMemcpyAsync(s->prior, h_delta_U, 8ull * n, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_neglog(n, s->prior, s->LU, st));
+    HIPCHK(hipStreamSynchronize(st));
+    s->delta_ready = true;
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_set_mlp_weights(kad_sampler *s, const float *h_params, const float *h_norm)
+{
+    if (!s || !h_params || !h_norm) return fail(KAD_EINVAL, "null argument");
+    s->mlp_params.assign(h_params, h_params + 4481);
+    s->mlp_norm.assign(h_norm, h_norm + 6);
+    s->have_mlp = true;
+    return KAD_OK;
+}
+
+// Learned prior: features -> standardise -> MLP -> b_hat = max(0, e^y - 1/omega).
+static kad_status learned_prior(kad_sampler *s)
+{
+    hipStream_t st = s->ctx->stream;
+    const int32_t n = s->g->n;
+    float *feat = nullptr, *params = nullptr, *norm = nullptr, *yhat = nullptr;
+    HIPCHK(hipMallocAsync((void **)&feat, sizeof(float) * 3 * (size_t)n, st));
+    HIPCHK(hipMallocAsync((void **)&yhat, sizeof(float) * (size_t)n, st));
+    HIPCHK(hipMallocAsync((void **)&params, sizeof(float) * 4481, st));
+    HIPCHK(hipMallocAsync((void **)&norm, sizeof(float) * 6, st));
+    HIPCHK(hipMemcpyAsync(params, s->mlp_params.data(), sizeof(float) * 4481, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(norm, s->mlp_norm.data(), sizeof(float) * 6, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_features(s->g->dev(), feat, st));
+    HIPCHK(launch_normalize(n, feat, norm, st));
+    HIPCHK(launch_mlp_forward(params, feat, n, yhat, st));
+    HIPCHK(launch_prior_from_mlp(n, yhat, s->omega, s->prior, st));
+    HIPCHK(hipFreeAsync(feat, st));
+    HIPCHK(hipFreeAsync(yhat, st));
+    HIPCHK(hipFreeAsync(params, st));
+    HIPCHK(hipFreeAsync(norm, st));
+    return KAD_OK;
+}
+
+// Checks the allocation's budget on the host: every delta in (0, 1) and
+// the (compensated) sum of delta_L + delta_U below delta / 2.
+static bool alloc_is_valid(kad_sampler *s)
+{
+    const int32_t n = s->g->n;
+    std::vector<double> LL(n), LU(n);
+    if (hipMemcpy(LL.data(), s->LL, 8ull * n, hipMemcpyDeviceToHost) != hipSuccess) return false;
+    if (hipMemcpy(LU.data(), s->LU, 8ull * n, hipMemcpyDeviceToHost) != hipSuccess) return false;
+    double sum = 0.0, comp = 0.0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (!std::isfinite(LL[v]) || !std::isfinite(LU[v]) || LL[v] <= 0.0 || LU[v] <= 0.0) return false;
+        const double x = exp(-LL[v]) + exp(-LU[v]);
+        const double y = x - comp;
+        const double t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+    }
+    return sum <= 0.5 * s->o.delta;
+}
+
+static kad_status ensure_delta(kad_sampler *s)
+{
+    if (s->delta_ready) return KAD_OK;
+    hipStream_t st = s->ctx->stream;
+    const int32_t n = s->g->n;
+    const double t0 = now_ms();
+    AllocArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = n;
+    a.delta = s->o.delta;
+    a.beta = 1e-3;
+    a.lo_hi = s->lo_hi;
+    a.partials = s->partials;
+    a.LL = s->LL;
+    a.LU = s->LU;
+    bool learned = false;
+    if (s->o.alloc_mode == KAD_ALLOC_EXPLICIT) return fail(KAD_ESTATE, "EXPLICIT mode needs kad_set_delta first");
+    if (s->o.alloc_mode == KAD_ALLOC_LEARNED) {
+        if (!s->have_mlp) return fail(KAD_ESTATE, "LEARNED mode needs kad_set_mlp_weights first");
+        kad_status r = learned_prior(s);
+        if (r != KAD_OK) return r;
+        a.dense_prior = s->prior;
+        double C = 0.0;
+        HIPCHK(run_alloc(a, st, &C));
+        HIPCHK(hipStreamSynchronize(st));
+        s->C = C;
+        learned = alloc_is_valid(s);   // fallback to the plain allocation otherwise
+    }
+    if (!learned) {
+        // Phase 2 (Sec. III-A): tau0 = ceil(omega / 100) non-adaptive samples on stream 1.
+        s->tau0 = (uint64_t)ceil(s->omega / 100.0);
+        HIPCHK(hipMemsetAsync(s->cprime, 0, 4ull * n, st));
+        kad_status r = count_into(s, KAD_STREAM_CALIB, 0, s->tau0, s->cprime, nullptr, nullptr, 0);
+        if (r != KAD_OK) return r;
+        a.counts = s->cprime;
+        a.tau0 = (double)s->tau0;
+        double C = 0.0;
+        HIPCHK(run_alloc(a, st, &C));
+        HIPCHK(hipStreamSynchronize(st));
+        s->C = C;
+        r = check_stats_error(s);
+        if (r != KAD_OK) return r;
+        HIPCHK(hipMemsetAsync(s->stats, 0, sizeof(SampleStats), st));
+    }
+    s->res.tau0 = learned ? 0 : s->tau0;
+    s->res.t_alloc_ms = now_ms() - t0;
+    s->delta_ready = true;
+    return KAD_OK;
+}
+
+// Enqueue one epoch: sampler (range read on the device) + merge/stop.
+static kad_status enqueue_epoch(kad_sampler *s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    hipStream_t st = s->ctx->stream;
+    SampleLaunch a = base_launch(s);
+    a.dev_range = s->es->range;
+    a.stop_flag = &s->es->stopped;
+    if (ev0) HIPCHK(hipEventRecord(ev0, st));
+    HIPCHK(launch_sampler(a, s->slots, s->block, st));
+    if (ev1) HIPCHK(hipEventRecord(ev1, st));
+    HIPCHK(launch_merge_stop_impl(s->g->dev(), s->c, s->sf[0], s->sf[1], s->LL, s->LU, s->omega,
+                                  s->o.epsilon, s->cap, s->E, s->es, s->work_ctr, s->hist, s->hist_cap,
+                                  st));
+    return KAD_OK;
+}
+
+static kad_status read_state(kad_sampler *s)
+{
+    HIPCHK(hipMemcpyAsync(s->h_es, s->es, sizeof(EpochState), hipMemcpyDeviceToHost, s->ctx->stream));
+    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_step_epoch(kad_sampler *s, int *stopped)
+{
+    if (!s || !stopped) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    kad_status r = ensure_delta(s);
+    if (r != KAD_OK) return r;
+    r = read_state(s);
+    if (r != KAD_OK) return r;
+    if (!s->h_es->stopped) {
+        r = enqueue_epoch(s, nullptr, nullptr);
+        if (r != KAD_OK) return r;
+        r = read_state(s);
+        if (r != KAD_OK) return r;
+        r = check_stats_error(s);
+        if (r != KAD_OK) return r;
+    }
+    *stopped = s->h_es->stopped;
+    return KAD_OK;
+}
+
+static kad_status fill_result(kad_sampler *s)
+{
+    SampleStats h;
+    HIPCHK(hipMemcpy(&h, s->stats, sizeof(h), hipMemcpyDeviceToHost));
+    kad_result &r = s->res;
+    r.tau = s->h_es->tau;
+    r.epochs = (uint32_t)s->h_es->epoch;
+    r.stop_reason = s->h_es->reason;
+    r.max_f = s->h_es->max_f;
+    r.max_g = s->h_es->max_g;
+    r.min_margin = s->h_es->min_margin;
+    r.edges_scanned = (int64_t)h.edges;
+    r.vertices_expanded = (int64_t)h.expanded;
+    r.vertices_visited = (int64_t)h.visited;
+    r.pred_edges = (int64_t)h.pred_edges;
+    r.path_vertices = (int64_t)h.path_vertices;
+    r.fp_samples = (int64_t)h.fp_samples;
+    r.t_sample_kernel_ms = s->t_kernel_ms;
+    r.sample_launches = s->launches;
+    r.epoch_size = s->E;
+    r.slots = s->slots;
+    return KAD_OK;
+}
+
+static kad_status build_graph(kad_sampler *s)
+{
+    hipStream_t st = s->ctx->stream;
+    hipGraph_t graph;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < s->inflight; ++i) {
+        kad_status r = enqueue_epoch(s, nullptr, nullptr);
+        if (r != KAD_OK) {
+            hipStreamEndCapture(st, &graph);
+            return r;
+        }
+    }
+    HIPCHK(hipStreamEndCapture(st, &graph));
+    HIPCHK(hipGraphInstantiate(&s->gexec, graph, nullptr, nullptr, 0));
+    HIPCHK(hipGraphDestroy(graph));
+    s->have_graph = true;
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
+{
+    if (!s) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    hipStream_t st = s->ctx->stream;
+    const double t_start = now_ms();
+    kad_status r = ensure_delta(s);
+    if (r != KAD_OK) return r;
+    const double t_ads0 = now_ms();
+    r = read_state(s);
+    if (r != KAD_OK) return r;
+    const unsigned long long epoch_at_start = s->h_es->epoch;
+    const bool timing = s->o.timing != 0;
+    std::vector<hipEvent_t> evs;
+    if (s->o.use_graphs && !timing && !s->have_graph) {
+        r = build_graph(s);
+        if (r != KAD_OK) return r;
+    }
+    while (!s->h_es->stopped) {
+        if (s->have_graph && !timing) {
+            HIPCHK(hipGraphLaunch(s->gexec, st));
+        } else {
+            for (int i = 0; i < s->inflight; ++i) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (timing) {
+                    HIPCHK(hipEventCreate(&e0));
+                    HIPCHK(hipEventCreate(&e1));
+                    evs.push_back(e0);
+                    evs.push_back(e1);
+                }
+                r = enqueue_epoch(s, e0, e1);
+                if (r != KAD_OK) return r;
+            }
+        }
+        r = read_state(s);
+        if (r != KAD_OK) return r;
+    }
+    const double t_ads1 = now_ms();
+    if (timing) {
+        // only launches that sampled (before the stop) are counted
+        const size_t ran = (size_t)(s->h_es->epoch - epoch_at_start);
+        for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+            if (i / 2 < ran) {
+                float ms = 0.0f;
+                HIPCHK(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
+                s->t_kernel_ms += ms;
+                s->launches += 1;
+            }
+        }
+        for (hipEvent_t e : evs) hipEventDestroy(e);
+    }
+    r = check_stats_error(s);
+    if (r != KAD_OK) return r;
+    s->res.t_ads_ms = t_ads1 - t_ads0;
+    s->res.t_total_ms = s->res.t_omega_ms + (t_ads1 - t_start);
+    r = fill_result(s);
+    if (r != KAD_OK) return r;
+    if (out) *out = s->res;
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_fetch_result(const kad_sampler *s, kad_result *out)
+{
+    if (!s || !out) return fail(KAD_EINVAL, "null argument");
+    *out = s->res;
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_fetch_counts(const kad_sampler *s, uint32_t *h_c, uint64_t *h_tau)
+{
+    if (!s || !h_c) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    EpochState es;
+    HIPCHK(hipMemcpyAsync(h_c, s->c, 4ull * s->g->n, hipMemcpyDeviceToHost, s->ctx->stream));
+    HIPCHK(hipMemcpyAsync(&es, s->es, sizeof(es), hipMemcpyDeviceToHost, s->ctx->stream));
+    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    if (h_tau) *h_tau = es.tau;
+    return KAD_OK;
+}
+
+static kad_status fetch_tau(const kad_sampler *s, double *tau)
+{
+    EpochState es;
+    HIPCHK(hipMemcpyAsync(&es, s->es, sizeof(es), hipMemcpyDeviceToHost, s->ctx->stream));
+    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    if (es.tau == 0) return fail(KAD_ESTATE, "no samples merged yet");
+    *tau = (double)es.tau;
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_fetch_btilde(const kad_sampler *s, double *h_b)
+{
+    if (!s || !h_b) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    double tau;
+    kad_status r = fetch_tau(s, &tau);
+    if (r != KAD_OK) return r;
+    hipStream_t st = s->ctx->stream;
+    double *d = nullptr;
+    HIPCHK(hipMallocAsync((void **)&d, 8ull * s->g->n, st));
+    HIPCHK(launch_btilde(s->g->n, s->c, tau, d, st));
+    HIPCHK(hipMemcpyAsync(h_b, d, 8ull * s->g->n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipFreeAsync(d, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_fetch_fg(const kad_sampler *s, double *h_f, double *h_g)
+{
+    if (!s || !h_f || !h_g) return fail(KAD_EINVAL, "null argument");
+    if (!s->delta_ready) return fail(KAD_ESTATE, "delta allocation not done");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    double tau;
+    kad_status r = fetch_tau(s, &tau);
+    if (r != KAD_OK) return r;
+    hipStream_t st = s->ctx->stream;
+    double *f = nullptr, *g = nullptr;
+    HIPCHK(hipMallocAsync((void **)&f, 8ull * s->g->n, st));
+    HIPCHK(hipMallocAsync((void **)&g, 8ull * s->g->n, st));
+    HIPCHK(launch_fg(s->g->n, s->c, tau, s->LL, s->LU, s->omega, f, g, st));
+    HIPCHK(hipMemcpyAsync(h_f, f, 8ull * s->g->n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_g, g, 8ull * s->g->n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipFreeAsync(f, st));
+    HIPCHK(hipFreeAsync(g, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_fetch_delta(const kad_sampler *s, double *h_lnInvDL, double *h_lnInvDU)
+{
+    if (!s || !h_lnInvDL || !h_lnInvDU) return fail(KAD_EINVAL, "null argument");
+    if (!s->delta_ready) return fail(KAD_ESTATE, "delta allocation not done");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    HIPCHK(hipMemcpyAsync(h_lnInvDL, s->LL, 8ull * s->g->n, hipMemcpyDeviceToHost, s->ctx->stream));
+    HIPCHK(hipMemcpyAsync(h_lnInvDU, s->LU, 8ull * s->g->n, hipMemcpyDeviceToHost, s->ctx->stream));
+    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_fetch_history(const kad_sampler *s, uint32_t epochs, double *h_hist)
+{
+    if (!s || !h_hist) return fail(KAD_EINVAL, "null argument");
+    if ((int32_t)epochs > s->hist_cap) return fail(KAD_EINVAL, "more epochs than recorded");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    const size_t rec = epoch_hist_bytes();
+    std::vector<unsigned char> buf(rec * epochs);
+    if (epochs) {
+        HIPCHK(hipMemcpyAsync(buf.data(), s->hist, rec * epochs, hipMemcpyDeviceToHost, s->ctx->stream));
+        HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    }
+    for (uint32_t i = 0; i < epochs; ++i) {
+        double v[3];
+        int32_t ok;
+        memcpy(v, buf.data() + rec * i, sizeof(v));
+        memcpy(&ok, buf.data() + rec * i + sizeof(v), sizeof(ok));
+        h_hist[4 * i + 0] = v[0];
+        h_hist[4 * i + 1] = v[1];
+        h_hist[4 * i + 2] = v[2];
+        h_hist[4 * i + 3] = ok ? 1.0 : 0.0;
+    }
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_fetch_calibration(const kad_sampler *s, uint32_t *h_cprime, uint64_t *h_tau0,
+                                            double *h_C)
+{
+    if (!s) return fail(KAD_EINVAL, "null argument");
+    if (!s->delta_ready || s->o.alloc_mode == KAD_ALLOC_EXPLICIT)
+        return fail(KAD_ESTATE, "no calibration has run");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    if (h_cprime) {
+        HIPCHK(hipMemcpyAsync(h_cprime, s->cprime, 4ull * s->g->n, hipMemcpyDeviceToHost, s->ctx->stream));
+        HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    }
+    if (h_tau0) *h_tau0 = s->res.tau0;
+    if (h_C) *h_C = s->C;
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_count_samples(kad_sampler *s, uint64_t stream, uint64_t first, uint64_t count,
+                                        uint32_t *h_c)
+{
+    if (!s || !h_c) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    hipStream_t st = s->ctx->stream;
+    const int32_t n = s->g->n;
+    HIPCHK(hipMemsetAsync(s->scratch_counts, 0, 4ull * n, st));
+    HIPCHK(hipMemsetAsync(s->stats, 0, sizeof(SampleStats), st));
+    kad_status r = count_into(s, stream, first, count, s->scratch_counts, nullptr, nullptr, 0);
+    if (r != KAD_OK) return r;
+    r = check_stats_error(s);
+    if (r != KAD_OK) return r;
+    std::vector<uint32_t> tmp(n);
+    HIPCHK(hipMemcpy(tmp.data(), s->scratch_counts, 4ull * n, hipMemcpyDeviceToHost));
+    for (int32_t v = 0; v < n; ++v) h_c[v] += tmp[v];
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_sample_paths(kad_sampler *s, uint64_t stream, uint64_t first, uint32_t count,
+                                       int32_t max_len, int32_t *h_paths, int64_t *h_info)
+{
+    if (!s || !h_paths || !h_info || max_len < 2) return fail(KAD_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    hipStream_t st = s->ctx->stream;
+    const int32_t n = s->g->n;
+    int32_t *dp = nullptr;
+    int64_t *di = nullptr;
+    HIPCHK(hipMallocAsync((void **)&dp, sizeof(int32_t) * (size_t)count * max_len + 4, st));
+    HIPCHK(hipMallocAsync((void **)&di, sizeof(int64_t) * (size_t)count * 8 + 8, st));
+    HIPCHK(hipMemsetAsync(dp, 0xFF, sizeof(int32_t) * (size_t)count * max_len + 4, st));
+    HIPCHK(hipMemsetAsync(s->scratch_counts, 0, 4ull * n, st));
+    HIPCHK(hipMemsetAsync(s->stats, 0, sizeof(SampleStats), st));
+    kad_status r = count_into(s, stream, first, count, s->scratch_counts, dp, di, max_len);
+    if (r == KAD_OK) r = check_stats_error(s);
+    if (r == KAD_OK) {
+        HIPCHK(hipMemcpyAsync(h_paths, dp, sizeof(int32_t) * (size_t)count * max_len, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h_info, di, sizeof(int64_t) * (size_t)count * 8, hipMemcpyDeviceToHost, st));
+    }
+    hipFreeAsync(dp, st);
+    hipFreeAsync(di, st);
+    HIPCHK(hipStreamSynchronize(st));
+    return r;
+}
+
+extern "C" kad_status kad_philox(kad_ctx *ctx, uint64_t seed, uint64_t stream, uint64_t first,
+                                 uint32_t count, uint32_t nwords, uint64_t *h_out)
+{
+    if (!ctx || !h_out || count == 0 || nwords == 0) return fail(KAD_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    uint64_t *d = nullptr;
+    const size_t bytes = sizeof(uint64_t) * (size_t)count * nwords;
+    HIPCHK(hipMallocAsync((void **)&d, bytes, st));
+    HIPCHK(launch_philox(seed, stream, first, count, nwords, d, st));
+    HIPCHK(hipMemcpyAsync(h_out, d, bytes, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipFreeAsync(d, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return KAD_OK;
+}
+
+// ------------------------------------------------------------- learned prior
+
+struct kad_mlp {
+    kad_ctx *ctx;
+    int device;
+    float *params, *grad, *m, *v, *loss;
+    float *scratch;
+    size_t scratch_cap;
+    int step;
+};
+
+extern "C" kad_status kad_features(kad_ctx *ctx, const kad_graph *g, float *d_out, float *h_out)
+{
+    if (!ctx || !g || (!d_out && !h_out)) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    float *d = d_out;
+    if (!d) HIPCHK(hipMallocAsync((void **)&d, sizeof(float) * 3 * (size_t)g->n, st));
+    HIPCHK(launch_features(g->dev(), d, st));
+    if (!d_out) {
+        HIPCHK(hipMemcpyAsync(h_out, d, sizeof(float) * 3 * (size_t)g->n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipFreeAsync(d, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_mlp_create(kad_ctx *ctx, const float *h_params, kad_mlp **out)
+{
+    if (!ctx || !h_params || !out) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    kad_mlp *m = new kad_mlp();
+    m->ctx = ctx;
+    m->device = ctx->device;
+    if (hipMalloc((void **)&m->params, 4 * 4481) != hipSuccess || hipMalloc((void **)&m->grad, 4 * 4481) != hipSuccess ||
+        hipMalloc((void **)&m->m, 4 * 4481) != hipSuccess || hipMalloc((void **)&m->v, 4 * 4481) != hipSuccess ||
+        hipMalloc((void **)&m->loss, 16) != hipSuccess) {
+        delete m;
+        return fail(KAD_ENOMEM, "mlp allocation failed");
+    }
+    HIPCHK(hipMemcpy(m->params, h_params, 4 * 4481, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(m->m, 0, 4 * 4481));
+    HIPCHK(hipMemset(m->v, 0, 4 * 4481));
+    *out = m;
+    return KAD_OK;
+}
+
+extern "C" void kad_mlp_free(kad_mlp *m)
+{
+    if (!m) return;
+    hipSetDevice(m->device);
+    hipDeviceSynchronize();
+    hipFree(m->params);
+    hipFree(m->grad);
+    hipFree(m->m);
+    hipFree(m->v);
+    hipFree(m->loss);
+    if (m->scratch) hipFree(m->scratch);
+    delete m;
+}
+
+extern "C" kad_status kad_mlp_get_params(const kad_mlp *m, float *h_params)
+{
+    if (!m || !h_params) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(m->ctx->device));
+    HIPCHK(hipMemcpyAsync(h_params, m->params, 4 * 4481, hipMemcpyDeviceToHost, m->ctx->stream));
+    HIPCHK(hipStreamSynchronize(m->ctx->stream));
+    return KAD_OK;
+}
+
+static kad_status mlp_scratch(kad_mlp *m, int64_t rows)
+{
+    const size_t need = mlp_scratch_floats(rows);
+    if (need > m->scratch_cap) {
+        if (m->scratch) hipFree(m->scratch);
+        m->scratch = nullptr;
+        if (hipMalloc((void **)&m->scratch, need * sizeof(float)) != hipSuccess)
+            return fail(KAD_ENOMEM, "mlp scratch allocation failed");
+        m->scratch_cap = need;
+    }
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_mlp_loss_grad(kad_mlp *m, const float *d_x, const float *d_y, int64_t rows,
+                                        float *h_loss, float *h_grad)
+{
+    if (!m || !d_x || !d_y || rows <= 0) return fail(KAD_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(m->ctx->device));
+    kad_status r = mlp_scratch(m, rows);
+    if (r != KAD_OK) return r;
+    hipStream_t st = m->ctx->stream;
+    HIPCHK(launch_mlp_loss_grad(m->params, d_x, d_y, rows, m->grad, m->loss, m->scratch, st));
+    if (h_grad) HIPCHK(hipMemcpyAsync(h_grad, m->grad, 4 * 4481, hipMemcpyDeviceToHost, st));
+    if (h_loss) HIPCHK(hipMemcpyAsync(h_loss, m->loss, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_mlp_train_step(kad_mlp *m, const float *d_x, const float *d_y, int64_t rows,
+                                         float lr, float *h_loss)
+{
+    if (!m || !d_x || !d_y || rows <= 0) return fail(KAD_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(m->ctx->device));
+    kad_status r = mlp_scratch(m, rows);
+    if (r != KAD_OK) return r;
+    hipStream_t st = m->ctx->stream;
+    HIPCHK(launch_mlp_loss_grad(m->params, d_x, d_y, rows, m->grad, m->loss, m->scratch, st));
+    m->step += 1;
+    HIPCHK(launch_adam(m->params, m->grad, m->m, m->v, 4481, m->step, lr, st));
+    if (h_loss) {
+        HIPCHK(hipMemcpyAsync(h_loss, m->loss, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_mlp_forward(kad_mlp *m, const float *d_x, int64_t rows, float *d_y, float *h_y)
+{
+    if (!m || !d_x || rows <= 0 || (!d_y && !h_y)) return fail(KAD_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(m->ctx->device));
+    hipStream_t st = m->ctx->stream;
+    float *y = d_y;
+    if (!y) HIPCHK(hipMallocAsync((void **)&y, sizeof(float) * (size_t)rows, st));
+    HIPCHK(launch_mlp_forward(m->params, d_x, rows, y, st));
+    if (!d_y) {
+        HIPCHK(hipMemcpyAsync(h_y, y, sizeof(float) * (size_t)rows, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipFreeAsync(y, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return KAD_OK;
+}

@@ -1,0 +1,461 @@
+// Epoch boundary, stop rule, delta allocation, diameter bracket, Philox dump.
+//
+// Epoch boundary (Sec. III-B, Alg. 2 on one GPU): the samples of epoch k
+// were counted into state frame SF[k & 1]; the merge kernel adds that frame
+// into c~, clears it for epoch k + 2 (two frames suffice: frames of epoch
+// e - 2 are never touched again), and evaluates the stop rule on exactly
+// the samples [0, tau) -- the consistent snapshot the rule needs because f
+// and g are not monotone.
+//
+// Stop rule (Sec. III-A): stop once f(b~(v), delta_L(v), omega, tau) < eps
+// and g(b~(v), delta_U(v), omega, tau) < eps for every vertex, or tau has
+// reached ceil(omega).  With L = ln(1/delta) and a = omega / tau (KADABRA's
+// Bernstein-type bounds, the reading used throughout):
+//   f = L/tau ((1/3 - a) + sqrt((1/3 - a)^2 + 2 b~ omega / L)), capped at b~
+//   g = L/tau ((1/3 + a) + sqrt((1/3 + a)^2 + 2 b~ omega / L)), capped at 1 - b~
+// evaluated in FP64 (the only FP64 on the sampling path), without FMA
+// contraction, in the order written.
+#include <math.h>
+
+#include "kad_internal.h"
+#include "philox.h"
+
+namespace kad {
+namespace {
+
+constexpr int MB = 256;   // merge block size
+
+__device__ __forceinline__ double fval(double bt, double L, double omega, double tau)
+{
+    const double a = (1.0 / 3.0) - omega / tau;
+    const double q = a * a + ((2.0 * bt) * omega) / L;
+    const double f = (L / tau) * (a + sqrt(q));
+    return f < bt ? f : bt;
+}
+__device__ __forceinline__ double gval(double bt, double L, double omega, double tau)
+{
+    const double a = (1.0 / 3.0) + omega / tau;
+    const double q = a * a + ((2.0 * bt) * omega) / L;
+    const double g = (L / tau) * (a + sqrt(q));
+    const double cap = 1.0 - bt;
+    return g < cap ? g : cap;
+}
+__device__ __forceinline__ uint64_t bits(double d) { return __builtin_bit_cast(uint64_t, d); }
+__device__ __forceinline__ double dbl(uint64_t b) { return __builtin_bit_cast(double, b); }
+
+struct EpochHist {
+    double max_f, max_g, min_margin;
+    int32_t ok;
+    int32_t pad;
+};
+
+__global__ __launch_bounds__(MB) void k_merge_stop(int32_t n, uint32_t *c, uint32_t *sf0, uint32_t *sf1,
+                                                   const double *LL, const double *LU, double omega,
+                                                   double eps, unsigned long long cap,
+                                                   unsigned long long E, EpochState *es,
+                                                   unsigned long long *work_ctr, EpochHist *hist,
+                                                   int32_t hist_cap)
+{
+    if (__hip_atomic_load(&es->stopped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const unsigned long long first = es->range[0], count = es->range[1];
+    uint32_t *sf = (es->range[2] & 1) ? sf1 : sf0;
+    const unsigned long long tau_u = first + count;
+    const double tau = (double)tau_u;
+    int ok = 1;
+    double mf = 0.0, mg = 0.0, mm = INFINITY;
+    for (int32_t v = blockIdx.x * MB + threadIdx.x; v < n; v += gridDim.x * MB) {
+        const uint32_t cv = c[v] + sf[v];
+        c[v] = cv;
+        sf[v] = 0;
+        const double bt = (double)cv / tau;
+        const double f = fval(bt, LL[v], omega, tau);
+        const double g = gval(bt, LU[v], omega, tau);
+        ok &= (f < eps && g < eps) ? 1 : 0;
+        mf = f > mf ? f : mf;
+        mg = g > mg ? g : mg;
+        double mar = eps - (f > g ? f : g);
+        mar = mar < 0 ? -mar : mar;
+        mm = mar < mm ? mar : mm;
+    }
+    // block reduction
+    __shared__ int s_ok;
+    __shared__ unsigned long long s_f, s_g, s_m;
+    if (threadIdx.x == 0) {
+        s_ok = 1;
+        s_f = 0;
+        s_g = 0;
+        s_m = bits(INFINITY);
+    }
+    __syncthreads();
+    if (!ok) atomicAnd(&s_ok, 0);
+    atomicMax(&s_f, (unsigned long long)bits(mf));
+    atomicMax(&s_g, (unsigned long long)bits(mg));
+    atomicMin(&s_m, (unsigned long long)bits(mm));
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (!s_ok) atomicAnd(&es->all_ok, 0);
+    atomicMax(&es->max_f_bits, s_f);
+    atomicMax(&es->max_g_bits, s_g);
+    atomicMin(&es->min_margin_bits, s_m);
+    __threadfence();
+    const unsigned long long done = atomicAdd(&es->blocks_done, 1ull);
+    if (done != gridDim.x - 1) return;
+    __threadfence();
+    // last block: decide, record, prepare the next epoch's range
+    const int all = __hip_atomic_load(&es->all_ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double F = dbl(__hip_atomic_load(&es->max_f_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const double G = dbl(__hip_atomic_load(&es->max_g_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const double M = dbl(__hip_atomic_load(&es->min_margin_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const unsigned long long ep = es->epoch;
+    if ((int64_t)ep < hist_cap) {
+        hist[ep].max_f = F;
+        hist[ep].max_g = G;
+        hist[ep].min_margin = M;
+        hist[ep].ok = all;
+    }
+    es->tau = tau_u;
+    es->epoch = ep + 1;
+    es->max_f = F;
+    es->max_g = G;
+    es->min_margin = M;
+    int stop = 0, reason = KAD_STOP_NONE;
+    if (all) { stop = 1; reason = KAD_STOP_COND; }
+    else if (tau_u >= cap) { stop = 1; reason = KAD_STOP_OMEGA; }
+    es->reason = reason;
+    es->all_ok = 1;
+    es->max_f_bits = 0;
+    es->max_g_bits = 0;
+    es->min_margin_bits = bits(INFINITY);
+    es->blocks_done = 0;
+    const unsigned long long nfirst = tau_u;
+    es->range[0] = nfirst;
+    es->range[1] = stop ? 0 : ((cap - nfirst) < E ? (cap - nfirst) : E);
+    es->range[2] = ep + 1;
+    *work_ctr = 0;
+    __threadfence();
+    __hip_atomic_store(&es->stopped, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_fg(int32_t n, const uint32_t *c, double tau, const double *LL, const double *LU,
+                     double omega, double *f, double *g)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const double bt = (double)c[v] / tau;
+        f[v] = fval(bt, LL[v], omega, tau);
+        g[v] = gval(bt, LU[v], omega, tau);
+    }
+}
+
+__global__ void k_btilde(int32_t n, const uint32_t *c, double tau, double *b)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        b[v] = (double)c[v] / tau;
+}
+
+__global__ void k_neglog(int32_t n, const double *in, double *out)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        out[v] = -log(in[v]);
+}
+
+__global__ void k_philox(uint64_t seed, uint64_t stream, uint64_t first, uint32_t count, uint32_t nwords,
+                         uint64_t *out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    SampleDraws dr;
+    dr.init(seed, stream, first + i);
+    for (uint32_t j = 0; j < nwords; ++j) out[i * nwords + j] = dr.get(j);
+}
+
+// ---- delta allocation (calibration, Sec. III-A phase 2; reading:
+// delta(v) = (1 - beta) exp(-C / prior(v)) + beta delta / (4n), with C the
+// smallest value for which the sum over vertices with prior > 0 of
+// exp(-C / prior(v)) stays below delta / 4 (shrunk by 1e-9), by bisection).
+
+constexpr int AB = 256;
+
+__device__ __forceinline__ double prior_of(const AllocArgs &a, int32_t v)
+{
+    return a.counts ? (double)a.counts[v] / a.tau0 : a.dense_prior[v];
+}
+
+__global__ __launch_bounds__(AB) void k_alloc_count(AllocArgs a, unsigned long long *K)
+{
+    unsigned long long k = 0;
+    for (int32_t v = blockIdx.x * AB + threadIdx.x; v < a.n; v += gridDim.x * AB)
+        k += prior_of(a, v) > 0.0 ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o);
+    if ((threadIdx.x & 63) == 0 && k) atomicAdd(K, k);
+}
+
+// Partial sums of exp(-mid / prior) over fixed vertex ranges, reduced in a
+// fixed order (run-to-run deterministic).
+__global__ __launch_bounds__(AB) void k_alloc_sum(AllocArgs a, int32_t chunk)
+{
+    const double lo = a.lo_hi[0], hi = a.lo_hi[1];
+    if (a.lo_hi[2] != 0.0) return;
+    const double mid = 0.5 * (lo + hi);
+    const int32_t beg = blockIdx.x * chunk;
+    const int32_t end = min(a.n, beg + chunk);
+    double s = 0.0;
+    for (int32_t v = beg + threadIdx.x; v < end; v += AB) {
+        const double p = prior_of(a, v);
+        if (p > 0.0) s = s + exp(-mid / p);
+    }
+    __shared__ double red[AB];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = AB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
+}
+
+__global__ void k_alloc_update(double *lo_hi, const double *partials, int32_t nb, double target)
+{
+    if (lo_hi[2] != 0.0) return;
+    const double lo = lo_hi[0], hi = lo_hi[1];
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) { lo_hi[2] = 1.0; return; }
+    double s = 0.0;
+    for (int32_t b = 0; b < nb; ++b) s = s + partials[b];
+    if (s <= target) lo_hi[1] = mid; else lo_hi[0] = mid;
+}
+
+__global__ void k_alloc_delta(AllocArgs a, double C)
+{
+    const double floor_d = a.beta * a.delta / (4.0 * (double)a.n);
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
+        const double p = prior_of(a, v);
+        double dv = floor_d;
+        if (p > 0.0) dv = (1.0 - a.beta) * exp(-C / p) + floor_d;
+        const double L = -log(dv);
+        a.LL[v] = L;
+        a.LU[v] = L;
+    }
+}
+
+// ---- BFS sweeps for the vertex-diameter bracket (omega, Sec. III-A phase 1)
+
+__global__ void k_argmax_degree(DevGraph g, unsigned long long *best)
+{
+    unsigned long long b = 0;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
+        const unsigned long long deg = (unsigned long long)(g.rp[v + 1] - g.rp[v]);
+        const unsigned long long key = (deg << 32) | (0xFFFFFFFFull - (unsigned long long)v);
+        b = key > b ? key : b;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(b, o);
+        b = y > b ? y : b;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(best, b);
+}
+
+__global__ void k_bfs_init(int32_t n, int32_t *dist, int32_t src, int32_t *fr, int32_t *sizes)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        dist[v] = (v == src) ? 0 : -1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        fr[0] = src;
+        sizes[0] = 1;   // current frontier size
+        sizes[1] = 0;   // next frontier size
+        sizes[2] = 0;   // depth of the current frontier
+    }
+}
+
+// One BFS level: a wave per frontier vertex, lanes stride its adjacency.
+// sizes = {cur, next, depth}; an empty frontier makes the launch a no-op.
+__global__ void k_bfs_level(DevGraph g, int32_t *dist, const int32_t *fr, int32_t *nf, int32_t *sizes)
+{
+    const int32_t cur = sizes[0];
+    const int32_t depth = sizes[2];
+    const int lane = threadIdx.x & 63;
+    const int32_t wpb = blockDim.x >> 6;
+    for (int32_t i = blockIdx.x * wpb + (threadIdx.x >> 6); i < cur; i += gridDim.x * wpb) {
+        const int32_t u = fr[i];
+        for (int64_t e = g.rp[u] + lane; e < g.rp[u + 1]; e += 64) {
+            const int32_t w = g.ci[e];
+            if (atomicCAS(&dist[w], -1, depth + 1) == -1) nf[atomicAdd(&sizes[1], 1)] = w;
+        }
+    }
+}
+
+__global__ void k_bfs_swap(int32_t *sizes, int32_t *last_depth)
+{
+    if (sizes[0] == 0) return;
+    if (sizes[1] > 0) {
+        sizes[2] += 1;
+        *last_depth = sizes[2];
+    }
+    sizes[0] = sizes[1];
+    sizes[1] = 0;
+}
+
+__global__ void k_min_at_depth(int32_t n, const int32_t *dist, int32_t depth, int32_t *out)
+{
+    int32_t b = 0x7fffffff;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (dist[v] == depth && v < b) b = v;
+    if (b != 0x7fffffff) atomicMin(out, b);
+}
+
+#define CK(expr)                                \
+    do {                                        \
+        hipError_t ck_ = (expr);                \
+        if (ck_ != hipSuccess) return ck_;      \
+    } while (0)
+
+int grid_for(int64_t n, int block, int cap = 8192)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_merge_stop_impl(const DevGraph &g, uint32_t *c, uint32_t *sf0, uint32_t *sf1,
+                                  const double *LL, const double *LU, double omega, double eps,
+                                  unsigned long long cap, unsigned long long E, EpochState *es,
+                                  unsigned long long *work_ctr, void *hist, int32_t hist_cap,
+                                  hipStream_t st)
+{
+    hipLaunchKernelGGL(k_merge_stop, dim3(grid_for(g.n, MB, 2048)), dim3(MB), 0, st, g.n, c, sf0, sf1,
+                       LL, LU, omega, eps, cap, E, es, work_ctr, (EpochHist *)hist, hist_cap);
+    return hipGetLastError();
+}
+
+size_t epoch_hist_bytes() { return sizeof(EpochHist); }
+
+hipError_t launch_fg(int32_t n, const uint32_t *c, double tau, const double *LL, const double *LU,
+                     double omega, double *f, double *g, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fg, dim3(grid_for(n, 256)), dim3(256), 0, st, n, c, tau, LL, LU, omega, f, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_btilde(int32_t n, const uint32_t *c, double tau, double *b, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_btilde, dim3(grid_for(n, 256)), dim3(256), 0, st, n, c, tau, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_neglog(int32_t n, const double *in, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_neglog, dim3(grid_for(n, 256)), dim3(256), 0, st, n, in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(uint64_t seed, uint64_t stream, uint64_t first, uint32_t count,
+                         uint32_t nwords, uint64_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_philox, dim3((count + 255) / 256), dim3(256), 0, st, seed, stream, first, count,
+                       nwords, out);
+    return hipGetLastError();
+}
+
+hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host)
+{
+    hipError_t e;
+    const double target = 0.25 * a.delta * (1.0 - 1e-9);
+    unsigned long long *dK = nullptr;
+    if ((e = hipMallocAsync((void **)&dK, sizeof(unsigned long long), st)) != hipSuccess) return e;
+    CK(hipMemsetAsync(dK, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_alloc_count, dim3(grid_for(a.n, AB, 1024)), dim3(AB), 0, st, a, dK);
+    unsigned long long K = 0;
+    CK(hipMemcpyAsync(&K, dK, sizeof(K), hipMemcpyDeviceToHost, st));
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    CK(hipFreeAsync(dK, st));
+    double C = 0.0;
+    if (K > 0) {
+        double init[3] = {0.0, log((double)K / target), 0.0};
+        if (init[1] < 0.0) init[1] = 0.0;
+        CK(hipMemcpyAsync(a.lo_hi, init, sizeof(init), hipMemcpyHostToDevice, st));
+        const int32_t chunk = 4096;
+        const int32_t nb = (a.n + chunk - 1) / chunk;
+        for (int it = 0; it < 200; ++it) {
+            hipLaunchKernelGGL(k_alloc_sum, dim3(nb), dim3(AB), 0, st, a, chunk);
+            hipLaunchKernelGGL(k_alloc_update, dim3(1), dim3(1), 0, st, a.lo_hi, a.partials, nb, target);
+            if ((it & 31) == 31) {
+                double fin[3];
+                CK(hipMemcpyAsync(fin, a.lo_hi, sizeof(fin), hipMemcpyDeviceToHost, st));
+                if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+                if (fin[2] != 0.0) break;
+            }
+        }
+        double fin[3];
+        CK(hipMemcpyAsync(fin, a.lo_hi, sizeof(fin), hipMemcpyDeviceToHost, st));
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        C = fin[1];
+    }
+    hipLaunchKernelGGL(k_alloc_delta, dim3(grid_for(a.n, 256)), dim3(256), 0, st, a, C);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    *C_host = C;
+    return hipSuccess;
+}
+
+size_t alloc_partials(int32_t n) { return (size_t)((n + 4095) / 4096); }
+
+hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, int64_t *vd_hi)
+{
+    hipError_t e;
+    const int32_t n = g.n;
+    int32_t *dist = nullptr, *fa = nullptr, *fb = nullptr, *sizes = nullptr;
+    unsigned long long *best = nullptr;
+    if ((e = hipMallocAsync((void **)&dist, sizeof(int32_t) * n, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&fa, sizeof(int32_t) * n, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&fb, sizeof(int32_t) * n, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&sizes, sizeof(int32_t) * 8, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&best, sizeof(unsigned long long), st)) != hipSuccess) return e;
+    CK(hipMemsetAsync(best, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_argmax_degree, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, g, best);
+    unsigned long long hb = 0;
+    CK(hipMemcpyAsync(&hb, best, sizeof(hb), hipMemcpyDeviceToHost, st));
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    const int32_t r = (int32_t)(0xFFFFFFFFull - (hb & 0xFFFFFFFFull));
+
+    auto bfs = [&](int32_t src, int32_t *ecc, int32_t *far) -> hipError_t {
+        hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, 256)), dim3(256), 0, st, n, dist, src, fa, sizes);
+        hipMemsetAsync(sizes + 3, 0, sizeof(int32_t), st);   // last nonempty depth
+        int32_t *cur = fa, *nxt = fb;
+        for (;;) {
+            for (int i = 0; i < 32; ++i) {
+                hipLaunchKernelGGL(k_bfs_level, dim3(1024), dim3(256), 0, st, g, dist, cur, nxt, sizes);
+                hipLaunchKernelGGL(k_bfs_swap, dim3(1), dim3(1), 0, st, sizes, sizes + 3);
+                int32_t *tmp = cur; cur = nxt; nxt = tmp;
+            }
+            int32_t hs[4];
+            CK(hipMemcpyAsync(hs, sizes, sizeof(hs), hipMemcpyDeviceToHost, st));
+            hipError_t ee = hipStreamSynchronize(st);
+            if (ee != hipSuccess) return ee;
+            if (hs[0] == 0) { *ecc = hs[3]; break; }
+        }
+        int32_t init = 0x7fffffff;
+        CK(hipMemcpyAsync(sizes + 4, &init, sizeof(int32_t), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_min_at_depth, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, dist, *ecc,
+                           sizes + 4);
+        CK(hipMemcpyAsync(far, sizes + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        return hipStreamSynchronize(st);
+    };
+    int32_t er, ea, eb, a, b, cfar;
+    if ((e = bfs(r, &er, &a)) != hipSuccess) return e;
+    if ((e = bfs(a, &ea, &b)) != hipSuccess) return e;
+    if ((e = bfs(b, &eb, &cfar)) != hipSuccess) return e;
+    const int32_t lb = ea > eb ? ea : eb;
+    int32_t mn = er < ea ? er : ea;
+    mn = eb < mn ? eb : mn;
+    *vd_lo = (int64_t)lb + 1;
+    *vd_hi = 2 * (int64_t)mn + 1;
+    CK(hipFreeAsync(dist, st));
+    CK(hipFreeAsync(fa, st));
+    CK(hipFreeAsync(fb, st));
+    CK(hipFreeAsync(sizes, st));
+    CK(hipFreeAsync(best, st));
+    return hipGetLastError();
+}
+
+}  // namespace kad

@@ -1,0 +1,136 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/kadabra.h"
+
+namespace kad {
+
+// Per-vertex, per-slot record of the bidirectional BFS (16 bytes).
+//   key   = (stamp << 32) | state; a record belongs to the current sample of
+//           its slot only when stamp equals the slot's current stamp, so a
+//           slot never has to clear its records between samples.
+//   state = side << 31 | meet << 30 | depth (depth < 2^30).
+//   sig   = number of shortest paths from the side's root (uint64, or the
+//           bits of an FP64 value in FP mode).
+struct Rec {
+    uint32_t state;
+    uint32_t stamp;
+    uint64_t sig;
+};
+static_assert(sizeof(Rec) == 16, "record layout");
+
+constexpr uint32_t SIDE_BIT = 1u << 31;
+constexpr uint32_t MEET_BIT = 1u << 30;
+constexpr uint32_t DEPTH_MASK = MEET_BIT - 1;
+
+// Per-sample statistics accumulated by the sampler kernel (device).
+struct SampleStats {
+    unsigned long long edges;          // adjacency entries read by expansions (final attempt)
+    unsigned long long expanded;       // frontier vertices expanded
+    unsigned long long visited;        // vertices newly discovered
+    unsigned long long pred_edges;     // predecessor edges summed into sigma
+    unsigned long long path_vertices;  // interior vertices counted
+    unsigned long long fp_samples;     // samples in FP mode
+    unsigned long long samples;        // samples finished
+    unsigned long long edges_all;      // adjacency entries read including redone attempts
+    int error;                         // nonzero: a sample found the graph disconnected
+    int pad[3];
+};
+
+struct DevGraph {
+    int32_t n;
+    int64_t nnz;
+    const int64_t *rp;
+    const int32_t *ci;
+};
+
+// Arguments of one sampler launch.
+struct SampleLaunch {
+    DevGraph g;
+    uint64_t seed;
+    uint64_t stream;
+    uint64_t first;                 // first sample index of the launch
+    uint64_t count;                 // samples in the launch (from host), or
+    const unsigned long long *dev_range;  // if non-null: {first, count, sf_index} read on the device
+    uint32_t *sf[2];                // counter buffers (state frames)
+    Rec *recs;                      // slots * n records
+    int32_t *queues;                // slots * n frontier entries
+    int32_t *mbufs;                 // slots * n meet-set entries
+    uint32_t *stamps;               // slots stamps
+    unsigned long long *work_ctr;   // next sample to take (device counter)
+    SampleStats *stats;
+    const int32_t *stop_flag;       // if non-null and set: skip the launch
+    int sigma_fp;                   // 1: FP mode for every sample
+    int32_t *paths;                 // optional per-sample paths [count][max_len]
+    int64_t *info;                  // optional per-sample info  [count][8]
+    int32_t max_len;
+};
+
+hipError_t launch_sampler(const SampleLaunch &a, int slots, int block, hipStream_t st);
+int sampler_max_block();
+int sampler_blocks_per_cu(int block);   // resident workgroups per CU
+
+// Epoch merge + stop rule (FP64).
+struct EpochState {
+    unsigned long long tau;        // samples merged so far
+    unsigned long long epoch;      // epochs merged so far
+    int32_t stopped;               // 1 once the stop rule holds or tau hit the cap
+    int32_t reason;                // KAD_STOP_*
+    double max_f, max_g, min_margin;
+    unsigned long long blocks_done;
+    int32_t all_ok;                // reduction scratch for the epoch in flight
+    int32_t pad;
+    unsigned long long max_f_bits, max_g_bits, min_margin_bits;
+    unsigned long long range[3];   // {first, count, sf_index} of the next epoch
+};
+
+hipError_t launch_merge_stop_impl(const DevGraph &g, uint32_t *c, uint32_t *sf0, uint32_t *sf1,
+                                  const double *LL, const double *LU, double omega, double eps,
+                                  unsigned long long cap, unsigned long long E, EpochState *es,
+                                  unsigned long long *work_ctr, void *hist, int32_t hist_cap,
+                                  hipStream_t st);
+size_t epoch_hist_bytes();   // per-epoch record: max_f, max_g, min_margin (f64), ok (i32), pad
+size_t alloc_partials(int32_t n);
+hipError_t launch_fg(int32_t n, const uint32_t *c, double tau, const double *LL, const double *LU,
+                     double omega, double *f, double *g, hipStream_t st);
+hipError_t launch_btilde(int32_t n, const uint32_t *c, double tau, double *b, hipStream_t st);
+hipError_t launch_neglog(int32_t n, const double *in, double *out, hipStream_t st);
+hipError_t launch_philox(uint64_t seed, uint64_t stream, uint64_t first, uint32_t count,
+                         uint32_t nwords, uint64_t *out, hipStream_t st);
+
+// Delta allocation from a prior (calibration counts or learned prior).
+// prior(v) = counts[v] / tau0 when counts != null, else dense_prior[v].
+struct AllocArgs {
+    int32_t n;
+    const uint32_t *counts;
+    double tau0;
+    const double *dense_prior;
+    double delta, beta;
+    double *lo_hi;       // device: {lo, hi, done}
+    double *partials;    // device scratch, one per block
+    double *LL, *LU;     // out
+};
+hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host);
+
+// Vertex-diameter bracket by BFS sweeps on the device.
+hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, int64_t *vd_hi);
+
+// Learned prior.
+hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st);
+hipError_t launch_normalize(int32_t n, float *x, const float *norm, hipStream_t st);
+hipError_t launch_mlp_forward(const float *params, const float *x, int64_t rows, float *y,
+                              hipStream_t st);
+hipError_t launch_mlp_loss_grad(const float *params, const float *x, const float *y, int64_t rows,
+                                float *grad, float *loss, float *scratch, hipStream_t st);
+hipError_t launch_adam(float *params, const float *grad, float *m, float *v, int count, int step,
+                       float lr, hipStream_t st);
+hipError_t launch_prior_from_mlp(int32_t n, const float *yhat, double omega, double *prior,
+                                 hipStream_t st);
+size_t mlp_scratch_floats(int64_t rows);
+
+}  // namespace kad

@@ -1,0 +1,317 @@
+// Learned prior for the delta allocation (not in the paper; the paper's
+// calibration phase, Sec. III-A phase 2, picks delta_L/delta_U from a few
+// samples, and any split with sum below delta is valid -- so a predicted
+// prior may replace those samples without touching the guarantee).
+//
+//  * features of vertex v: ln(1 + deg v), mean over neighbours u of
+//    ln(1 + deg u), ln(1 + sum over neighbours of deg u) -- one wave per
+//    vertex, lanes stride the adjacency, FP64 inside, FP32 out;
+//  * MLP 3 -> 64 -> 64 -> 1 with ReLU, FP32.  A workgroup of four waves
+//    takes 64 rows at a time; the three dense 64x64 contractions (hidden
+//    layer forward, its weight gradient, and the back-propagated signal)
+//    run on the FP32 matrix cores (v_mfma_f32_16x16x4f32, one 16-row strip
+//    per wave); the 3-wide input layer and the 64-wide output dot product
+//    are plain FMAs.  Gradients are reduced per workgroup and then summed
+//    over workgroups in a fixed order.
+#include <math.h>
+
+#include "kad_internal.h"
+
+namespace kad {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int TR = 64;          // rows per tile
+constexpr int LD = 68;          // padded row stride in LDS (floats)
+constexpr int NP = 4481;        // parameters
+constexpr int PSTRIDE = NP + 1; // per-block partial: gradient then loss
+constexpr int OFF_W1 = 0, OFF_B1 = 192, OFF_W2 = 256, OFF_B2 = 4352, OFF_W3 = 4416, OFF_B3 = 4480;
+
+__global__ void k_features(DevGraph g, float *out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t v = wave; v < g.n; v += waves) {
+        const int64_t beg = g.rp[v], end = g.rp[v + 1];
+        double acc = 0.0, sd = 0.0;
+        for (int64_t e = beg + lane; e < end; e += 64) {
+            const int32_t u = g.ci[e];
+            const double du = (double)(g.rp[u + 1] - g.rp[u]);
+            acc += log1p(du);
+            sd += du;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            acc += __shfl_xor(acc, o);
+            sd += __shfl_xor(sd, o);
+        }
+        if (lane == 0) {
+            const double dv = (double)(end - beg);
+            out[3 * v + 0] = (float)log1p(dv);
+            out[3 * v + 1] = (float)(dv > 0 ? acc / dv : 0.0);
+            out[3 * v + 2] = (float)log1p(sd);
+        }
+    }
+}
+
+__global__ void k_normalize(int32_t n, float *x, const float *norm)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3ll * n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(i % 3);
+        x[i] = (x[i] - norm[j]) / norm[3 + j];
+    }
+}
+
+// C[16x16] += A[16 x K] * B[K x 16] on the matrix cores; a(m, k), b(k, n)
+// fetch operands.  Lane l supplies A[l % 16][k0 + l / 16] and
+// B[k0 + l / 16][l % 16]; the result element (row, col) of accumulator i
+// is row = (l / 16) * 4 + i, col = l % 16.
+template <typename FA, typename FB>
+__device__ __forceinline__ floatx4 mfma_tile(floatx4 c, int K, FA a, FB b)
+{
+    const int lane = threadIdx.x & 63;
+    const int m = lane & 15, kk = lane >> 4;
+    for (int k0 = 0; k0 < K; k0 += 4) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a(m, k0 + kk), b(k0 + kk, m), c, 0, 0, 0);
+    return c;
+}
+
+// Forward (and, when train != 0, backward) over all rows.
+__global__ __launch_bounds__(256) void k_mlp(const float *P, const float *X, const float *Yt, int64_t rows,
+                                             float *Yout, float *partial, int train)
+{
+    __shared__ float sW1[192], sb1[64], sb2[64], sW3[64];
+    __shared__ float sW2[64 * LD];
+    __shared__ float sX[TR * 3];
+    __shared__ float sH1[TR * LD];
+    __shared__ float sH2[TR * LD];   // H2, then D1
+    __shared__ float sD2[TR * LD];
+    __shared__ float sdy[TR];
+    __shared__ float gW1[192], gb1[64], gb2[64], gW3[64];
+    __shared__ float sgb3, sloss;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int i = tid; i < 192; i += 256) { sW1[i] = P[OFF_W1 + i]; gW1[i] = 0.f; }
+    for (int i = tid; i < 64; i += 256) {
+        sb1[i] = P[OFF_B1 + i];
+        sb2[i] = P[OFF_B2 + i];
+        sW3[i] = P[OFF_W3 + i];
+        gb1[i] = gb2[i] = gW3[i] = 0.f;
+    }
+    for (int i = tid; i < 4096; i += 256) sW2[(i >> 6) * LD + (i & 63)] = P[OFF_W2 + i];
+    if (tid == 0) { sgb3 = 0.f; sloss = 0.f; }
+    const float b3 = P[OFF_B3];
+    floatx4 gacc[4];
+    for (int t = 0; t < 4; ++t) gacc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+    const float scale = 2.0f / (float)rows;
+
+    for (int64_t r0 = (int64_t)blockIdx.x * TR; r0 < rows; r0 += (int64_t)gridDim.x * TR) {
+        const int cnt = (int)min<int64_t>(TR, rows - r0);
+        for (int i = tid; i < TR * 3; i += 256) sX[i] = (i / 3 < cnt) ? X[r0 * 3 + i] : 0.f;
+        __syncthreads();
+        // hidden layer 1 (K = 3): thread -> row tid/4, 16 outputs
+        {
+            const int r = tid >> 2, o0 = (tid & 3) * 16;
+            const float x0 = sX[3 * r], x1 = sX[3 * r + 1], x2 = sX[3 * r + 2];
+            for (int o = o0; o < o0 + 16; ++o) {
+                float z = sb1[o];
+                z = fmaf(sW1[3 * o + 0], x0, z);
+                z = fmaf(sW1[3 * o + 1], x1, z);
+                z = fmaf(sW1[3 * o + 2], x2, z);
+                sH1[r * LD + o] = z > 0.f ? z : 0.f;
+            }
+        }
+        __syncthreads();
+        // hidden layer 2: Z2[r][o] = sum_k H1[r][k] W2[o][k]; wave w owns rows 16w..16w+15
+        for (int ct = 0; ct < 4; ++ct) {
+            floatx4 c = mfma_tile(floatx4{0.f, 0.f, 0.f, 0.f}, 64,
+                                  [&](int m, int k) { return sH1[(16 * w + m) * LD + k]; },
+                                  [&](int k, int nn) { return sW2[(16 * ct + nn) * LD + k]; });
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * w + (lane >> 4) * 4 + i, col = 16 * ct + (lane & 15);
+                const float z = c[i] + sb2[col];
+                sH2[row * LD + col] = z > 0.f ? z : 0.f;
+            }
+        }
+        __syncthreads();
+        // output layer and loss
+        if (tid < TR) {
+            float y = b3;
+            for (int k = 0; k < 64; ++k) y = fmaf(sW3[k], sH2[tid * LD + k], y);
+            if (tid < cnt) {
+                if (Yout) Yout[r0 + tid] = y;
+                if (train) {
+                    const float d = y - Yt[r0 + tid];
+                    atomicAdd(&sloss, d * d);
+                    sdy[tid] = scale * d;
+                }
+            } else {
+                sdy[tid] = 0.f;
+            }
+        }
+        if (!train) { __syncthreads(); continue; }
+        __syncthreads();
+        // D2 = dy W3 masked by H2 > 0; gW3, gb3
+        for (int i = tid; i < TR * 64; i += 256) {
+            const int r = i >> 6, o = i & 63;
+            const float h = sH2[r * LD + o];
+            sD2[r * LD + o] = h > 0.f ? sdy[r] * sW3[o] : 0.f;
+        }
+        if (tid < 64) {
+            float gw = 0.f, gb = 0.f;
+            for (int r = 0; r < TR; ++r) gw = fmaf(sdy[r], sH2[r * LD + tid], gw);
+            gW3[tid] += gw;
+            if (tid == 0) {
+                for (int r = 0; r < TR; ++r) gb += sdy[r];
+                sgb3 += gb;
+            }
+        }
+        __syncthreads();
+        // gW2[o][k] += sum_r D2[r][o] H1[r][k]  (wave w owns o in 16w..16w+15)
+        for (int kt = 0; kt < 4; ++kt)
+            gacc[kt] = mfma_tile(gacc[kt], TR,
+                                 [&](int m, int r) { return sD2[r * LD + 16 * w + m]; },
+                                 [&](int r, int nn) { return sH1[r * LD + 16 * kt + nn]; });
+        if (tid < 64) {
+            float gb = 0.f;
+            for (int r = 0; r < TR; ++r) gb += sD2[r * LD + tid];
+            gb2[tid] += gb;
+        }
+        // D1[r][k] = sum_o D2[r][o] W2[o][k], masked by H1 > 0 (into sH2)
+        for (int kt = 0; kt < 4; ++kt) {
+            floatx4 c = mfma_tile(floatx4{0.f, 0.f, 0.f, 0.f}, 64,
+                                  [&](int m, int o) { return sD2[(16 * w + m) * LD + o]; },
+                                  [&](int o, int nn) { return sW2[o * LD + 16 * kt + nn]; });
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * w + (lane >> 4) * 4 + i, col = 16 * kt + (lane & 15);
+                sH2[row * LD + col] = sH1[row * LD + col] > 0.f ? c[i] : 0.f;
+            }
+        }
+        __syncthreads();
+        // gW1[o][j] += sum_r D1[r][o] X[r][j]; gb1
+        if (tid < 64) {
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, gb = 0.f;
+            for (int r = 0; r < TR; ++r) {
+                const float d = sH2[r * LD + tid];
+                a0 = fmaf(d, sX[3 * r], a0);
+                a1 = fmaf(d, sX[3 * r + 1], a1);
+                a2 = fmaf(d, sX[3 * r + 2], a2);
+                gb += d;
+            }
+            gW1[3 * tid] += a0;
+            gW1[3 * tid + 1] += a1;
+            gW1[3 * tid + 2] += a2;
+            gb1[tid] += gb;
+        }
+        __syncthreads();
+    }
+    if (!train) return;
+    float *out = partial + (size_t)blockIdx.x * PSTRIDE;
+    for (int kt = 0; kt < 4; ++kt)
+        for (int i = 0; i < 4; ++i) {
+            const int o = 16 * w + (lane >> 4) * 4 + i, k = 16 * kt + (lane & 15);
+            out[OFF_W2 + o * 64 + k] = gacc[kt][i];
+        }
+    __syncthreads();
+    for (int i = tid; i < 192; i += 256) out[OFF_W1 + i] = gW1[i];
+    for (int i = tid; i < 64; i += 256) {
+        out[OFF_B1 + i] = gb1[i];
+        out[OFF_B2 + i] = gb2[i];
+        out[OFF_W3 + i] = gW3[i];
+    }
+    if (tid == 0) {
+        out[OFF_B3] = sgb3;
+        out[NP] = sloss;
+    }
+}
+
+__global__ void k_reduce_partials(const float *partial, int nb, float *grad, float *loss, float inv_rows)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > NP) return;
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += partial[(size_t)b * PSTRIDE + i];
+    if (i < NP) grad[i] = s;
+    else *loss = s * inv_rows;
+}
+
+__global__ void k_adam(float *p, const float *g, float *m, float *v, int count, float lr, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_prior(int32_t n, const float *y, double inv_omega, double *prior)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const double b = exp((double)y[v]) - inv_omega;
+        prior[v] = b > 0.0 ? b : (b == b ? 0.0 : b);
+    }
+}
+
+int blocks_for_rows(int64_t rows)
+{
+    int64_t b = (rows + TR - 1) / TR;
+    return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 1024);
+}
+
+}  // namespace
+
+size_t mlp_scratch_floats(int64_t rows) { return (size_t)blocks_for_rows(rows) * PSTRIDE; }
+
+hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st)
+{
+    const int64_t waves = std::min<int64_t>(g.n, 1 << 16);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(int32_t n, float *x, const float *norm, hipStream_t st)
+{
+    const int64_t blocks = std::min<int64_t>((3ll * n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_normalize, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, n, x, norm);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float *params, const float *x, int64_t rows, float *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp, dim3(blocks_for_rows(rows)), dim3(256), 0, st, params, x, (const float *)nullptr,
+                       rows, y, (float *)nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_loss_grad(const float *params, const float *x, const float *y, int64_t rows, float *grad,
+                                float *loss, float *scratch, hipStream_t st)
+{
+    const int nb = blocks_for_rows(rows);
+    hipLaunchKernelGGL(k_mlp, dim3(nb), dim3(256), 0, st, params, x, y, rows, (float *)nullptr, scratch, 1);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((NP + 1 + 255) / 256), dim3(256), 0, st, scratch, nb, grad, loss,
+                       1.0f / (float)rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *params, const float *grad, float *m, float *v, int count, int step, float lr,
+                       hipStream_t st)
+{
+    const float c1 = 1.f - powf(0.9f, (float)step), c2 = 1.f - powf(0.999f, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((count + 255) / 256), dim3(256), 0, st, params, grad, m, v, count, lr, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_prior_from_mlp(int32_t n, const float *yhat, double omega, double *prior, hipStream_t st)
+{
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_prior, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, n, yhat,
+                       1.0 / omega, prior);
+    return hipGetLastError();
+}
+
+}  // namespace kad

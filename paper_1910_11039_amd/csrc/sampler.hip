@@ -1,0 +1,857 @@
+// KADABRA sampler kernel for gfx950: one sample per workgroup at a time,
+// persistent workgroups pulling sample indices from a device counter.
+//
+// One sample (Sec. III-A): draw an ordered pair s != t, run a bidirectional
+// BFS that counts shortest paths, choose one shortest s-t path uniformly,
+// add one to the counter of each interior vertex.
+//
+// Search rules (readings; the paper only names a bidirectional BFS):
+//  * grow the side whose newest layer has the smaller degree sum (ties: s);
+//    each step adds the whole next layer as a set;
+//  * the search meets when the new layer of side X contains vertices already
+//    reached by side Y; those form the meet set M, all in Y's newest layer;
+//  * sigma of a layer is the sum of sigma over its predecessors; it is taken
+//    for every layer that gets expanded (while expanding it) and for M;
+//  * integer mode: uint64 sums with exact overflow detection; on overflow
+//    the whole sample is redone in FP mode; FP mode: FP64 sums in ascending
+//    CSR position, each layer rescaled by 2^-400 when its maximum exceeds
+//    2^400;
+//  * the meet vertex is chosen in ascending id with weight sigma_X * sigma_Y,
+//    predecessors in CSR order with weight sigma, walking to s first, then
+//    to t; each pick is the first candidate whose inclusive prefix sum
+//    exceeds the draw scaled to the total (one draw per pick).
+//
+// Data layout (HBM): per slot, Rec[n] (16 B: stamp, state, sigma), a
+// frontier queue int32[n] (side s grows from the front, side t from the
+// back; the two sides never share a vertex outside M) and a meet list
+// int32[n].  Records carry the slot's sample stamp, so nothing is cleared
+// between samples.
+//
+// Expansion (integer mode) is edge-parallel and load-balanced: a chunk of
+// up to BS frontier vertices is staged in LDS with the exclusive scan of
+// their degrees, every lane takes one adjacency entry, finds its owner by
+// binary search in LDS, and sigma contributions go to per-owner LDS
+// accumulators.  New frontier entries are compacted with a wave ballot and
+// mbcnt prefix, one LDS atomic per wave.  FP mode is vertex-parallel so that
+// every sum runs in CSR order in one lane.
+#include "kad_internal.h"
+#include "philox.h"
+
+namespace kad {
+namespace {
+
+constexpr int MCAP = 1024;                 // meet sets up to this size are ranked in LDS
+constexpr double BIG = 0x1p400;
+constexpr double SHRINK = 0x1p-400;
+constexpr uint32_t X_SHIFT = 31;
+
+__device__ __forceinline__ uint64_t ld_key(Rec *r)
+{
+    return __hip_atomic_load(reinterpret_cast<uint64_t *>(r), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ bool cas_key(Rec *r, uint64_t expect, uint64_t desired)
+{
+    return __hip_atomic_compare_exchange_strong(reinterpret_cast<uint64_t *>(r), &expect, desired,
+                                                __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t or_state(Rec *r, uint32_t bits)
+{
+    return __hip_atomic_fetch_or(&r->state, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void st_key(Rec *r, uint64_t v)
+{
+    __hip_atomic_store(reinterpret_cast<uint64_t *>(r), v, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint64_t ld_sig(Rec *r)
+{
+    return __hip_atomic_load(&r->sig, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void st_sig(Rec *r, uint64_t v)
+{
+    __hip_atomic_store(&r->sig, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ double as_f64(uint64_t b) { return __builtin_bit_cast(double, b); }
+__device__ __forceinline__ uint64_t as_u64(double d) { return __builtin_bit_cast(uint64_t, d); }
+__device__ __forceinline__ double unit53(uint64_t u) { return (double)(u >> 11) * 0x1p-53; }
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t y = __shfl_up(v, o);
+        if (lane >= o) v += y;
+    }
+    return v;
+}
+
+template <int BS>
+struct Smem {
+    union {
+        struct {
+            int32_t u[BS];
+            int64_t rs[BS];
+            int64_t off[BS];
+            unsigned long long acc[BS];
+            unsigned long long acc2[BS];
+        } e;
+        struct {
+            int32_t id[MCAP];
+            unsigned long long w[MCAP];
+        } m;
+    };
+    int64_t wsum[BS / 64];
+    unsigned long long nextdeg;
+    unsigned long long sigst;
+    unsigned long long fmax_bits;
+    unsigned long long sid;
+    int64_t sdeg[2];
+    int32_t lo[2], hi[2], dep[2];
+    int32_t tail, mcount, ovf, err, w, wmin;
+    uint32_t stamp;
+    int32_t s, t;
+};
+
+// Exclusive block scan of int64 values (all threads must call).
+template <int BS>
+__device__ int64_t block_excl_scan(Smem<BS> &sm, int64_t v, int64_t &total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sm.wsum[wid] = x;
+    __syncthreads();
+    int64_t pre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < BS / 64; ++i) {
+        int64_t s = sm.wsum[i];
+        pre += (i < wid) ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + x - v;
+}
+
+struct Ctx {
+    DevGraph g;
+    Rec *R;
+    int32_t *Q;
+    int32_t *MB;
+    uint32_t cur;
+    int fp;
+};
+
+__device__ __forceinline__ int64_t qpos(int32_t n, int side, int64_t p)
+{
+    return side ? (int64_t)n - 1 - p : p;
+}
+
+// Thread-local statistics, flushed once per workgroup.
+struct LocalStats {
+    unsigned long long pred, visited;
+};
+
+// One expansion of side X from its layer k (frontier = queue positions
+// [lo, hi)).  Discovered vertices are appended from position hi on; meet
+// vertices go to the meet list.  Computes sigma for layer k (k >= 1).
+template <int BS>
+__device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t lo, int32_t hi,
+                           LocalStats &ls)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int32_t n = c.g.n;
+    const uint32_t xbit = (uint32_t)X << X_SHIFT;
+    const uint64_t newkey = ((uint64_t)c.cur << 32) | xbit | (uint32_t)(k + 1);
+    unsigned long long nd = 0;
+    for (int32_t base = lo; base < hi; base += BS) {
+        const int cnt = min(BS, hi - base);
+        int32_t u = -1;
+        int64_t rs = 0, d = 0;
+        if (tid < cnt) {
+            u = c.Q[qpos(n, X, base + tid)];
+            rs = c.g.rp[u];
+            d = c.g.rp[u + 1] - rs;
+        }
+        sm.e.u[tid] = u;
+        sm.e.rs[tid] = rs;
+        sm.e.acc[tid] = 0;
+        int64_t total;
+        const int64_t off = block_excl_scan<BS>(sm, d, total);
+        sm.e.off[tid] = off;
+        __syncthreads();
+        for (int64_t e0 = tid & ~63; e0 < total; e0 += BS) {
+            const int64_t e = e0 + lane;
+            bool disc = false, newmeet = false;
+            int32_t w = -1;
+            if (e < total) {
+                int a = 0, b = cnt - 1;
+                while (a < b) {
+                    int mid = (a + b + 1) >> 1;
+                    if (sm.e.off[mid] <= e) a = mid; else b = mid - 1;
+                }
+                w = c.g.ci[sm.e.rs[a] + (e - sm.e.off[a])];
+                Rec *r = c.R + w;
+                const uint64_t kk = ld_key(r);
+                if ((uint32_t)(kk >> 32) == c.cur) {
+                    const uint32_t st = (uint32_t)kk;
+                    if ((st & SIDE_BIT) == xbit) {
+                        if (k >= 1 && (st & DEPTH_MASK) == (uint32_t)(k - 1)) {
+                            const uint64_t v = ld_sig(r);
+                            const unsigned long long old = atomicAdd(&sm.e.acc[a], (unsigned long long)v);
+                            if (old + v < old) sm.ovf = 1;
+                            ls.pred += 1;
+                        }
+                    } else {
+                        const uint32_t old = or_state(r, MEET_BIT);
+                        newmeet = !(old & MEET_BIT);
+                    }
+                } else {
+                    disc = cas_key(r, kk, newkey);
+                }
+            }
+            const uint64_t dm = __ballot(disc);
+            if (dm) {
+                const int leader = __ffsll((unsigned long long)dm) - 1;
+                int pos = 0;
+                if (lane == leader) pos = atomicAdd(&sm.tail, __popcll(dm));
+                pos = __shfl(pos, leader);
+                if (disc) {
+                    c.Q[qpos(n, X, pos + (int)mbcnt(dm))] = w;
+                    nd += (unsigned long long)(c.g.rp[w + 1] - c.g.rp[w]);
+                    ls.visited += 1;
+                }
+            }
+            const uint64_t mm = __ballot(newmeet);
+            if (mm) {
+                const int leader = __ffsll((unsigned long long)mm) - 1;
+                int pos = 0;
+                if (lane == leader) pos = atomicAdd(&sm.mcount, __popcll(mm));
+                pos = __shfl(pos, leader);
+                if (newmeet) c.MB[pos + (int)mbcnt(mm)] = w;
+            }
+        }
+        __syncthreads();
+        if (k >= 1 && tid < cnt) st_sig(c.R + sm.e.u[tid], sm.e.acc[tid]);
+        __syncthreads();
+    }
+    if (nd) atomicAdd(&sm.nextdeg, nd);
+}
+
+template <int BS>
+__device__ void expand_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t lo, int32_t hi,
+                          LocalStats &ls)
+{
+    const int tid = threadIdx.x;
+    const int32_t n = c.g.n;
+    const uint32_t xbit = (uint32_t)X << X_SHIFT;
+    const uint64_t newkey = ((uint64_t)c.cur << 32) | xbit | (uint32_t)(k + 1);
+    unsigned long long nd = 0;
+    double mx = 0.0;
+    for (int32_t p = lo + tid; p < hi; p += BS) {
+        const int32_t u = c.Q[qpos(n, X, p)];
+        double acc = 0.0;
+        const int64_t beg = c.g.rp[u], end = c.g.rp[u + 1];
+        for (int64_t e = beg; e < end; ++e) {
+            const int32_t w = c.g.ci[e];
+            Rec *r = c.R + w;
+            const uint64_t kk = ld_key(r);
+            if ((uint32_t)(kk >> 32) == c.cur) {
+                const uint32_t st = (uint32_t)kk;
+                if ((st & SIDE_BIT) == xbit) {
+                    if (k >= 1 && (st & DEPTH_MASK) == (uint32_t)(k - 1)) {
+                        acc = acc + as_f64(ld_sig(r));
+                        ls.pred += 1;
+                    }
+                } else {
+                    const uint32_t old = or_state(r, MEET_BIT);
+                    if (!(old & MEET_BIT)) c.MB[atomicAdd(&sm.mcount, 1)] = w;
+                }
+            } else if (cas_key(r, kk, newkey)) {
+                c.Q[qpos(n, X, atomicAdd(&sm.tail, 1))] = w;
+                nd += (unsigned long long)(c.g.rp[w + 1] - c.g.rp[w]);
+                ls.visited += 1;
+            }
+        }
+        if (k >= 1) {
+            st_sig(c.R + u, as_u64(acc));
+            mx = acc > mx ? acc : mx;
+        }
+    }
+    if (nd) atomicAdd(&sm.nextdeg, nd);
+    if (mx > 0.0) atomicMax(&sm.fmax_bits, (unsigned long long)as_u64(mx));
+}
+
+// sigma_X(w) * sigma_Y(w) for every meet vertex, stored in w's record.
+template <int BS>
+__device__ void meet_weights_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t kY, int32_t m)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const uint32_t xbit = (uint32_t)X << X_SHIFT, ybit = (uint32_t)(1 - X) << X_SHIFT;
+    for (int32_t base = 0; base < m; base += BS) {
+        const int cnt = min(BS, m - base);
+        int32_t w = -1;
+        int64_t rs = 0, d = 0;
+        if (tid < cnt) {
+            w = c.MB[base + tid];
+            rs = c.g.rp[w];
+            d = c.g.rp[w + 1] - rs;
+        }
+        sm.e.u[tid] = w;
+        sm.e.rs[tid] = rs;
+        sm.e.acc[tid] = 0;
+        sm.e.acc2[tid] = 0;
+        int64_t total;
+        const int64_t off = block_excl_scan<BS>(sm, d, total);
+        sm.e.off[tid] = off;
+        __syncthreads();
+        for (int64_t e0 = tid & ~63; e0 < total; e0 += BS) {
+            const int64_t e = e0 + lane;
+            if (e < total) {
+                int a = 0, b = cnt - 1;
+                while (a < b) {
+                    int mid = (a + b + 1) >> 1;
+                    if (sm.e.off[mid] <= e) a = mid; else b = mid - 1;
+                }
+                const int32_t x = c.g.ci[sm.e.rs[a] + (e - sm.e.off[a])];
+                Rec *r = c.R + x;
+                const uint64_t kk = ld_key(r);
+                if ((uint32_t)(kk >> 32) == c.cur) {
+                    const uint32_t st = (uint32_t)kk;
+                    const uint32_t dep = st & DEPTH_MASK;
+                    unsigned long long *acc = nullptr;
+                    if ((st & SIDE_BIT) == xbit && dep == (uint32_t)kX) acc = &sm.e.acc[a];
+                    else if ((st & SIDE_BIT) == ybit && kY >= 1 && dep == (uint32_t)(kY - 1)) acc = &sm.e.acc2[a];
+                    if (acc) {
+                        const uint64_t v = ld_sig(r);
+                        const unsigned long long old = atomicAdd(acc, (unsigned long long)v);
+                        if (old + v < old) sm.ovf = 1;
+                    }
+                }
+            }
+        }
+        (void)lane;
+        __syncthreads();
+        if (tid < cnt) {
+            const uint64_t ax = sm.e.acc[tid];
+            const uint64_t ay = (kY == 0) ? 1ull : (uint64_t)sm.e.acc2[tid];
+            if (__umul64hi(ax, ay) != 0) sm.ovf = 1;
+            const uint64_t a = ax * ay;
+            st_sig(c.R + w, a);
+            const unsigned long long old = atomicAdd(&sm.sigst, (unsigned long long)a);
+            if (old + a < old) sm.ovf = 1;
+        }
+        __syncthreads();
+    }
+}
+
+template <int BS>
+__device__ void meet_weights_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t kY, int32_t m)
+{
+    const uint32_t xstate = ((uint32_t)X << X_SHIFT) | (uint32_t)kX;
+    const uint32_t ystate = ((uint32_t)(1 - X) << X_SHIFT) | (uint32_t)(kY - 1);
+    for (int32_t i = threadIdx.x; i < m; i += BS) {
+        const int32_t w = c.MB[i];
+        double ax = 0.0, ay = 0.0;
+        for (int64_t e = c.g.rp[w]; e < c.g.rp[w + 1]; ++e) {
+            const int32_t x = c.g.ci[e];
+            Rec *r = c.R + x;
+            const uint64_t kk = ld_key(r);
+            if ((uint32_t)(kk >> 32) != c.cur) continue;
+            const uint32_t st = (uint32_t)kk & ~MEET_BIT;
+            if (st == xstate) ax = ax + as_f64(ld_sig(r));
+            else if (kY >= 1 && st == ystate) ay = ay + as_f64(ld_sig(r));
+        }
+        if (kY == 0) ay = 1.0;
+        st_sig(c.R + w, as_u64(ax * ay));
+    }
+    (void)sm;
+}
+
+// Smallest meet-list id above `last` (all threads call; uniform result).
+template <int BS>
+__device__ int32_t next_min(Smem<BS> &sm, const Ctx &c, int32_t m, int32_t last)
+{
+    if (threadIdx.x == 0) sm.wmin = 0x7fffffff;
+    __syncthreads();
+    int32_t best = 0x7fffffff;
+    for (int32_t i = threadIdx.x; i < m; i += BS) {
+        const int32_t id = c.MB[i];
+        if (id > last && id < best) best = id;
+    }
+    if (best != 0x7fffffff) atomicMin(&sm.wmin, best);
+    __syncthreads();
+    const int32_t r = sm.wmin;
+    __syncthreads();
+    return r;
+}
+
+// Chooses the meet vertex; result in sm.w (all threads call).
+template <int BS>
+__device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2)
+{
+    constexpr int PER = MCAP / BS;
+    const int tid = threadIdx.x;
+    if (m <= MCAP) {
+        for (int32_t i = tid; i < m; i += BS) {
+            const int32_t w = c.MB[i];
+            sm.m.id[i] = w;
+            sm.m.w[i] = ld_sig(c.R + w);
+        }
+        __syncthreads();
+        int32_t myid[PER];
+        uint64_t myw[PER];
+        int32_t myrank[PER];
+        uint64_t mypre[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int32_t i = tid + j * BS;
+            myid[j] = -1;
+            myw[j] = 0;
+            myrank[j] = 0;
+            mypre[j] = 0;
+            if (i < m) {
+                myid[j] = sm.m.id[i];
+                myw[j] = sm.m.w[i];
+            }
+        }
+        // rank (and, in integer mode, exclusive prefix) in ascending id
+        for (int32_t jj = 0; jj < m; ++jj) {
+            const int32_t idj = sm.m.id[jj];
+            const uint64_t wj = sm.m.w[jj];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                if (myid[j] >= 0 && idj < myid[j]) {
+                    myrank[j] += 1;
+                    mypre[j] += wj;
+                }
+            }
+        }
+        if (!c.fp) {
+            const uint64_t r = __umul64hi(u2, (uint64_t)sm.sigst);
+#pragma unroll
+            for (int j = 0; j < PER; ++j)
+                if (myid[j] >= 0 && mypre[j] <= r && r - mypre[j] < myw[j]) sm.w = myid[j];
+            __syncthreads();
+            return;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            if (myid[j] >= 0) {
+                sm.m.id[myrank[j]] = myid[j];
+                sm.m.w[myrank[j]] = myw[j];
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double tot = 0.0;
+            for (int32_t i = 0; i < m; ++i) tot = tot + as_f64(sm.m.w[i]);
+            const double r = unit53(u2) * tot;
+            double pre = 0.0;
+            int32_t pick = -1;
+            for (int32_t i = 0; i < m; ++i) {
+                const double a = as_f64(sm.m.w[i]);
+                pre = pre + a;
+                if (a != 0.0) pick = sm.m.id[i];
+                if (pre > r) { pick = sm.m.id[i]; break; }
+            }
+            sm.w = pick;
+        }
+        __syncthreads();
+        return;
+    }
+    // Large meet sets: ranks against the whole list in global memory.
+    if (!c.fp) {
+        const uint64_t r = __umul64hi(u2, (uint64_t)sm.sigst);
+        for (int32_t i = tid; i < m; i += BS) {
+            const int32_t id = c.MB[i];
+            uint64_t pre = 0;
+            for (int32_t jj = 0; jj < m; ++jj) {
+                const int32_t idj = c.MB[jj];
+                if (idj < id) pre += ld_sig(c.R + idj);
+            }
+            const uint64_t wt = ld_sig(c.R + id);
+            if (pre <= r && r - pre < wt) sm.w = id;
+        }
+        __syncthreads();
+        return;
+    }
+    // FP mode, large meet set: visit the list in ascending id by repeated
+    // minimum search; first pass sums the weights, second finds the pick.
+    double tot = 0.0;
+    for (int32_t step = 0, last = -1; step < m; ++step) {
+        const int32_t id = next_min<BS>(sm, c, m, last);
+        tot = tot + as_f64(ld_sig(c.R + id));
+        last = id;
+    }
+    const double r = unit53(u2) * tot;
+    double pre = 0.0;
+    int32_t pick = -1;
+    for (int32_t step = 0, last = -1; step < m; ++step) {
+        const int32_t id = next_min<BS>(sm, c, m, last);
+        const double a = as_f64(ld_sig(c.R + id));
+        pre = pre + a;
+        if (a != 0.0) pick = id;
+        if (pre > r) { pick = id; break; }
+        last = id;
+    }
+    if (tid == 0) sm.w = pick;
+    __syncthreads();
+}
+
+// One predecessor pick walking back on `side` from v at depth l (>= 2).
+__device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint64_t u, int lane)
+{
+    const uint32_t want = ((uint32_t)side << X_SHIFT) | (uint32_t)(l - 1);
+    const int64_t beg = c.g.rp[v], end = c.g.rp[v + 1];
+    if (!c.fp) {
+        uint64_t tot = 0;
+        for (int64_t c0 = beg; c0 < end; c0 += 64) {
+            const int64_t e = c0 + lane;
+            uint64_t wt = 0;
+            if (e < end) {
+                Rec *r = c.R + c.g.ci[e];
+                const uint64_t kk = ld_key(r);
+                if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) wt = ld_sig(r);
+            }
+            tot += wave_sum_u64(wt);
+        }
+        const uint64_t r = __umul64hi(u, tot);
+        uint64_t pre = 0;
+        for (int64_t c0 = beg; c0 < end; c0 += 64) {
+            const int64_t e = c0 + lane;
+            uint64_t wt = 0;
+            int32_t x = -1;
+            if (e < end) {
+                x = c.g.ci[e];
+                Rec *rc = c.R + x;
+                const uint64_t kk = ld_key(rc);
+                if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) wt = ld_sig(rc);
+            }
+            const uint64_t incl = wave_incl_scan_u64(wt, lane);
+            const uint64_t hit = __ballot(wt != 0 && pre + incl > r);
+            if (hit) return __shfl(x, __ffsll((unsigned long long)hit) - 1);
+            pre += __shfl(incl, 63);
+        }
+        return -1;
+    }
+    double tot = 0.0;
+    for (int64_t c0 = beg; c0 < end; c0 += 64) {
+        const int64_t e = c0 + lane;
+        double wt = 0.0;
+        bool cand = false;
+        if (e < end) {
+            Rec *r = c.R + c.g.ci[e];
+            const uint64_t kk = ld_key(r);
+            if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) {
+                cand = true;
+                wt = as_f64(ld_sig(r));
+            }
+        }
+        uint64_t mask = __ballot(cand);
+        while (mask) {
+            const int j = __ffsll((unsigned long long)mask) - 1;
+            tot = tot + __shfl(wt, j);
+            mask &= mask - 1;
+        }
+    }
+    const double r = unit53(u) * tot;
+    double pre = 0.0;
+    int32_t last_nz = -1;
+    for (int64_t c0 = beg; c0 < end; c0 += 64) {
+        const int64_t e = c0 + lane;
+        double wt = 0.0;
+        bool cand = false;
+        int32_t x = -1;
+        if (e < end) {
+            x = c.g.ci[e];
+            Rec *rc = c.R + x;
+            const uint64_t kk = ld_key(rc);
+            if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) {
+                cand = true;
+                wt = as_f64(ld_sig(rc));
+            }
+        }
+        uint64_t mask = __ballot(cand);
+        while (mask) {
+            const int j = __ffsll((unsigned long long)mask) - 1;
+            const double a = __shfl(wt, j);
+            const int32_t xj = __shfl(x, j);
+            pre = pre + a;
+            if (a != 0.0) last_nz = xj;
+            if (pre > r) return xj;
+            mask &= mask - 1;
+        }
+    }
+    return last_nz;
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
+{
+    __shared__ Smem<BS> sm;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (a.stop_flag && __hip_atomic_load(a.stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    uint64_t first = a.first, count = a.count;
+    uint32_t *sf = a.sf[0];
+    if (a.dev_range) {
+        first = a.dev_range[0];
+        count = a.dev_range[1];
+        sf = a.sf[a.dev_range[2] & 1];
+    }
+    const int32_t n = a.g.n;
+    const size_t slot = blockIdx.x;
+    Ctx c;
+    c.g = a.g;
+    c.R = a.recs + slot * (size_t)n;
+    c.Q = a.queues + slot * (size_t)n;
+    c.MB = a.mbufs + slot * (size_t)n;
+    LocalStats ls{0, 0};
+    unsigned long long st_edges = 0, st_exp = 0, st_path = 0, st_fp = 0, st_samples = 0, st_all = 0;
+
+    for (;;) {
+        if (tid == 0) sm.sid = atomicAdd(a.work_ctr, 1ull);
+        __syncthreads();
+        const unsigned long long sid = sm.sid;
+        if (sid >= count) break;
+        const uint64_t idx = first + sid;
+        int fp = a.sigma_fp;
+        if (tid == 0) {
+            SampleDraws dr;
+            dr.init(a.seed, a.stream, idx);
+            const uint64_t u0 = dr.get(0), u1 = dr.get(1);
+            const int32_t s = (int32_t)__umul64hi(u0, (uint64_t)n);
+            int32_t t = (int32_t)__umul64hi(u1, (uint64_t)(n - 1));
+            if (t >= s) t += 1;
+            sm.s = s;
+            sm.t = t;
+        }
+        int X = 0;
+        int32_t kX = 0, kY = 0, m = 0;
+        unsigned long long edges = 0;
+        int steps = 0;
+        bool failed = false;
+        for (;;) {  // attempt (integer mode, then FP mode if it overflowed)
+            if (tid == 0) {
+                const uint32_t cur = a.stamps[slot] + 1;
+                a.stamps[slot] = cur;
+                sm.stamp = cur;
+                const int32_t s = sm.s, t = sm.t;
+                st_key(c.R + s, ((uint64_t)cur << 32) | 0u);
+                st_sig(c.R + s, fp ? as_u64(1.0) : 1ull);
+                st_key(c.R + t, ((uint64_t)cur << 32) | SIDE_BIT);
+                st_sig(c.R + t, fp ? as_u64(1.0) : 1ull);
+                c.Q[0] = s;
+                c.Q[n - 1] = t;
+                sm.lo[0] = sm.lo[1] = 0;
+                sm.hi[0] = sm.hi[1] = 1;
+                sm.dep[0] = sm.dep[1] = 0;
+                sm.sdeg[0] = a.g.rp[s + 1] - a.g.rp[s];
+                sm.sdeg[1] = a.g.rp[t + 1] - a.g.rp[t];
+                sm.ovf = 0;
+                sm.err = 0;
+                sm.sigst = 0;
+            }
+            __syncthreads();
+            c.cur = sm.stamp;
+            c.fp = fp;
+            edges = 0;
+            steps = 0;
+            for (;;) {
+                X = (sm.sdeg[0] <= sm.sdeg[1]) ? 0 : 1;
+                const int32_t k = sm.dep[X], lo = sm.lo[X], hi = sm.hi[X];
+                edges += (unsigned long long)sm.sdeg[X];
+                st_exp += (unsigned long long)(hi - lo);
+                steps += 1;
+                __syncthreads();
+                if (tid == 0) {
+                    sm.tail = hi;
+                    sm.mcount = 0;
+                    sm.nextdeg = 0;
+                    sm.fmax_bits = 0;
+                }
+                __syncthreads();
+                if (!fp) expand_int<BS>(sm, c, X, k, lo, hi, ls);
+                else expand_fp<BS>(sm, c, X, k, lo, hi, ls);
+                __syncthreads();
+                if (fp && k >= 1 && as_f64(sm.fmax_bits) > BIG) {
+                    for (int32_t p = lo + tid; p < hi; p += BS) {
+                        Rec *r = c.R + c.Q[qpos(n, X, p)];
+                        st_sig(r, as_u64(as_f64(ld_sig(r)) * SHRINK));
+                    }
+                    __syncthreads();
+                }
+                if (!fp && sm.ovf) break;
+                if (sm.mcount > 0) break;
+                if (sm.tail == hi) { failed = true; break; }
+                __syncthreads();
+                if (tid == 0) {
+                    sm.lo[X] = hi;
+                    sm.hi[X] = sm.tail;
+                    sm.dep[X] = k + 1;
+                    sm.sdeg[X] = (int64_t)sm.nextdeg;
+                }
+                __syncthreads();
+            }
+            st_all += edges;
+            if (failed) break;
+            if (!fp && sm.ovf) { __syncthreads(); fp = 1; continue; }
+            kX = sm.dep[X];
+            kY = sm.dep[1 - X];
+            m = sm.mcount;
+            __syncthreads();
+            if (!fp) meet_weights_int<BS>(sm, c, X, kX, kY, m);
+            else meet_weights_fp<BS>(sm, c, X, kX, kY, m);
+            __syncthreads();
+            if (!fp && sm.ovf) { __syncthreads(); fp = 1; continue; }
+            break;
+        }
+        if (failed) {
+            if (tid == 0) a.stats->error = 1;
+            __syncthreads();
+            continue;
+        }
+        // meet vertex
+        if (tid == 0) sm.w = -1;
+        __syncthreads();
+        {
+            SampleDraws dr;
+            dr.init(a.seed, a.stream, idx);
+            const uint64_t u2 = dr.get(2);
+            choose_meet<BS>(sm, c, m, u2);
+        }
+        // walk back and count (wave 0)
+        const int32_t d = kX + 1 + kY;
+        if (sm.w < 0) {   // no meet vertex chosen: report instead of walking
+            if (tid == 0) a.stats->error = 3;
+            __syncthreads();
+            continue;
+        }
+        if (wid == 0) {
+            const int32_t s = sm.s, t = sm.t, w = sm.w;
+            int32_t dep[2];
+            dep[X] = kX + 1;
+            dep[1 - X] = kY;
+            int32_t *prow = nullptr;
+            if (a.paths) {
+                if (d + 1 <= a.max_len) prow = a.paths + (size_t)sid * (size_t)a.max_len;
+                else if (lane == 0) a.stats->error = 2;
+            }
+            if (prow && lane == 0) {
+                prow[0] = s;
+                prow[d] = t;
+                prow[dep[0]] = w;
+            }
+            unsigned long long cnt = 0;
+            if (w != s && w != t) {
+                if (lane == 0) atomicAdd(sf + w, 1u);
+                cnt += 1;
+            }
+            SampleDraws dr;
+            dr.init(a.seed, a.stream, idx);
+            uint64_t j = 3;
+            for (int side = 0; side < 2; ++side) {
+                int32_t v = w;
+                for (int32_t l = dep[side]; l >= 2; --l) {
+                    const uint64_t u = dr.get(j++);
+                    const int32_t p = pick_pred(c, side, v, l, u, lane);
+                    if (p < 0) {   // no predecessor found: report, stop this walk
+                        if (lane == 0) a.stats->error = 3;
+                        break;
+                    }
+                    if (lane == 0) {
+                        atomicAdd(sf + p, 1u);
+                        if (prow) prow[side == 0 ? (l - 1) : (d - (l - 1))] = p;
+                    }
+                    cnt += 1;
+                    v = p;
+                }
+            }
+            if (lane == 0 && a.info) {
+                int64_t *inf = a.info + (size_t)sid * 8;
+                inf[0] = s;
+                inf[1] = t;
+                inf[2] = d;
+                inf[3] = w;
+                inf[4] = fp;
+                inf[5] = m;
+                inf[6] = steps;
+                inf[7] = (int64_t)edges;
+            }
+            st_path += cnt;
+        }
+        st_edges += edges;
+        st_fp += fp ? 1 : 0;
+        st_samples += 1;
+        __syncthreads();
+    }
+    // flush statistics
+    unsigned long long pred = ls.pred, vis = ls.visited;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        pred += __shfl_xor(pred, o);
+        vis += __shfl_xor(vis, o);
+    }
+    if (lane == 0) {
+        if (pred) atomicAdd(&a.stats->pred_edges, pred);
+        if (vis) atomicAdd(&a.stats->visited, vis);
+    }
+    if (tid == 0) {
+        atomicAdd(&a.stats->edges, st_edges);
+        atomicAdd(&a.stats->expanded, st_exp);
+        atomicAdd(&a.stats->path_vertices, st_path);
+        atomicAdd(&a.stats->fp_samples, st_fp);
+        atomicAdd(&a.stats->samples, st_samples);
+        atomicAdd(&a.stats->edges_all, st_all);
+    }
+}
+
+}  // namespace
+
+int sampler_max_block() { return 512; }
+
+int sampler_blocks_per_cu(int block)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (block) {
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<64>, 64, 0); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<128>, 128, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<256>, 256, 0); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<512>, 512, 0); break;
+    default: break;
+    }
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+hipError_t launch_sampler(const SampleLaunch &a, int slots, int block, hipStream_t st)
+{
+    switch (block) {
+    case 64: hipLaunchKernelGGL(k_sample<64>, dim3(slots), dim3(64), 0, st, a); break;
+    case 128: hipLaunchKernelGGL(k_sample<128>, dim3(slots), dim3(128), 0, st, a); break;
+    case 256: hipLaunchKernelGGL(k_sample<256>, dim3(slots), dim3(256), 0, st, a); break;
+    case 512: hipLaunchKernelGGL(k_sample<512>, dim3(slots), dim3(512), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace kad
