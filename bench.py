@@ -1,0 +1,195 @@
+"""Benchmark: KADABRA adaptive sampling to its stop rule on one MI355X.
+
+One step = one whole run of the sampling path on a graph already resident
+in HBM: the vertex-diameter bracket and omega, the delta allocation
+(calibration samples for the plain arm; features + MLP inference for the
+learned arm), then epochs of sampling with the merge + FP64 stop check
+until the rule holds.  Default workload: R-MAT scale 20, edge factor 16
+(Graph500 parameters), largest component, eps = 0.005, delta = 0.1.
+
+Prints one JSON line.  value = samples per second over the timed steps
+(calibration plus adaptive samples, divided by the steps' wall time).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "samples/s + time-to-stop at eps=0.01,delta=0.1; learned vs plain delta alloc"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (graphgen workload, eps, description)
+    "rmat20": ("rmat20", 0.005, "R-MAT scale 20, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), "
+                                "symmetrised, deduplicated, largest component"),
+    "er2048": ("er2048", 0.01, "Erdos-Renyi G(2048, 16384), largest component"),
+    "grid2048": ("grid2048", 0.01, "2048x2048 grid, 5% edges removed, 0.1% shortcuts of offset <= 8, "
+                                   "largest component"),
+}
+
+
+def algorithmic_bytes(r) -> int:
+    """Bytes the sampling method must move for the work in one result
+    (per-unit figures: 16 B per expanded frontier vertex (two row offsets),
+    8 B per adjacency entry scanned (column index + the neighbour's visited
+    probe), 8 B per predecessor edge (its path count), 20 B per newly
+    visited vertex (record + frontier entry), 8 (d + 1) B of backtrack
+    reads and 4 (d - 1) B of counter updates per sample)."""
+    samples = r["samples"]
+    return int(16 * r["vertices_expanded"] + 8 * r["edges_scanned"] + 8 * r["pred_edges"]
+               + 20 * r["vertices_visited"] + 8 * (r["path_vertices"] + 2 * samples)
+               + 4 * r["path_vertices"])
+
+
+def cpu_baseline(g, seed: int, target_s: float = 12.0):
+    """The oracle, as it stands, on the host: first samples of the adaptive
+    stream, single thread, grown until about target_s seconds."""
+    from oracle import oracle as O
+    G = O.Graph(g)
+    n_s, t = 256, 0.0
+    while True:
+        t0 = time.perf_counter()
+        O.count(G, seed, 0, 0, n_s)
+        t = time.perf_counter() - t0
+        if t >= target_s or n_s >= 1 << 22:
+            break
+        n_s = int(n_s * min(8.0, max(1.5, 1.2 * target_s / max(t, 1e-3))))
+    return n_s, t
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--use-graphs", type=int, default=0)
+    ap.add_argument("--epoch-size", type=int, default=0)
+    ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain device copy of known size (counter calibration) and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "epoch aggregation is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_probe:
+        copy_probe()
+        return
+
+    import graphgen as gg
+    from paper_1910_11039_amd import kadabra as K
+
+    wname, eps, desc = WORKLOADS[args.workload]
+    g = gg.workload(wname)
+    ctx = K.Context(0)
+    G = K.Graph(ctx, g)
+    S = K.Sampler(G, seed=1, epsilon=eps, delta=0.1, timing=0 if args.use_graphs else 1,
+                  use_graphs=args.use_graphs, epoch_size=args.epoch_size, slots=args.slots,
+                  block_size=args.block)
+    print(f"# workload {wname}: n={g.n} m={g.m}; warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+
+    def step(seed):
+        S.reset(seed)
+        return S.run_to_stop().as_dict()
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    results = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        results.append(step(1 + i))
+        print(f"# step {i}: tau0={results[-1]['tau0']} tau={results[-1]['tau']} "
+              f"epochs={results[-1]['epochs']} total_ms={results[-1]['t_total_ms']:.1f}",
+              file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+
+    samples = sum(r["tau0"] + r["tau"] for r in results)
+    value = samples / wall
+    agg = {k: sum(r[k] for r in results) for k in
+           ("edges_scanned", "vertices_expanded", "vertices_visited", "pred_edges", "path_vertices",
+            "t_sample_kernel_ms", "sample_launches", "tau")}
+    agg["samples"] = agg["tau"]
+    roof = None
+    if agg["sample_launches"] > 0 and agg["t_sample_kernel_ms"] > 0:
+        per_launch_bytes = algorithmic_bytes(agg) / agg["sample_launches"]
+        per_launch_s = agg["t_sample_kernel_ms"] / 1e3 / agg["sample_launches"]
+        achieved = per_launch_bytes / per_launch_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": "k_sample (adaptive-phase launches)",
+                "launch_ms": round(per_launch_s * 1e3, 4),
+                "bytes_per_launch": int(per_launch_bytes)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_s, t = cpu_baseline(g, 1, args.cpu_seconds)
+        cpu = {"value": round(n_s / t, 2), "unit": "samples/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {n_s} samples of the adaptive stream (seed 1) on the same graph, "
+                         f"oracle sample loop, one host thread, {t:.1f} s"}
+
+    r0 = results[0]
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"{wname}: {desc}, n={g.n}, m={g.m}", "epsilon": eps, "delta": 0.1,
+                   "delta_alloc": "plain (calibration samples)", "epoch_size": r0["epoch_size"],
+                   "slots": r0["slots"], "omega": r0["omega"], "vd_bracket": [r0["vd_lo"], r0["vd_hi"]]},
+        "time_to_stop_ms": round(float(np.mean([r["t_total_ms"] for r in results])), 3),
+        "adaptive_samples_per_run": float(np.mean([r["tau"] for r in results])),
+        "calibration_samples_per_run": float(np.mean([r["tau0"] for r in results])),
+        "edges_scanned_per_s": round(agg["edges_scanned"] / wall, 1),
+        "phase_ms": {k: round(float(np.mean([r[k] for r in results])), 3)
+                     for k in ("t_omega_ms", "t_alloc_ms", "t_ads_ms")},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    S.close()
+    G.close()
+    ctx.close()
+
+
+def copy_probe(nbytes: int = 1 << 30, reps: int = 5):
+    """A plain device-to-device copy of known size (hipMemcpy's blit kernel)
+    to scale the HBM byte counters of the profiler."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    src, dst = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(src), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMalloc(ctypes.byref(dst), ctypes.c_size_t(nbytes)) == 0
+    hip.hipMemset(src, 1, ctypes.c_size_t(nbytes))
+    for _ in range(reps):
+        assert hip.hipMemcpy(dst, src, ctypes.c_size_t(nbytes), 3) == 0   # device to device
+    hip.hipDeviceSynchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+    hip.hipFree(src)
+    hip.hipFree(dst)
+
+
+if __name__ == "__main__":
+    main()

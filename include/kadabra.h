@@ -141,6 +141,12 @@ kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const kad_opts *o,
                             kad_sampler **out);
 void kad_sampler_free(kad_sampler *s);
 
+/* kad_sampler_reset: start a new run of the same sampler with a new seed:
+ * recomputes omega (phase 1, unless omega_override was given), clears the
+ * counters, the epochs and the statistics, and drops a PLAIN or LEARNED
+ * allocation (EXPLICIT arrays are kept).  No device memory is allocated. */
+kad_status kad_sampler_reset(kad_sampler *s, uint64_t seed);
+
 /* kad_set_delta: EXPLICIT allocation, h_delta_L/U float64[n] in (0, 1);
  * the sum over vertices of delta_L + delta_U must stay below delta / 2
  * (the other half of delta is spent on omega); checked, EINVAL otherwise.
@@ -188,8 +194,11 @@ kad_status kad_count_samples(kad_sampler *s, uint64_t stream, uint64_t first, ui
 
 /* kad_sample_paths: run samples [first, first+count) of `stream` and
  * return each path s..t: h_paths int32[count][max_len] (entries past d are
- * -1), h_info int64[count][8] = {s, t, d, w, fp_mode, meet_size, steps,
- * edges}.  A path longer than max_len-1 edges returns KAD_EOVERFLOW. */
+ * -1), h_info int64[count][14] = {s, t, d, w, fp_mode, meet_size, steps,
+ * edges, duration_ns, attempts, expand_ns, meet_weights_ns, choose_ns,
+ * walk_ns} (durations: wall time inside the sample's workgroup, in total
+ * and per phase of the last attempt; attempts: 2 when integer path counts
+ * overflowed and the sample was redone in FP64).  A path longer than max_len-1 edges returns KAD_EOVERFLOW. */
 kad_status kad_sample_paths(kad_sampler *s, uint64_t stream, uint64_t first, uint32_t count,
                             int32_t max_len, int32_t *h_paths, int64_t *h_info);
 

@@ -71,6 +71,8 @@ struct kad_sampler {
     double *LL, *LU, *lo_hi, *partials, *prior;
     Rec *recs;
     int32_t *queues, *mbufs;
+    unsigned long long *macc;
+    int32_t macc_cap;
     uint32_t *stamps;
     unsigned long long *work_ctr;
     SampleStats *stats;
@@ -225,7 +227,7 @@ extern "C" kad_status kad_vd_bracket(kad_ctx *ctx, const kad_graph *g, int64_t *
 static void free_sampler(kad_sampler *s)
 {
     if (s->have_graph) hipGraphExecDestroy(s->gexec);
-    void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->cprime, s->scratch_counts, s->LL, s->LU, s->lo_hi,
+    void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->cprime, s->scratch_counts, s->LL, s->LU, s->lo_hi, s->macc,
                     s->partials, s->prior, s->recs, s->queues, s->mbufs, s->stamps, s->work_ctr,
                     s->stats, s->es, s->hist};
     for (void *p : ptrs)
@@ -298,7 +300,8 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     s->cap = (unsigned long long)ceil(s->omega);
 
     // Slots: as many concurrent samples as fit the visited-state budget.
-    const size_t per_slot = (size_t)n * (sizeof(Rec) + 2 * sizeof(int32_t));
+    const size_t per_slot = (size_t)n * (sizeof(Rec) + 2 * sizeof(int32_t)) +
+                            16ull * (size_t)std::min<int64_t>(n, 1 << 16);
     size_t free_b = 0, total_b = 0;
     HIPCHK(hipMemGetInfo(&free_b, &total_b));
     size_t budget = o->visited_budget_bytes ? (size_t)o->visited_budget_bytes : free_b / 2;
@@ -314,6 +317,7 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     if (o->epoch_size) s->E = o->epoch_size;
     else s->E = (uint32_t)std::min<unsigned long long>(std::max<unsigned long long>(4ull * s->slots, 1024ull), 16384ull);
     s->inflight = o->epochs_in_flight > 0 ? o->epochs_in_flight : 4;
+    s->macc_cap = (int32_t)std::min<int64_t>(n, 1 << 16);   // larger meet sets take the slow path
     s->hist_cap = (int32_t)((s->cap + s->E - 1) / s->E + 2);
 
     auto alloc = [&](void **p, size_t bytes) {
@@ -326,6 +330,7 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
               alloc((void **)&s->partials, 8 * alloc_partials(n)) && alloc((void **)&s->prior, 8ull * n) &&
               alloc((void **)&s->recs, sizeof(Rec) * (size_t)n * s->slots) &&
               alloc((void **)&s->queues, 4ull * n * s->slots) && alloc((void **)&s->mbufs, 4ull * n * s->slots) &&
+              alloc((void **)&s->macc, 16ull * (size_t)s->macc_cap * s->slots) &&
               alloc((void **)&s->stamps, 4ull * s->slots) && alloc((void **)&s->work_ctr, 8) &&
               alloc((void **)&s->stats, sizeof(SampleStats)) && alloc((void **)&s->es, sizeof(EpochState)) &&
               alloc((void **)&s->hist, epoch_hist_bytes() * s->hist_cap);
@@ -347,6 +352,36 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     return KAD_OK;
 }
 
+extern "C" kad_status kad_sampler_reset(kad_sampler *s, uint64_t seed)
+{
+    if (!s) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = s->ctx->stream;
+    HIPCHK(hipStreamSynchronize(st));
+    s->o.seed = seed;
+    const double t0 = now_ms();
+    if (!(s->o.omega_override > 0.0)) {
+        HIPCHK(device_vd_bracket(s->g->dev(), st, &s->vd_lo, &s->vd_hi));
+        const double om = kad_omega(s->vd_lo, s->vd_hi, s->o.epsilon, s->o.delta);
+        if (om != s->omega) return fail(KAD_ESTATE, "omega changed for the same graph");
+    }
+    const double t_omega = now_ms() - t0;
+    kad_status r = reset_epochs(s);
+    if (r != KAD_OK) return r;
+    if (s->o.alloc_mode != KAD_ALLOC_EXPLICIT) s->delta_ready = false;
+    memset(&s->res, 0, sizeof(s->res));
+    s->res.t_omega_ms = t_omega;
+    s->res.omega = s->omega;
+    s->res.vd_lo = s->vd_lo;
+    s->res.vd_hi = s->vd_hi;
+    s->res.epoch_size = s->E;
+    s->res.slots = s->slots;
+    s->t_kernel_ms = 0.0;
+    s->launches = 0;
+    HIPCHK(hipStreamSynchronize(st));
+    return KAD_OK;
+}
+
 static SampleLaunch base_launch(kad_sampler *s)
 {
     SampleLaunch a;
@@ -359,6 +394,8 @@ static SampleLaunch base_launch(kad_sampler *s)
     a.recs = s->recs;
     a.queues = s->queues;
     a.mbufs = s->mbufs;
+    a.macc = s->macc;
+    a.macc_cap = s->macc_cap;
     a.stamps = s->stamps;
     a.work_ctr = s->work_ctr;
     a.stats = s->stats;
@@ -819,7 +856,7 @@ extern "C" kad_status kad_sample_paths(kad_sampler *s, uint64_t stream, uint64_t
     int32_t *dp = nullptr;
     int64_t *di = nullptr;
     HIPCHK(hipMallocAsync((void **)&dp, sizeof(int32_t) * (size_t)count * max_len + 4, st));
-    HIPCHK(hipMallocAsync((void **)&di, sizeof(int64_t) * (size_t)count * 8 + 8, st));
+    HIPCHK(hipMallocAsync((void **)&di, sizeof(int64_t) * (size_t)count * KAD_INFO_WIDTH + 8, st));
     HIPCHK(hipMemsetAsync(dp, 0xFF, sizeof(int32_t) * (size_t)count * max_len + 4, st));
     HIPCHK(hipMemsetAsync(s->scratch_counts, 0, 4ull * n, st));
     HIPCHK(hipMemsetAsync(s->stats, 0, sizeof(SampleStats), st));
@@ -827,11 +864,22 @@ extern "C" kad_status kad_sample_paths(kad_sampler *s, uint64_t stream, uint64_t
     if (r == KAD_OK) r = check_stats_error(s);
     if (r == KAD_OK) {
         HIPCHK(hipMemcpyAsync(h_paths, dp, sizeof(int32_t) * (size_t)count * max_len, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h_info, di, sizeof(int64_t) * (size_t)count * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h_info, di, sizeof(int64_t) * (size_t)count * KAD_INFO_WIDTH,
+                              hipMemcpyDeviceToHost, st));
     }
     hipFreeAsync(dp, st);
     hipFreeAsync(di, st);
     HIPCHK(hipStreamSynchronize(st));
+    if (r == KAD_OK) {
+        int khz = 0;
+        HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device));
+        for (uint32_t i = 0; i < count; ++i) {
+            for (int k : {8, 10, 11, 12, 13}) {
+                int64_t &t = h_info[(size_t)i * KAD_INFO_WIDTH + k];
+                t = khz > 0 ? (int64_t)((double)t * 1e6 / (double)khz) : -1;   // ticks -> ns
+            }
+        }
+    }
     return r;
 }
 

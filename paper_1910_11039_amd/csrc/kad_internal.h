@@ -10,6 +10,8 @@
 
 namespace kad {
 
+constexpr int KAD_INFO_WIDTH = 14;
+
 // Per-vertex, per-slot record of the bidirectional BFS (16 bytes).
 //   key   = (stamp << 32) | state; a record belongs to the current sample of
 //           its slot only when stamp equals the slot's current stamp, so a
@@ -61,13 +63,15 @@ struct SampleLaunch {
     Rec *recs;                      // slots * n records
     int32_t *queues;                // slots * n frontier entries
     int32_t *mbufs;                 // slots * n meet-set entries
+    unsigned long long *macc;       // slots * 2 * macc_cap meet-weight accumulators
+    int32_t macc_cap;
     uint32_t *stamps;               // slots stamps
     unsigned long long *work_ctr;   // next sample to take (device counter)
     SampleStats *stats;
     const int32_t *stop_flag;       // if non-null and set: skip the launch
     int sigma_fp;                   // 1: FP mode for every sample
     int32_t *paths;                 // optional per-sample paths [count][max_len]
-    int64_t *info;                  // optional per-sample info  [count][8]
+    int64_t *info;                  // optional per-sample info  [count][KAD_INFO_WIDTH]
     int32_t max_len;
 };
 

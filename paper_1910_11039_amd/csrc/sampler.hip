@@ -41,6 +41,7 @@ namespace kad {
 namespace {
 
 constexpr int MCAP = 1024;                 // meet sets up to this size are ranked in LDS
+constexpr int LMAX = 30;                   // layers whose queue offsets are kept in LDS
 constexpr double BIG = 0x1p400;
 constexpr double SHRINK = 0x1p-400;
 constexpr uint32_t X_SHIFT = 31;
@@ -100,27 +101,27 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v, int lane)
 
 template <int BS>
 struct Smem {
-    union {
-        struct {
-            int32_t u[BS];
-            int64_t rs[BS];
-            int64_t off[BS];
-            unsigned long long acc[BS];
-            unsigned long long acc2[BS];
-        } e;
-        struct {
-            int32_t id[MCAP];
-            unsigned long long w[MCAP];
-        } m;
-    };
+    struct {
+        int32_t u[BS];
+        int64_t rs[BS];
+        int64_t off[BS];
+        unsigned long long acc[BS];
+        unsigned long long acc2[BS];
+    } e;
+    struct {
+        int32_t id[MCAP];
+        unsigned long long w[MCAP];    // sigma_X accumulators, then the meet weights
+        unsigned long long w2[MCAP];   // sigma_Y accumulators
+    } m;
     int64_t wsum[BS / 64];
     unsigned long long nextdeg;
     unsigned long long sigst;
     unsigned long long fmax_bits;
     unsigned long long sid;
-    int64_t sdeg[2];
-    int32_t lo[2], hi[2], dep[2];
-    int32_t tail, mcount, ovf, err, w, wmin;
+    int64_t sdeg[2], psdeg[2];
+    int32_t lo[2], hi[2], dep[2], plo[2], phi[2];
+    int32_t loff[2][LMAX + 2];   // layer j of a side = queue positions [loff[j], loff[j+1])
+    int32_t tail, mcount, ovf, err, w, wmin, mpath;
     uint32_t stamp;
     int32_t s, t;
 };
@@ -148,6 +149,21 @@ __device__ int64_t block_excl_scan(Smem<BS> &sm, int64_t v, int64_t &total)
     __syncthreads();
     total = tot;
     return pre + x - v;
+}
+
+// Sum of one uint64 per thread over the workgroup (all threads call; all get it).
+template <int BS>
+__device__ uint64_t block_sum_u64(Smem<BS> &sm, uint64_t v)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_sum_u64(v);
+    if (lane == 0) sm.wsum[wid] = (int64_t)v;
+    __syncthreads();
+    uint64_t tot = 0;
+#pragma unroll
+    for (int i = 0; i < BS / 64; ++i) tot += (uint64_t)sm.wsum[i];
+    __syncthreads();
+    return tot;
 }
 
 struct Ctx {
@@ -245,7 +261,11 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
                 int pos = 0;
                 if (lane == leader) pos = atomicAdd(&sm.mcount, __popcll(mm));
                 pos = __shfl(pos, leader);
-                if (newmeet) c.MB[pos + (int)mbcnt(mm)] = w;
+                if (newmeet) {
+                    const int mp = pos + (int)mbcnt(mm);
+                    c.MB[mp] = w;
+                    st_sig(c.R + w, (uint64_t)mp);   // meet vertices are never expanded:
+                }                                    // their sigma field holds the list position
             }
         }
         __syncthreads();
@@ -362,6 +382,152 @@ __device__ void meet_weights_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, 
     }
 }
 
+// Adds sigma(u) to acc[position of w] for every edge (u, w) with u in the
+// queue positions [lo, hi) of `side` and w a meet vertex.
+template <int BS>
+__device__ void push_to_meet(Smem<BS> &sm, const Ctx &c, int side, int32_t lo, int32_t hi,
+                             unsigned long long *acc)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int32_t n = c.g.n;
+    for (int32_t base = lo; base < hi; base += BS) {
+        const int cnt = min(BS, hi - base);
+        int64_t rs = 0, d = 0;
+        uint64_t su = 0;
+        if (tid < cnt) {
+            const int32_t u = c.Q[qpos(n, side, base + tid)];
+            rs = c.g.rp[u];
+            d = c.g.rp[u + 1] - rs;
+            su = ld_sig(c.R + u);
+        }
+        sm.e.rs[tid] = rs;
+        sm.e.acc[tid] = su;
+        int64_t total;
+        const int64_t off = block_excl_scan<BS>(sm, d, total);
+        sm.e.off[tid] = off;
+        __syncthreads();
+        for (int64_t e0 = tid & ~63; e0 < total; e0 += BS) {
+            const int64_t e = e0 + lane;
+            if (e < total) {
+                int a = 0, b = cnt - 1;
+                while (a < b) {
+                    int mid = (a + b + 1) >> 1;
+                    if (sm.e.off[mid] <= e) a = mid; else b = mid - 1;
+                }
+                Rec *r = c.R + c.g.ci[sm.e.rs[a] + (e - sm.e.off[a])];
+                const uint64_t kk = ld_key(r);
+                if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & MEET_BIT)) {
+                    const uint64_t v = sm.e.acc[a];
+                    const unsigned long long old = atomicAdd(acc + ld_sig(r), (unsigned long long)v);
+                    if (old + v < old) sm.ovf = 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// For every meet vertex w (list position i): accX[i] += sigma of w's
+// neighbours in layer kX of X, accY[i] += sigma of w's neighbours in layer
+// kY - 1 of Y (either accumulator may be null: that side is skipped).
+template <int BS>
+__device__ void pull_to_meet(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t kY, int32_t m,
+                             unsigned long long *accX, unsigned long long *accY)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const uint32_t xstate = ((uint32_t)X << X_SHIFT) | (uint32_t)kX;
+    const uint32_t ystate = ((uint32_t)(1 - X) << X_SHIFT) | (uint32_t)(kY - 1);
+    for (int32_t base = 0; base < m; base += BS) {
+        const int cnt = min(BS, m - base);
+        int64_t rs = 0, d = 0;
+        if (tid < cnt) {
+            const int32_t w = c.MB[base + tid];
+            rs = c.g.rp[w];
+            d = c.g.rp[w + 1] - rs;
+        }
+        sm.e.rs[tid] = rs;
+        int64_t total;
+        const int64_t off = block_excl_scan<BS>(sm, d, total);
+        sm.e.off[tid] = off;
+        __syncthreads();
+        for (int64_t e0 = tid & ~63; e0 < total; e0 += BS) {
+            const int64_t e = e0 + lane;
+            if (e < total) {
+                int a = 0, b = cnt - 1;
+                while (a < b) {
+                    int mid = (a + b + 1) >> 1;
+                    if (sm.e.off[mid] <= e) a = mid; else b = mid - 1;
+                }
+                Rec *r = c.R + c.g.ci[sm.e.rs[a] + (e - sm.e.off[a])];
+                const uint64_t kk = ld_key(r);
+                if ((uint32_t)(kk >> 32) == c.cur) {
+                    const uint32_t st = (uint32_t)kk & ~MEET_BIT;
+                    unsigned long long *acc = nullptr;
+                    if (accX && st == xstate) acc = accX + base + a;
+                    else if (accY && kY >= 1 && st == ystate) acc = accY + base + a;
+                    if (acc) {
+                        const uint64_t v = ld_sig(r);
+                        const unsigned long long old = atomicAdd(acc, (unsigned long long)v);
+                        if (old + v < old) sm.ovf = 1;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Integer-mode meet weights a_w = sigma_X(w) * sigma_Y(w).  Each side's sum
+// is taken over whichever edge set is smaller: the edges of the layer the
+// predecessors live in (pushed to the meet vertices) or the edges of the
+// meet vertices themselves (pulled).  Integer sums do not depend on the
+// order, so both give the same value.  Weights end in sm.m.w (m <= MCAP),
+// in the slot's global buffer (m <= MACC) or, beyond that, in the meet
+// vertices' sigma fields; sm.mpath says which.
+template <int BS>
+__device__ void meet_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t kY, int32_t m,
+                         unsigned long long *gacc, int32_t macc_cap)
+{
+    const int tid = threadIdx.x;
+    const int path = (m <= MCAP) ? 0 : (m <= macc_cap ? 1 : 2);
+    if (path == 2) {
+        meet_weights_int<BS>(sm, c, X, kX, kY, m);
+        if (tid == 0) sm.mpath = 2;
+        __syncthreads();
+        return;
+    }
+    unsigned long long *accX = path == 0 ? sm.m.w : gacc;
+    unsigned long long *accY = path == 0 ? sm.m.w2 : gacc + macc_cap;
+    uint64_t dsum = 0;
+    for (int32_t i = tid; i < m; i += BS) {
+        const int32_t w = c.MB[i];
+        dsum += (uint64_t)(c.g.rp[w + 1] - c.g.rp[w]);
+        accX[i] = 0;
+        accY[i] = 0;
+        if (path == 0) sm.m.id[i] = w;
+    }
+    const uint64_t dM = block_sum_u64<BS>(sm, dsum);
+    const int Y = 1 - X;
+    const bool pushX = (uint64_t)sm.sdeg[X] <= dM;
+    const bool pushY = kY >= 1 && (uint64_t)sm.psdeg[Y] <= dM;
+    if (pushX) push_to_meet<BS>(sm, c, X, sm.lo[X], sm.hi[X], accX);
+    if (pushY) push_to_meet<BS>(sm, c, Y, sm.plo[Y], sm.phi[Y], accY);
+    if (!pushX || (kY >= 1 && !pushY))
+        pull_to_meet<BS>(sm, c, X, kX, kY, m, pushX ? nullptr : accX, (kY >= 1 && !pushY) ? accY : nullptr);
+    __syncthreads();
+    for (int32_t i = tid; i < m; i += BS) {
+        const uint64_t ax = accX[i];
+        const uint64_t ay = (kY == 0) ? 1ull : (uint64_t)accY[i];
+        if (__umul64hi(ax, ay) != 0) sm.ovf = 1;
+        const uint64_t a = ax * ay;
+        accX[i] = a;
+        const unsigned long long old = atomicAdd(&sm.sigst, (unsigned long long)a);
+        if (old + a < old) sm.ovf = 1;
+    }
+    if (tid == 0) sm.mpath = path;
+    __syncthreads();
+}
+
 template <int BS>
 __device__ void meet_weights_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t kY, int32_t m)
 {
@@ -405,15 +571,18 @@ __device__ int32_t next_min(Smem<BS> &sm, const Ctx &c, int32_t m, int32_t last)
 
 // Chooses the meet vertex; result in sm.w (all threads call).
 template <int BS>
-__device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2)
+__device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
+                            const unsigned long long *gacc)
 {
     constexpr int PER = MCAP / BS;
     const int tid = threadIdx.x;
     if (m <= MCAP) {
-        for (int32_t i = tid; i < m; i += BS) {
-            const int32_t w = c.MB[i];
-            sm.m.id[i] = w;
-            sm.m.w[i] = ld_sig(c.R + w);
+        if (c.fp) {   // integer mode filled ids and weights in LDS already
+            for (int32_t i = tid; i < m; i += BS) {
+                const int32_t w = c.MB[i];
+                sm.m.id[i] = w;
+                sm.m.w[i] = ld_sig(c.R + w);
+            }
         }
         __syncthreads();
         int32_t myid[PER];
@@ -478,19 +647,24 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2)
         __syncthreads();
         return;
     }
-    // Large meet sets: ranks against the whole list in global memory.
+    // Large meet sets, integer mode: the chosen vertex is the smallest id x
+    // at which the weight of the meet vertices with id <= x exceeds r;
+    // binary search over the id range, one block-wide sum per step.
     if (!c.fp) {
         const uint64_t r = __umul64hi(u2, (uint64_t)sm.sigst);
-        for (int32_t i = tid; i < m; i += BS) {
-            const int32_t id = c.MB[i];
-            uint64_t pre = 0;
-            for (int32_t jj = 0; jj < m; ++jj) {
-                const int32_t idj = c.MB[jj];
-                if (idj < id) pre += ld_sig(c.R + idj);
+        const bool global_w = sm.mpath == 1;    // weights in the slot buffer, else in sigma fields
+        int32_t lo = 0, hi = c.g.n - 1;
+        while (lo < hi) {
+            const int32_t mid = lo + ((hi - lo) >> 1);
+            uint64_t part = 0;
+            for (int32_t i = tid; i < m; i += BS) {
+                const int32_t id = c.MB[i];
+                if (id <= mid) part += global_w ? (uint64_t)gacc[i] : ld_sig(c.R + id);
             }
-            const uint64_t wt = ld_sig(c.R + id);
-            if (pre <= r && r - pre < wt) sm.w = id;
+            const uint64_t tot = block_sum_u64<BS>(sm, part);
+            if (tot > r) hi = mid; else lo = mid + 1;
         }
+        if (tid == 0) sm.w = lo;
         __syncthreads();
         return;
     }
@@ -604,6 +778,77 @@ __device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint6
     return last_nz;
 }
 
+__device__ __forceinline__ bool row_contains(const DevGraph &g, int32_t row, int32_t target)
+{
+    int64_t lo = g.rp[row], hi = g.rp[row + 1];
+    const int64_t end = hi;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (g.ci[mid] < target) lo = mid + 1; else hi = mid;
+    }
+    return lo < end && g.ci[lo] == target;
+}
+
+// Integer-mode predecessor pick at a high-degree vertex v: the candidates
+// are the vertices of layer l - 1 of `side` (queue positions [lo, hi))
+// adjacent to v, found by binary search in the shorter of the two rows;
+// the pick is the same as scanning v's row (ascending id = CSR order).
+// Wave 0 only; candidates go to the (idle) expansion LDS area.  Returns -2
+// when there are more candidates than fit (the caller scans v's row).
+template <int BS>
+__device__ int32_t pick_pred_layer(Smem<BS> &sm, const Ctx &c, int side, int32_t v, int32_t lo,
+                                   int32_t hi, uint64_t u, int lane)
+{
+    const int32_t n = c.g.n;
+    const int64_t dv = c.g.rp[v + 1] - c.g.rp[v];
+    uint64_t tot = 0;
+    int32_t ncand = 0;
+    for (int32_t p0 = lo; p0 < hi; p0 += 64) {
+        const int32_t p = p0 + lane;
+        bool cand = false;
+        int32_t x = -1;
+        uint64_t wt = 0;
+        if (p < hi) {
+            x = c.Q[qpos(n, side, p)];
+            const int64_t dx = c.g.rp[x + 1] - c.g.rp[x];
+            cand = dx <= dv ? row_contains(c.g, x, v) : row_contains(c.g, v, x);
+            if (cand) wt = ld_sig(c.R + x);
+        }
+        const uint64_t cm = __ballot(cand);
+        const int32_t k = __popcll(cm);
+        if (ncand + k > BS) return -2;
+        if (cand) {
+            const int32_t slot = ncand + (int32_t)mbcnt(cm);
+            sm.e.u[slot] = x;
+            sm.e.acc[slot] = wt;
+        }
+        ncand += k;
+        tot += wave_sum_u64(wt);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const uint64_t r = __umul64hi(u, tot);
+    int32_t pick = -1;
+    for (int32_t i0 = 0; i0 < ncand; i0 += 64) {
+        const int32_t i = i0 + lane;
+        bool hit = false;
+        int32_t id = -1;
+        if (i < ncand) {
+            id = sm.e.u[i];
+            const uint64_t wi = sm.e.acc[i];
+            uint64_t pre = 0;
+            for (int32_t j = 0; j < ncand; ++j)
+                if (sm.e.u[j] < id) pre += sm.e.acc[j];
+            hit = pre <= r && r - pre < wi;
+        }
+        const uint64_t hm = __ballot(hit);
+        if (hm) { pick = __shfl(id, __ffsll((unsigned long long)hm) - 1); break; }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return pick;
+}
+
 template <int BS>
 __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
 {
@@ -624,6 +869,7 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
     c.R = a.recs + slot * (size_t)n;
     c.Q = a.queues + slot * (size_t)n;
     c.MB = a.mbufs + slot * (size_t)n;
+    unsigned long long *gacc = a.macc + slot * 2 * (size_t)a.macc_cap;
     LocalStats ls{0, 0};
     unsigned long long st_edges = 0, st_exp = 0, st_path = 0, st_fp = 0, st_samples = 0, st_all = 0;
 
@@ -633,7 +879,9 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
         const unsigned long long sid = sm.sid;
         if (sid >= count) break;
         const uint64_t idx = first + sid;
+        const uint64_t t_begin = wall_clock64();
         int fp = a.sigma_fp;
+        int attempts = 0;
         if (tid == 0) {
             SampleDraws dr;
             dr.init(a.seed, a.stream, idx);
@@ -644,12 +892,14 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
             sm.s = s;
             sm.t = t;
         }
+        uint64_t t_exp = 0, t_mw = 0, t_ch = 0, t_walk = 0, t_mark = 0;
         int X = 0;
         int32_t kX = 0, kY = 0, m = 0;
         unsigned long long edges = 0;
         int steps = 0;
         bool failed = false;
         for (;;) {  // attempt (integer mode, then FP mode if it overflowed)
+            attempts += 1;
             if (tid == 0) {
                 const uint32_t cur = a.stamps[slot] + 1;
                 a.stamps[slot] = cur;
@@ -663,6 +913,11 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                 c.Q[n - 1] = t;
                 sm.lo[0] = sm.lo[1] = 0;
                 sm.hi[0] = sm.hi[1] = 1;
+                sm.plo[0] = sm.plo[1] = 0;
+                sm.phi[0] = sm.phi[1] = 0;
+                sm.loff[0][0] = sm.loff[1][0] = 0;
+                sm.loff[0][1] = sm.loff[1][1] = 1;
+                sm.psdeg[0] = sm.psdeg[1] = 0;
                 sm.dep[0] = sm.dep[1] = 0;
                 sm.sdeg[0] = a.g.rp[s + 1] - a.g.rp[s];
                 sm.sdeg[1] = a.g.rp[t + 1] - a.g.rp[t];
@@ -689,9 +944,11 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                     sm.fmax_bits = 0;
                 }
                 __syncthreads();
+                t_mark = wall_clock64();
                 if (!fp) expand_int<BS>(sm, c, X, k, lo, hi, ls);
                 else expand_fp<BS>(sm, c, X, k, lo, hi, ls);
                 __syncthreads();
+                t_exp += wall_clock64() - t_mark;
                 if (fp && k >= 1 && as_f64(sm.fmax_bits) > BIG) {
                     for (int32_t p = lo + tid; p < hi; p += BS) {
                         Rec *r = c.R + c.Q[qpos(n, X, p)];
@@ -704,10 +961,14 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                 if (sm.tail == hi) { failed = true; break; }
                 __syncthreads();
                 if (tid == 0) {
+                    sm.plo[X] = lo;
+                    sm.phi[X] = hi;
+                    sm.psdeg[X] = sm.sdeg[X];
                     sm.lo[X] = hi;
                     sm.hi[X] = sm.tail;
                     sm.dep[X] = k + 1;
                     sm.sdeg[X] = (int64_t)sm.nextdeg;
+                    if (k + 2 <= LMAX + 1) sm.loff[X][k + 2] = sm.tail;
                 }
                 __syncthreads();
             }
@@ -718,9 +979,11 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
             kY = sm.dep[1 - X];
             m = sm.mcount;
             __syncthreads();
-            if (!fp) meet_weights_int<BS>(sm, c, X, kX, kY, m);
+            t_mark = wall_clock64();
+            if (!fp) meet_int<BS>(sm, c, X, kX, kY, m, gacc, a.macc_cap);
             else meet_weights_fp<BS>(sm, c, X, kX, kY, m);
             __syncthreads();
+            t_mw += wall_clock64() - t_mark;
             if (!fp && sm.ovf) { __syncthreads(); fp = 1; continue; }
             break;
         }
@@ -732,12 +995,15 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
         // meet vertex
         if (tid == 0) sm.w = -1;
         __syncthreads();
+        t_mark = wall_clock64();
         {
             SampleDraws dr;
             dr.init(a.seed, a.stream, idx);
             const uint64_t u2 = dr.get(2);
-            choose_meet<BS>(sm, c, m, u2);
+            choose_meet<BS>(sm, c, m, u2, gacc);
         }
+        t_ch = wall_clock64() - t_mark;
+        t_mark = wall_clock64();
         // walk back and count (wave 0)
         const int32_t d = kX + 1 + kY;
         if (sm.w < 0) {   // no meet vertex chosen: report instead of walking
@@ -772,7 +1038,14 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                 int32_t v = w;
                 for (int32_t l = dep[side]; l >= 2; --l) {
                     const uint64_t u = dr.get(j++);
-                    const int32_t p = pick_pred(c, side, v, l, u, lane);
+                    int32_t p = -2;
+                    if (!fp && l - 1 <= LMAX) {
+                        const int32_t llo = sm.loff[side][l - 1], lhi = sm.loff[side][l];
+                        const int64_t dv = a.g.rp[v + 1] - a.g.rp[v];
+                        if (2 * (int64_t)(lhi - llo) < dv)
+                            p = pick_pred_layer<BS>(sm, c, side, v, llo, lhi, u, lane);
+                    }
+                    if (p == -2) p = pick_pred(c, side, v, l, u, lane);
                     if (p < 0) {   // no predecessor found: report, stop this walk
                         if (lane == 0) a.stats->error = 3;
                         break;
@@ -786,7 +1059,7 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                 }
             }
             if (lane == 0 && a.info) {
-                int64_t *inf = a.info + (size_t)sid * 8;
+                int64_t *inf = a.info + (size_t)sid * KAD_INFO_WIDTH;
                 inf[0] = s;
                 inf[1] = t;
                 inf[2] = d;
@@ -795,6 +1068,13 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                 inf[5] = m;
                 inf[6] = steps;
                 inf[7] = (int64_t)edges;
+                t_walk = wall_clock64() - t_mark;
+                inf[8] = (int64_t)(wall_clock64() - t_begin);   // ticks of the constant wall clock
+                inf[9] = attempts;
+                inf[10] = (int64_t)t_exp;
+                inf[11] = (int64_t)t_mw;
+                inf[12] = (int64_t)t_ch;
+                inf[13] = (int64_t)t_walk;
             }
             st_path += cnt;
         }

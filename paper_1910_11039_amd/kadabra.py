@@ -25,6 +25,7 @@ KAD_SIGMA_AUTO, KAD_SIGMA_FP = 0, 1
 KAD_STOP_NONE, KAD_STOP_COND, KAD_STOP_OMEGA = 0, 1, 2
 KAD_GRAPH_VALIDATE = 1
 MLP_PARAMS = 4481
+INFO_WIDTH = 14
 
 
 class KadError(RuntimeError):
@@ -70,6 +71,7 @@ SIGNATURES = [
     ("kad_graph_free", None, [_vp]),
     ("kad_sampler_init", C.c_int, [_vp, _vp, _P(kad_opts), _P(_vp)]),
     ("kad_sampler_free", None, [_vp]),
+    ("kad_sampler_reset", C.c_int, [_vp, _u64]),
     ("kad_set_delta", C.c_int, [_vp, _vp, _vp]),
     ("kad_set_mlp_weights", C.c_int, [_vp, _vp, _vp]),
     ("kad_step_epoch", C.c_int, [_vp, _P(C.c_int)]),
@@ -164,6 +166,10 @@ def kad_sampler_free(s):
     lib().kad_sampler_free(s)
 
 
+def kad_sampler_reset(s, seed: int):
+    _check(lib().kad_sampler_reset(s, seed))
+
+
 def kad_set_delta(s, delta_L: np.ndarray, delta_U: np.ndarray):
     dl = np.ascontiguousarray(delta_L, dtype=np.float64)
     du = np.ascontiguousarray(delta_U, dtype=np.float64)
@@ -243,7 +249,7 @@ def kad_count_samples(s, stream: int, first: int, count: int, n: int) -> np.ndar
 
 def kad_sample_paths(s, stream: int, first: int, count: int, max_len: int):
     paths = np.full((count, max_len), -1, dtype=np.int32)
-    info = np.zeros((count, 8), dtype=np.int64)
+    info = np.zeros((count, INFO_WIDTH), dtype=np.int64)
     _check(lib().kad_sample_paths(s, stream, first, count, max_len, _p(paths), _p(info)))
     return paths, info
 
@@ -392,6 +398,9 @@ class Sampler:
             self.close()
         except Exception:
             pass
+
+    def reset(self, seed: int):
+        kad_sampler_reset(self.h, seed)
 
     def set_delta(self, dl, du):
         kad_set_delta(self.h, dl, du)

@@ -95,7 +95,8 @@ def _compare_paths(S, g, oracle, mode, count, seed, stream, first):
         assert np.array_equal(got, p), (i, got, p)
         assert np.all(paths[i, d + 1:] == -1)
         want = [inf.s, inf.t, inf.d, inf.w, inf.fp_mode, inf.meet_size, inf.steps, inf.edges]
-        assert list(info[i]) == want, (i, list(info[i]), want)
+        assert list(info[i, :8]) == want, (i, list(info[i, :8]), want)
+        assert info[i, 9] == (2 if (inf.fp_mode and mode == 0) else 1)
     return info
 
 
