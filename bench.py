@@ -122,8 +122,8 @@ def main():
     value = samples / wall
     agg = {k: sum(r[k] for r in results) for k in
            ("edges_scanned", "vertices_expanded", "vertices_visited", "pred_edges", "path_vertices",
-            "t_sample_kernel_ms", "sample_launches", "tau")}
-    agg["samples"] = agg["tau"]
+            "t_sample_kernel_ms", "sample_launches", "tau", "samples_run")}
+    agg["samples"] = agg["samples_run"]
     roof = None
     if agg["sample_launches"] > 0 and agg["t_sample_kernel_ms"] > 0:
         per_launch_bytes = algorithmic_bytes(agg) / agg["sample_launches"]

@@ -130,6 +130,8 @@ typedef struct {
     double min_margin;            /* min over vertices of |eps - max(f, g)|       */
     uint32_t epoch_size;          /* epoch size actually used                     */
     int32_t slots;                /* concurrent samples actually used             */
+    int64_t samples_run;          /* samples the kernels finished, speculative    */
+                                  /* ones after the stop epoch included           */
 } kad_result;
 
 /* kad_sampler_init: allocate the sampler state for graph g and options o.

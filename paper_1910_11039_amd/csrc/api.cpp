@@ -66,8 +66,17 @@ struct kad_sampler {
     unsigned long long cap;
     uint32_t E;
     int slots, block, inflight;
+    // P slot pools, state frames and streams: epoch k uses pool, frame and
+    // stream k mod P, so that later epochs sample while epoch k finishes
+    // its tail
+    int P;
+    hipStream_t sts[4];          // sts[0] is the context's stream
+    hipEvent_t ev_merge[4];
+    std::vector<hipEvent_t> ev_ring;   // one per epoch in flight: its merge is done
+    HostStatus *h_status, *d_status;   // pinned verdict mirror
+    unsigned long long next_epoch;     // epochs enqueued since the reset
     // device state
-    uint32_t *c, *sf[2], *cprime, *scratch_counts;
+    uint32_t *c, *sf[4], *cprime, *scratch_counts;
     double *LL, *LU, *lo_hi, *partials, *prior;
     Rec *recs;
     int32_t *queues, *mbufs;
@@ -227,7 +236,11 @@ extern "C" kad_status kad_vd_bracket(kad_ctx *ctx, const kad_graph *g, int64_t *
 static void free_sampler(kad_sampler *s)
 {
     if (s->have_graph) hipGraphExecDestroy(s->gexec);
-    void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->cprime, s->scratch_counts, s->LL, s->LU, s->lo_hi, s->macc,
+    for (hipEvent_t e : s->ev_ring) hipEventDestroy(e);
+    for (hipEvent_t e : s->ev_merge) if (e) hipEventDestroy(e);
+    for (int i = 1; i < 4; ++i) if (s->sts[i]) hipStreamDestroy(s->sts[i]);
+    if (s->h_status) hipHostFree(s->h_status);
+    void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->sf[2], s->sf[3], s->cprime, s->scratch_counts, s->LL, s->LU, s->lo_hi, s->macc,
                     s->partials, s->prior, s->recs, s->queues, s->mbufs, s->stamps, s->work_ctr,
                     s->stats, s->es, s->hist};
     for (void *p : ptrs)
@@ -257,10 +270,12 @@ static kad_status reset_epochs(kad_sampler *s)
     init.range[2] = 0;
     HIPCHK(hipMemcpyAsync(s->es, &init, sizeof(init), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemsetAsync(s->c, 0, sizeof(uint32_t) * s->g->n, st));
-    HIPCHK(hipMemsetAsync(s->sf[0], 0, sizeof(uint32_t) * s->g->n, st));
-    HIPCHK(hipMemsetAsync(s->sf[1], 0, sizeof(uint32_t) * s->g->n, st));
-    HIPCHK(hipMemsetAsync(s->work_ctr, 0, sizeof(unsigned long long), st));
+    for (int i = 0; i < s->P; ++i) HIPCHK(hipMemsetAsync(s->sf[i], 0, sizeof(uint32_t) * s->g->n, st));
+    HIPCHK(hipMemsetAsync(s->work_ctr, 0, 4 * sizeof(unsigned long long), st));
     HIPCHK(hipMemsetAsync(s->stats, 0, sizeof(SampleStats), st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (s->h_status) memset(s->h_status, 0, sizeof(HostStatus));
+    s->next_epoch = 0;
     return KAD_OK;
 }
 
@@ -304,12 +319,13 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
                             16ull * (size_t)std::min<int64_t>(n, 1 << 16);
     size_t free_b = 0, total_b = 0;
     HIPCHK(hipMemGetInfo(&free_b, &total_b));
-    size_t budget = o->visited_budget_bytes ? (size_t)o->visited_budget_bytes : free_b / 2;
+    size_t budget = o->visited_budget_bytes ? (size_t)o->visited_budget_bytes : free_b / 4 * 3;
     // Persistent workgroups: more slots than can be resident would only
     // start once resident ones exit, so the default is one full wave of them.
     int want = o->slots > 0 ? o->slots : ctx->cu_count * sampler_blocks_per_cu(block);
-    int fit = (int)std::min<size_t>(budget / per_slot, 1 << 16);
-    s->slots = std::max(1, std::min(want, fit));
+    // pools: up to 4 while a full wave of slots fits each, at least 2
+    s->slots = std::max(1, std::min(want, (int)std::min<size_t>(budget / (2 * per_slot), 1 << 16)));
+    s->P = (int)std::max<size_t>(2, std::min<size_t>(4, budget / ((size_t)s->slots * per_slot)));
     if (o->slots > 0 && s->slots < o->slots) {
         delete s;
         return fail(KAD_ENOMEM, "requested slots exceed the visited-state budget");
@@ -324,22 +340,34 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
         return hipMalloc(p, std::max<size_t>(bytes, 16)) == hipSuccess;
     };
     bool ok = alloc((void **)&s->c, 4ull * n) && alloc((void **)&s->sf[0], 4ull * n) &&
-              alloc((void **)&s->sf[1], 4ull * n) && alloc((void **)&s->cprime, 4ull * n) &&
+              alloc((void **)&s->sf[1], 4ull * n) && alloc((void **)&s->sf[2], 4ull * n) &&
+              alloc((void **)&s->sf[3], 4ull * n) && alloc((void **)&s->cprime, 4ull * n) &&
               alloc((void **)&s->scratch_counts, 4ull * n) && alloc((void **)&s->LL, 8ull * n) &&
               alloc((void **)&s->LU, 8ull * n) && alloc((void **)&s->lo_hi, 64) &&
               alloc((void **)&s->partials, 8 * alloc_partials(n)) && alloc((void **)&s->prior, 8ull * n) &&
-              alloc((void **)&s->recs, sizeof(Rec) * (size_t)n * s->slots) &&
-              alloc((void **)&s->queues, 4ull * n * s->slots) && alloc((void **)&s->mbufs, 4ull * n * s->slots) &&
-              alloc((void **)&s->macc, 16ull * (size_t)s->macc_cap * s->slots) &&
-              alloc((void **)&s->stamps, 4ull * s->slots) && alloc((void **)&s->work_ctr, 8) &&
+              alloc((void **)&s->recs, sizeof(Rec) * (size_t)n * s->P * s->slots) &&
+              alloc((void **)&s->queues, 4ull * n * s->P * s->slots) &&
+              alloc((void **)&s->mbufs, 4ull * n * s->P * s->slots) &&
+              alloc((void **)&s->macc, 16ull * (size_t)s->macc_cap * s->P * s->slots) &&
+              alloc((void **)&s->stamps, 4ull * s->P * s->slots) && alloc((void **)&s->work_ctr, 32) &&
               alloc((void **)&s->stats, sizeof(SampleStats)) && alloc((void **)&s->es, sizeof(EpochState)) &&
               alloc((void **)&s->hist, epoch_hist_bytes() * s->hist_cap);
-    if (!ok || hipHostMalloc((void **)&s->h_es, sizeof(EpochState), 0) != hipSuccess) {
+    if (!ok || hipHostMalloc((void **)&s->h_es, sizeof(EpochState), 0) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_status, sizeof(HostStatus), hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&s->d_status, s->h_status, 0) != hipSuccess ||
+        false) {
         free_sampler(s);
         return fail(KAD_ENOMEM, "sampler allocation failed");
     }
-    HIPCHK(hipMemsetAsync(s->recs, 0, sizeof(Rec) * (size_t)n * s->slots, st));
-    HIPCHK(hipMemsetAsync(s->stamps, 0, 4ull * s->slots, st));
+    s->sts[0] = st;
+    for (int i = 0; i < s->P; ++i) {
+        if (i > 0) HIPCHK(hipStreamCreate(&s->sts[i]));
+        HIPCHK(hipEventCreateWithFlags(&s->ev_merge[i], hipEventDisableTiming));
+    }
+    s->ev_ring.resize(std::max(s->inflight, s->P) + 1);
+    for (auto &e : s->ev_ring) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipMemsetAsync(s->recs, 0, sizeof(Rec) * (size_t)n * s->P * s->slots, st));
+    HIPCHK(hipMemsetAsync(s->stamps, 0, 4ull * s->P * s->slots, st));
     kad_status rs = reset_epochs(s);
     if (rs != KAD_OK) { free_sampler(s); return rs; }
     HIPCHK(hipStreamSynchronize(st));
@@ -382,8 +410,9 @@ extern "C" kad_status kad_sampler_reset(kad_sampler *s, uint64_t seed)
     return KAD_OK;
 }
 
-static SampleLaunch base_launch(kad_sampler *s)
+static SampleLaunch base_launch(kad_sampler *s, int pool = 0)
 {
+    const size_t n = (size_t)s->g->n, sl = (size_t)s->slots * pool;
     SampleLaunch a;
     memset(&a, 0, sizeof(a));
     a.g = s->g->dev();
@@ -391,13 +420,13 @@ static SampleLaunch base_launch(kad_sampler *s)
     a.stream = KAD_STREAM_ADS;
     a.sf[0] = s->sf[0];
     a.sf[1] = s->sf[1];
-    a.recs = s->recs;
-    a.queues = s->queues;
-    a.mbufs = s->mbufs;
-    a.macc = s->macc;
+    a.recs = s->recs + sl * n;
+    a.queues = s->queues + sl * n;
+    a.mbufs = s->mbufs + sl * n;
+    a.macc = s->macc + sl * 2 * (size_t)s->macc_cap;
     a.macc_cap = s->macc_cap;
-    a.stamps = s->stamps;
-    a.work_ctr = s->work_ctr;
+    a.stamps = s->stamps + sl;
+    a.work_ctr = s->work_ctr + pool;
     a.stats = s->stats;
     a.sigma_fp = s->o.sigma_mode == KAD_SIGMA_FP;
     return a;
@@ -562,7 +591,8 @@ static kad_status ensure_delta(kad_sampler *s)
     return KAD_OK;
 }
 
-// Enqueue one epoch: sampler (range read on the device) + merge/stop.
+// Enqueue one epoch for graph capture (single stream): sampler with the
+// range read on the device, then merge/stop.
 static kad_status enqueue_epoch(kad_sampler *s, hipEvent_t ev0, hipEvent_t ev1)
 {
     hipStream_t st = s->ctx->stream;
@@ -574,7 +604,37 @@ static kad_status enqueue_epoch(kad_sampler *s, hipEvent_t ev0, hipEvent_t ev1)
     if (ev1) HIPCHK(hipEventRecord(ev1, st));
     HIPCHK(launch_merge_stop_impl(s->g->dev(), s->c, s->sf[0], s->sf[1], s->LL, s->LU, s->omega,
                                   s->o.epsilon, s->cap, s->E, s->es, s->work_ctr, s->hist, s->hist_cap,
-                                  st));
+                                  s->d_status, st));
+    return KAD_OK;
+}
+
+// Enqueue epoch k overlapped with its neighbours: epoch k uses stream,
+// slot pool and state frame k mod P; its sampler runs after that stream's
+// previous merge (which cleared the frame), and its merge waits for the
+// merge of epoch k - 1, so c~ grows and the rule is checked in epoch order
+// on exactly samples [0, tau).  A sampler whose epoch turns out to follow
+// the stop quits at its next sample; its frame is never merged.
+static kad_status enqueue_epoch_k(kad_sampler *s, unsigned long long k, hipEvent_t ev0, hipEvent_t ev1)
+{
+    const int p = (int)(k % (unsigned long long)s->P);
+    hipStream_t st = s->sts[p];
+    const unsigned long long first = k * s->E;
+    const unsigned long long count = std::min<unsigned long long>(s->E, s->cap - first);
+    SampleLaunch a = base_launch(s, p);
+    a.first = first;
+    a.count = count;
+    a.sf[0] = a.sf[1] = s->sf[p];
+    a.stop_flag = &s->es->stopped;
+    HIPCHK(hipMemsetAsync(a.work_ctr, 0, sizeof(unsigned long long), st));
+    if (ev0) HIPCHK(hipEventRecord(ev0, st));
+    HIPCHK(launch_sampler(a, (int)std::min<unsigned long long>(s->slots, count), s->block, st));
+    if (ev1) HIPCHK(hipEventRecord(ev1, st));
+    if (k > 0) HIPCHK(hipStreamWaitEvent(st, s->ev_merge[(p + s->P - 1) % s->P], 0));
+    HIPCHK(launch_merge_stop_impl(s->g->dev(), s->c, s->sf[p], s->sf[p], s->LL, s->LU, s->omega,
+                                  s->o.epsilon, s->cap, s->E, s->es, nullptr, s->hist, s->hist_cap,
+                                  s->d_status, st));
+    HIPCHK(hipEventRecord(s->ev_merge[p], st));
+    HIPCHK(hipEventRecord(s->ev_ring[k % s->ev_ring.size()], st));
     return KAD_OK;
 }
 
@@ -594,8 +654,9 @@ extern "C" kad_status kad_step_epoch(kad_sampler *s, int *stopped)
     r = read_state(s);
     if (r != KAD_OK) return r;
     if (!s->h_es->stopped) {
-        r = enqueue_epoch(s, nullptr, nullptr);
+        r = enqueue_epoch_k(s, s->next_epoch++, nullptr, nullptr);
         if (r != KAD_OK) return r;
+        for (int i = 1; i < s->P; ++i) HIPCHK(hipStreamSynchronize(s->sts[i]));
         r = read_state(s);
         if (r != KAD_OK) return r;
         r = check_stats_error(s);
@@ -622,6 +683,7 @@ static kad_status fill_result(kad_sampler *s)
     r.pred_edges = (int64_t)h.pred_edges;
     r.path_vertices = (int64_t)h.path_vertices;
     r.fp_samples = (int64_t)h.fp_samples;
+    r.samples_run = (int64_t)h.samples;
     r.t_sample_kernel_ms = s->t_kernel_ms;
     r.sample_launches = s->launches;
     r.epoch_size = s->E;
@@ -666,11 +728,20 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
         r = build_graph(s);
         if (r != KAD_OK) return r;
     }
-    while (!s->h_es->stopped) {
-        if (s->have_graph && !timing) {
+    if (s->have_graph && !timing) {
+        while (!s->h_es->stopped) {
             HIPCHK(hipGraphLaunch(s->gexec, st));
-        } else {
-            for (int i = 0; i < s->inflight; ++i) {
+            r = read_state(s);
+            if (r != KAD_OK) return r;
+        }
+    } else if (!s->h_es->stopped) {
+        // Keep `inflight` epochs queued ahead of the newest verdict the host
+        // has seen; the verdict of epoch k is polled from pinned memory once
+        // its merge has completed.
+        const unsigned long long total = (s->cap + s->E - 1) / s->E;
+        unsigned long long known = s->next_epoch;
+        for (;;) {
+            while (s->next_epoch < total && s->next_epoch < known + (unsigned long long)s->inflight) {
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (timing) {
                     HIPCHK(hipEventCreate(&e0));
@@ -678,24 +749,28 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
                     evs.push_back(e0);
                     evs.push_back(e1);
                 }
-                r = enqueue_epoch(s, e0, e1);
+                r = enqueue_epoch_k(s, s->next_epoch++, e0, e1);
                 if (r != KAD_OK) return r;
             }
+            HIPCHK(hipEventSynchronize(s->ev_ring[known % s->ev_ring.size()]));
+            ++known;
+            if (__atomic_load_n(&s->h_status->stopped, __ATOMIC_ACQUIRE)) break;
+            if (known >= total) break;
         }
+        for (int i = 0; i < s->P; ++i) HIPCHK(hipStreamSynchronize(s->sts[i]));
         r = read_state(s);
         if (r != KAD_OK) return r;
     }
     const double t_ads1 = now_ms();
     if (timing) {
-        // only launches that sampled (before the stop) are counted
-        const size_t ran = (size_t)(s->h_es->epoch - epoch_at_start);
+        // every launch counts, speculative ones included: the work counters
+        // cover their samples too
+        (void)epoch_at_start;
         for (size_t i = 0; i + 1 < evs.size(); i += 2) {
-            if (i / 2 < ran) {
-                float ms = 0.0f;
-                HIPCHK(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
-                s->t_kernel_ms += ms;
-                s->launches += 1;
-            }
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
+            s->t_kernel_ms += ms;
+            s->launches += 1;
         }
         for (hipEvent_t e : evs) hipEventDestroy(e);
     }

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(MB) void k_merge_stop(int32_t n, uint32_t *c, uint3
                                                    double eps, unsigned long long cap,
                                                    unsigned long long E, EpochState *es,
                                                    unsigned long long *work_ctr, EpochHist *hist,
-                                                   int32_t hist_cap)
+                                                   int32_t hist_cap, HostStatus *hs)
 {
     if (__hip_atomic_load(&es->stopped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const unsigned long long first = es->range[0], count = es->range[1];
@@ -131,9 +131,16 @@ __global__ __launch_bounds__(MB) void k_merge_stop(int32_t n, uint32_t *c, uint3
     es->range[0] = nfirst;
     es->range[1] = stop ? 0 : ((cap - nfirst) < E ? (cap - nfirst) : E);
     es->range[2] = ep + 1;
-    *work_ctr = 0;
+    if (work_ctr) *work_ctr = 0;
     __threadfence();
     __hip_atomic_store(&es->stopped, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (hs) {
+        hs->reason = reason;
+        hs->epoch = ep + 1;
+        hs->tau = tau_u;
+        hs->stopped = stop;
+        __threadfence_system();
+    }
 }
 
 __global__ void k_fg(int32_t n, const uint32_t *c, double tau, const double *LL, const double *LU,
@@ -322,10 +329,10 @@ hipError_t launch_merge_stop_impl(const DevGraph &g, uint32_t *c, uint32_t *sf0,
                                   const double *LL, const double *LU, double omega, double eps,
                                   unsigned long long cap, unsigned long long E, EpochState *es,
                                   unsigned long long *work_ctr, void *hist, int32_t hist_cap,
-                                  hipStream_t st)
+                                  HostStatus *hs, hipStream_t st)
 {
     hipLaunchKernelGGL(k_merge_stop, dim3(grid_for(g.n, MB, 2048)), dim3(MB), 0, st, g.n, c, sf0, sf1,
-                       LL, LU, omega, eps, cap, E, es, work_ctr, (EpochHist *)hist, hist_cap);
+                       LL, LU, omega, eps, cap, E, es, work_ctr, (EpochHist *)hist, hist_cap, hs);
     return hipGetLastError();
 }
 

@@ -93,11 +93,18 @@ struct EpochState {
     unsigned long long range[3];   // {first, count, sf_index} of the next epoch
 };
 
+// Mirror of the epoch verdict in pinned host memory, written by the merge
+// kernel so the host can poll it without a device-to-host copy.
+struct HostStatus {
+    int32_t stopped, reason;
+    unsigned long long epoch, tau;
+};
+
 hipError_t launch_merge_stop_impl(const DevGraph &g, uint32_t *c, uint32_t *sf0, uint32_t *sf1,
                                   const double *LL, const double *LU, double omega, double eps,
                                   unsigned long long cap, unsigned long long E, EpochState *es,
                                   unsigned long long *work_ctr, void *hist, int32_t hist_cap,
-                                  hipStream_t st);
+                                  HostStatus *hs, hipStream_t st);
 size_t epoch_hist_bytes();   // per-epoch record: max_f, max_g, min_margin (f64), ok (i32), pad
 size_t alloc_partials(int32_t n);
 hipError_t launch_fg(int32_t n, const uint32_t *c, double tau, const double *LL, const double *LU,

@@ -874,7 +874,12 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
     unsigned long long st_edges = 0, st_exp = 0, st_path = 0, st_fp = 0, st_samples = 0, st_all = 0;
 
     for (;;) {
-        if (tid == 0) sm.sid = atomicAdd(a.work_ctr, 1ull);
+        if (tid == 0) {
+            // a later epoch that became speculative (the run stopped) quits early
+            const bool stop = a.stop_flag &&
+                              __hip_atomic_load(a.stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sm.sid = stop ? count : atomicAdd(a.work_ctr, 1ull);
+        }
         __syncthreads();
         const unsigned long long sid = sm.sid;
         if (sid >= count) break;

@@ -52,7 +52,7 @@ class kad_result(C.Structure):
                 ("vertices_visited", C.c_int64), ("pred_edges", C.c_int64),
                 ("path_vertices", C.c_int64), ("fp_samples", C.c_int64), ("max_f", C.c_double),
                 ("max_g", C.c_double), ("min_margin", C.c_double), ("epoch_size", C.c_uint32),
-                ("slots", C.c_int32)]
+                ("slots", C.c_int32), ("samples_run", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
