@@ -217,6 +217,15 @@ kad_status kad_vd_bracket(kad_ctx *ctx, const kad_graph *g, int64_t *vd_lo, int6
  * the bracket [vd_lo, vd_hi] (the upper end unless both ends agree). */
 double kad_omega(int64_t vd_lo, int64_t vd_hi, double eps, double delta);
 
+/* ---- device memory plumbing (for callers without another HIP runtime):
+ * kad_device_alloc returns `bytes` of device memory on the context's device
+ * in *d_out (caller-owned, release with kad_device_free); the copies are
+ * synchronous on the context's stream. */
+kad_status kad_device_alloc(kad_ctx *ctx, size_t bytes, void **d_out);
+kad_status kad_device_free(kad_ctx *ctx, void *d_ptr);
+kad_status kad_memcpy_h2d(kad_ctx *ctx, void *d_dst, const void *h_src, size_t bytes);
+kad_status kad_memcpy_d2h(kad_ctx *ctx, void *h_dst, const void *d_src, size_t bytes);
+
 /* ---- learned prior (not in the paper: a learned replacement for the
  * calibration phase; delta_L/delta_U remain a valid split either way) ---- */
 

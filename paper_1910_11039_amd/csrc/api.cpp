@@ -1105,3 +1105,40 @@ extern "C" kad_status kad_mlp_forward(kad_mlp *m, const float *d_x, int64_t rows
     HIPCHK(hipStreamSynchronize(st));
     return KAD_OK;
 }
+
+// ----------------------------------------------------------- device memory
+
+extern "C" kad_status kad_device_alloc(kad_ctx *ctx, size_t bytes, void **d_out)
+{
+    if (!ctx || !d_out) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (hipMalloc(d_out, std::max<size_t>(bytes, 16)) != hipSuccess) return fail(KAD_ENOMEM, "hipMalloc failed");
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_device_free(kad_ctx *ctx, void *d_ptr)
+{
+    if (!ctx) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipFree(d_ptr));
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_memcpy_h2d(kad_ctx *ctx, void *d_dst, const void *h_src, size_t bytes)
+{
+    if (!ctx || (bytes && (!d_dst || !h_src))) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipMemcpyAsync(d_dst, h_src, bytes, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return KAD_OK;
+}
+
+extern "C" kad_status kad_memcpy_d2h(kad_ctx *ctx, void *h_dst, const void *d_src, size_t bytes)
+{
+    if (!ctx || (bytes && (!d_src || !h_dst))) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipMemcpyAsync(h_dst, d_src, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return KAD_OK;
+}

@@ -89,6 +89,10 @@ SIGNATURES = [
     ("kad_vd_bracket", C.c_int, [_vp, _vp, _P(_i64), _P(_i64)]),
     ("kad_omega", _dbl, [_i64, _i64, _dbl, _dbl]),
     ("kad_features", C.c_int, [_vp, _vp, _vp, _vp]),
+    ("kad_device_alloc", C.c_int, [_vp, C.c_size_t, _P(_vp)]),
+    ("kad_device_free", C.c_int, [_vp, _vp]),
+    ("kad_memcpy_h2d", C.c_int, [_vp, _vp, _vp, C.c_size_t]),
+    ("kad_memcpy_d2h", C.c_int, [_vp, _vp, _vp, C.c_size_t]),
     ("kad_mlp_create", C.c_int, [_vp, _vp, _P(_vp)]),
     ("kad_mlp_free", None, [_vp]),
     ("kad_mlp_get_params", C.c_int, [_vp, _vp]),
@@ -278,6 +282,54 @@ def kad_features(ctx, g, n: int) -> np.ndarray:
 
 def kad_features_device(ctx, g, d_out_ptr: int):
     _check(lib().kad_features(ctx, g, C.c_void_p(d_out_ptr), None))
+
+
+def kad_device_alloc(ctx, nbytes: int) -> int:
+    out = _vp()
+    _check(lib().kad_device_alloc(ctx, nbytes, C.byref(out)))
+    return out.value
+
+
+def kad_device_free(ctx, d_ptr: int):
+    _check(lib().kad_device_free(ctx, C.c_void_p(d_ptr)))
+
+
+def kad_memcpy_h2d(ctx, d_dst: int, h_src: np.ndarray):
+    a = np.ascontiguousarray(h_src)
+    _check(lib().kad_memcpy_h2d(ctx, C.c_void_p(d_dst), _p(a), a.nbytes))
+
+
+def kad_memcpy_d2h(ctx, h_dst: np.ndarray, d_src: int):
+    assert h_dst.flags["C_CONTIGUOUS"]
+    _check(lib().kad_memcpy_d2h(ctx, _p(h_dst), C.c_void_p(d_src), h_dst.nbytes))
+
+
+class DeviceArray:
+    """A host array copied into device memory owned by the library (no
+    other HIP runtime involved).  .ptr is the device address."""
+
+    def __init__(self, ctx: "Context", a: np.ndarray):
+        self.ctx = ctx
+        a = np.ascontiguousarray(a)
+        self.shape, self.dtype, self.nbytes = a.shape, a.dtype, a.nbytes
+        self.ptr = kad_device_alloc(ctx.h, a.nbytes)
+        kad_memcpy_h2d(ctx.h, self.ptr, a)
+
+    def numpy(self) -> np.ndarray:
+        out = np.empty(self.shape, dtype=self.dtype)
+        kad_memcpy_d2h(self.ctx.h, out, self.ptr)
+        return out
+
+    def close(self):
+        if self.ptr and self.ctx.h:
+            kad_device_free(self.ctx.h, self.ptr)
+        self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def kad_mlp_create(ctx, params: np.ndarray):

@@ -1,0 +1,159 @@
+"""Learned prior for the delta_L / delta_U allocation.
+
+The paper's calibration phase (Sec. III-A, phase 2) spends a few
+non-adaptive samples to choose the per-vertex failure probabilities; any
+choice whose sum stays below delta is valid and only changes how soon the
+stop rule holds.  Here a small network predicts a betweenness prior from
+three cheap per-vertex features instead, and the same allocation rule
+turns that prior into delta_L = delta_U.  The plain allocation remains the
+fallback (the library uses it whenever the learned one is not finite or
+breaks the budget).
+
+Everything numeric runs in the library's HIP kernels (features, forward,
+backward, Adam); this module only orchestrates: it builds the training set
+from plain runs on seeded graphs, shuffles and uploads batches, and stores
+the weights.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+
+from . import kadabra as K
+
+N_PARAMS = 4481
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "mlp_prior.npz")
+INIT_STREAM = 2   # Philox stream of the initialisation and the shuffles
+
+
+def _rng(seed: int, salt: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(key=[(seed + salt) & (2**64 - 1), INIT_STREAM]))
+
+
+def init_params(seed: int = 7) -> np.ndarray:
+    """Uniform He initialisation (bound sqrt(6 / fan_in)), biases zero,
+    layout W1[64][3], b1[64], W2[64][64], b2[64], W3[64], b3."""
+    r = _rng(seed)
+    p = np.zeros(N_PARAMS, dtype=np.float32)
+    p[0:192] = r.uniform(-1, 1, 192) * math.sqrt(6 / 3)
+    p[256:4352] = r.uniform(-1, 1, 4096) * math.sqrt(6 / 64)
+    p[4416:4480] = r.uniform(-1, 1, 64) * math.sqrt(6 / 64)
+    return p
+
+
+def target_of(btilde: np.ndarray, omega: float) -> np.ndarray:
+    """Regression target ln(b~ + 1/omega); the prior is its inverse,
+    max(0, e^y - 1/omega)."""
+    return np.log(btilde + 1.0 / omega).astype(np.float32)
+
+
+def plain_run(ctx: K.Context, g, eps: float = 0.01, delta: float = 0.1, seed: int = 1):
+    """Plain KADABRA on the GPU; returns (features float32[n][3], b~, omega, result)."""
+    G = K.Graph(ctx, g)
+    S = K.Sampler(G, seed=seed, epsilon=eps, delta=delta)
+    r = S.run_to_stop()
+    b = S.btilde()
+    x = K.kad_features(ctx.h, G.h, g.n)
+    S.close()
+    G.close()
+    return x, b, r.omega, r
+
+
+def build_training_set(ctx: K.Context, graphs, eps: float = 0.01, seed: int = 1, log=None):
+    xs, ys = [], []
+    for g in graphs:
+        x, b, omega, r = plain_run(ctx, g, eps=eps, seed=seed)
+        xs.append(x)
+        ys.append(target_of(b, omega))
+        if log:
+            log(f"{g.name}: n={g.n} tau={r.tau} tau0={r.tau0} time={r.t_total_ms:.1f} ms")
+    return np.concatenate(xs), np.concatenate(ys)
+
+
+def standardize(x: np.ndarray):
+    mean = x.mean(axis=0).astype(np.float32)
+    std = x.std(axis=0).astype(np.float32)
+    std[std == 0] = 1.0
+    return np.concatenate([mean, std]).astype(np.float32)
+
+
+def train(ctx: K.Context, x: np.ndarray, y: np.ndarray, norm: np.ndarray, epochs: int = 8,
+          batch: int = 4096, lr: float = 2e-3, seed: int = 7, log=None):
+    """Adam on mean squared error with the library's forward/backward kernels."""
+    xs = ((x - norm[:3]) / norm[3:]).astype(np.float32)
+    m = K.kad_mlp_create(ctx.h, init_params(seed))
+    losses = []
+    try:
+        for ep in range(epochs):
+            order = _rng(seed, 1 + ep).permutation(len(xs))
+            bx = K.DeviceArray(ctx, xs[order])
+            by = K.DeviceArray(ctx, y[order])
+            tot, cnt = 0.0, 0
+            step_lr = lr * (0.5 ** (ep // 3))
+            for i in range(0, len(xs), batch):
+                rows = min(batch, len(xs) - i)
+                loss = K.kad_mlp_train_step(m, bx.ptr + 12 * i, by.ptr + 4 * i, rows, step_lr)
+                tot += loss * rows
+                cnt += rows
+            bx.close()
+            by.close()
+            losses.append(tot / cnt)
+            if log:
+                log(f"epoch {ep}: mse {losses[-1]:.5f}")
+        params = K.kad_mlp_get_params(m)
+    finally:
+        K.kad_mlp_free(m)
+    return params, losses
+
+
+def save(path: str, params: np.ndarray, norm: np.ndarray, **meta):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, params=params.astype(np.float32), norm=norm.astype(np.float32),
+             **{k: np.asarray(v) for k, v in meta.items()})
+
+
+def load(path: str = DEFAULT_WEIGHTS):
+    z = np.load(path, allow_pickle=False)
+    return z["params"].astype(np.float32), z["norm"].astype(np.float32)
+
+
+def main():
+    import argparse
+    import sys
+    import time
+
+    ROOT = os.path.dirname(HERE)
+    sys.path.insert(0, ROOT)
+    import graphgen as gg
+
+    ap = argparse.ArgumentParser(description="train the learned delta-allocation prior")
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--graphs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--eps", type=float, default=0.01)
+    args = ap.parse_args()
+
+    def log(s):
+        print(s, flush=True)
+
+    t0 = time.time()
+    graphs = gg.training_graphs(args.graphs)
+    log(f"graphs ready in {time.time() - t0:.1f} s")
+    ctx = K.Context(0)
+    x, y = build_training_set(ctx, graphs, eps=args.eps, log=log)
+    norm = standardize(x)
+    log(f"training rows: {len(x)}")
+    t1 = time.time()
+    params, losses = train(ctx, x, y, norm, epochs=args.epochs, log=log)
+    log(f"trained in {time.time() - t1:.1f} s")
+    save(args.out, params, norm, losses=np.array(losses), graph_seeds=np.arange(101, 101 + args.graphs),
+         eps=args.eps, rows=len(x))
+    log(f"saved {args.out}")
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+"""GPU parity of the learned-prior pieces against the FP64 oracle.
+
+Features: FP64 inside, FP32 out (1e-6 relative).  MLP: FP32 kernels
+(MFMA for the 64x64 contractions) against the FP64 oracle network: forward
+within 1e-5 relative, loss and every parameter tensor's gradient within
+1e-4 relative L2, Adam within 1e-4.  The learned allocation: the same
+delta arrays as the oracle's allocation from the oracle's own FP64 prior
+(1e-4 relative on ln(1/delta)), the budget below delta / 2, and the run's
+estimate within eps of exact betweenness.
+"""
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+K = None
+L = None
+SLICES = {"W1": slice(0, 192), "b1": slice(192, 256), "W2": slice(256, 4352),
+          "b2": slice(4352, 4416), "W3": slice(4416, 4480), "b3": slice(4480, 4481)}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    global K, L
+    from paper_1910_11039_amd import kadabra as KK
+    from paper_1910_11039_amd import learned as LL
+    K, L = KK, LL
+    global _ctx
+    c = K.Context(0)
+    _ctx = c
+    yield c
+    c.close()
+
+
+_ctx = None
+
+
+def dev(a):
+    return K.DeviceArray(_ctx, a)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_features_match_oracle(ctx, oracle):
+    g = gg.rmat(12, 16, 3)
+    G = K.Graph(ctx, g)
+    x = K.kad_features(ctx.h, G.h, g.n)
+    xo = oracle.features(g)
+    assert np.allclose(x, xo, rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("rows", [1, 63, 64, 1000, 70000])
+def test_mlp_forward_matches_oracle(ctx, oracle, rows):
+    p = L.init_params(3)
+    p[192:256] = np.random.default_rng(1).normal(0, 0.1, 64)
+    x = np.random.default_rng(rows).normal(size=(rows, 3)).astype(np.float32)
+    m = K.kad_mlp_create(ctx.h, p)
+    try:
+        X = dev(x)
+        y = K.kad_mlp_forward(m, X.ptr, rows)
+    finally:
+        K.kad_mlp_free(m)
+    yo = oracle.mlp_forward(p.astype(np.float64), x.astype(np.float64))
+    assert np.max(np.abs(y - yo)) <= 1e-5 * max(np.max(np.abs(yo)), 1.0)
+
+
+@pytest.mark.parametrize("rows", [64, 777, 20000])
+def test_mlp_loss_and_gradient_match_oracle(ctx, oracle, rows):
+    r = np.random.default_rng(rows)
+    p = L.init_params(5)
+    p[4480] = 0.3
+    x = r.normal(size=(rows, 3)).astype(np.float32)
+    t = r.normal(size=rows).astype(np.float32)
+    m = K.kad_mlp_create(ctx.h, p)
+    try:
+        X, T = dev(x), dev(t)
+        loss, grad = K.kad_mlp_loss_grad(m, X.ptr, T.ptr, rows)
+    finally:
+        K.kad_mlp_free(m)
+    lo, go = oracle.mlp_loss_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
+    for name, sl in SLICES.items():
+        assert rel_l2(grad[sl], go[sl]) <= 1e-4, name
+
+
+def test_adam_steps_match_oracle(ctx, oracle):
+    r = np.random.default_rng(9)
+    rows = 1500
+    p = L.init_params(9)
+    x = r.normal(size=(rows, 3)).astype(np.float32)
+    t = r.normal(size=rows).astype(np.float32)
+    m = K.kad_mlp_create(ctx.h, p)
+    try:
+        X, T = dev(x), dev(t)
+        for _ in range(4):
+            K.kad_mlp_train_step(m, X.ptr, T.ptr, rows, 1e-3)
+        got = K.kad_mlp_get_params(m)
+    finally:
+        K.kad_mlp_free(m)
+    q = p.astype(np.float64)
+    mm = np.zeros(4481)
+    vv = np.zeros(4481)
+    for step in range(1, 5):
+        _, gr = oracle.mlp_loss_grad(q, x.astype(np.float64), t.astype(np.float64))
+        oracle.adam_step(q, gr, mm, vv, step)
+    assert np.max(np.abs(got - q)) <= 1e-4 * max(np.max(np.abs(q)), 1.0)
+
+
+def test_training_reduces_the_loss(ctx):
+    r = np.random.default_rng(3)
+    rows = 32768
+    x = r.normal(size=(rows, 3)).astype(np.float32)
+    t = (np.sin(x[:, 0]) + 0.5 * x[:, 1] * x[:, 2]).astype(np.float32)
+    m = K.kad_mlp_create(ctx.h, L.init_params(4))
+    try:
+        X, T = dev(x), dev(t)
+        first = K.kad_mlp_loss_grad(m, X.ptr, T.ptr, rows)[0]
+        for ep in range(30):
+            for i in range(0, rows, 4096):
+                K.kad_mlp_train_step(m, X.ptr + 12 * i, T.ptr + 4 * i, 4096, 3e-3)
+        last = K.kad_mlp_loss_grad(m, X.ptr, T.ptr, rows)[0]
+    finally:
+        K.kad_mlp_free(m)
+    assert last < 0.1 * first, (first, last)
+
+
+def _oracle_learned_delta(oracle, g, params, norm, omega, delta=0.1):
+    x = oracle.features(g)
+    xs = (x - norm[:3].astype(np.float64)) / norm[3:].astype(np.float64)
+    y = oracle.mlp_forward(params.astype(np.float64), xs)
+    prior = np.maximum(np.exp(y) - 1.0 / omega, 0.0)
+    Cc = oracle.alloc_constant(prior, delta)
+    return oracle.alloc_delta(prior, Cc, delta)
+
+
+def test_learned_allocation_matches_oracle_and_keeps_the_guarantee(ctx, oracle):
+    g = gg.rmat(12, 16, 5)
+    G = K.Graph(ctx, g)
+    xo = oracle.features(g)
+    norm = np.concatenate([xo.mean(0), xo.std(0)]).astype(np.float32)
+    params = L.init_params(11)
+    params[4480] = -6.0            # prior around e^-6 before the ReLU stack's output
+    S = K.Sampler(G, seed=2, epsilon=0.01, delta=0.1, alloc_mode=K.KAD_ALLOC_LEARNED)
+    S.set_mlp_weights(params, norm)
+    r = S.run_to_stop()
+    assert r.tau0 == 0                  # no calibration samples: the learned arm was used
+    LLg, LUg = S.delta_logs()
+    LLo, _ = _oracle_learned_delta(oracle, g, params, norm, r.omega)
+    assert np.allclose(LLg, LLo, rtol=1e-4, atol=0)
+    mp.mp.dps = 40
+    assert mp.fsum(mp.e ** (-mp.mpf(a)) + mp.e ** (-mp.mpf(b)) for a, b in zip(LLg, LUg)) <= mp.mpf(0.1) / 2
+    # (an untrained prior may keep a hub's delta at the floor; then the run
+    # ends at omega, which keeps the guarantee too)
+    assert r.stop_reason in (K.KAD_STOP_COND, K.KAD_STOP_OMEGA)
+    bc = oracle.brandes(g)
+    assert np.abs(S.btilde() - bc).max() <= 0.01
+
+
+def test_learned_allocation_falls_back_to_plain(ctx, oracle):
+    g = gg.rmat(10, 8, 2)
+    G = K.Graph(ctx, g)
+    params = L.init_params(1)
+    params[4480] = np.inf              # non-finite prior -> plain calibration
+    S = K.Sampler(G, seed=1, epsilon=0.02, delta=0.1, alloc_mode=K.KAD_ALLOC_LEARNED)
+    S.set_mlp_weights(params, np.array([0, 0, 0, 1, 1, 1], dtype=np.float32))
+    r = S.run_to_stop()
+    assert r.tau0 == math.ceil(r.omega / 100)
