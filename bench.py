@@ -49,6 +49,23 @@ def algorithmic_bytes(r) -> int:
                + 4 * r["path_vertices"])
 
 
+def counter_traffic(workload: str, epoch_size: int):
+    """HBM bytes per sampler dispatch from the committed rocprofv3 counter
+    profile (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or None when
+    the sampler source has changed since the counters were taken, or the
+    launch configuration differs."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_sample_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    prof = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1910_11039_amd", "csrc", "sampler.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if sha != prof.get("sampler_hip_sha256") or prof.get("epoch_size") != epoch_size:
+        return None
+    return float(prof["traffic_bytes_per_dispatch"])
+
+
 def cpu_baseline(g, seed: int, target_s: float = 12.0):
     """The oracle, as it stands, on the host: first samples of the adaptive
     stream, single thread, grown until about target_s seconds."""
@@ -129,8 +146,10 @@ def main():
         per_launch_bytes = algorithmic_bytes(agg) / agg["sample_launches"]
         per_launch_s = agg["t_sample_kernel_ms"] / 1e3 / agg["sample_launches"]
         achieved = per_launch_bytes / per_launch_s / 1e9
+        traffic = counter_traffic(args.workload, results[0]["epoch_size"])
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": None if traffic is None else round(traffic),
                 "kernel": "k_sample (adaptive-phase launches)",
                 "launch_ms": round(per_launch_s * 1e3, 4),
                 "bytes_per_launch": int(per_launch_bytes)}

@@ -383,6 +383,7 @@ static int sample_pair_given(const orc_graph *g, orc_ws *w, uint64_t seed, uint6
     info->edges = edges;
     info->meet_size = w->nmeet;
     info->side = X;
+    info->visited = (int32_t)(w->loff[0][w->nlayers[0]] + w->loff[1][w->nlayers[1]] + w->nmeet);
     qsort(w->meet, (size_t)w->nmeet, sizeof(int32_t), cmp_i32);
 
     /* Sigma: every expanded layer of both sides, then the meet set. */

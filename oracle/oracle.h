@@ -37,7 +37,7 @@ typedef struct {
     uint64_t sigma_st_int;    /* integer mode: number of shortest s-t paths */
     double sigma_st;          /* FP mode: scaled count; sigma = this * 2^exp */
     int32_t sigma_exp;
-    int32_t pad_;
+    int32_t visited;          /* vertices reached by either side            */
 } orc_sample_info;
 
 typedef struct {

@@ -43,7 +43,7 @@ class SampleInfo(C.Structure):
                 ("side", C.c_int32), ("steps", C.c_int32), ("meet_size", C.c_int32),
                 ("fp_mode", C.c_int32), ("edges", C.c_int64), ("draws", C.c_uint64),
                 ("sigma_st_int", C.c_uint64), ("sigma_st", C.c_double), ("sigma_exp", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("visited", C.c_int32)]
 
 
 class RunOpts(C.Structure):
