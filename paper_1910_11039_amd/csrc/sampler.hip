@@ -192,6 +192,10 @@ template <int BS>
 __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t lo, int32_t hi,
                            LocalStats &ls)
 {
+    // Each lane takes U adjacency entries per iteration (64 apart, so every
+    // load stays coalesced across the wave) and issues their loads
+    // together: U column reads, then U record probes, then the U updates.
+    constexpr int U = 4;
     const int tid = threadIdx.x, lane = tid & 63;
     const int32_t n = c.g.n;
     const uint32_t xbit = (uint32_t)X << X_SHIFT;
@@ -213,60 +217,94 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
         const int64_t off = block_excl_scan<BS>(sm, d, total);
         sm.e.off[tid] = off;
         __syncthreads();
-        for (int64_t e0 = tid & ~63; e0 < total; e0 += BS) {
-            const int64_t e = e0 + lane;
-            bool disc = false, newmeet = false;
-            int32_t w = -1;
-            if (e < total) {
-                int a = 0, b = cnt - 1;
-                while (a < b) {
-                    int mid = (a + b + 1) >> 1;
-                    if (sm.e.off[mid] <= e) a = mid; else b = mid - 1;
+        for (int64_t e0 = (int64_t)(tid >> 6) * 64 * U; e0 < total; e0 += (int64_t)BS * U) {
+            int a[U];
+            int32_t w[U];
+            uint64_t kk[U];
+            uint32_t act = 0, pred = 0, meet = 0, claim = 0;
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int64_t e = e0 + 64 * j + lane;
+                a[j] = 0;
+                w[j] = 0;
+                if (e < total) {
+                    act |= 1u << j;
+                    int lo_i = 0, hi_i = cnt - 1;
+                    while (lo_i < hi_i) {
+                        const int mid = (lo_i + hi_i + 1) >> 1;
+                        if (sm.e.off[mid] <= e) lo_i = mid; else hi_i = mid - 1;
+                    }
+                    a[j] = lo_i;
+                    w[j] = c.g.ci[sm.e.rs[lo_i] + (e - sm.e.off[lo_i])];
                 }
-                w = c.g.ci[sm.e.rs[a] + (e - sm.e.off[a])];
-                Rec *r = c.R + w;
-                const uint64_t kk = ld_key(r);
-                if ((uint32_t)(kk >> 32) == c.cur) {
-                    const uint32_t st = (uint32_t)kk;
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) kk[j] = (act >> j & 1) ? ld_key(c.R + w[j]) : 0ull;
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                if (!(act >> j & 1)) continue;
+                const uint32_t st = (uint32_t)kk[j];
+                if ((uint32_t)(kk[j] >> 32) == c.cur) {
                     if ((st & SIDE_BIT) == xbit) {
-                        if (k >= 1 && (st & DEPTH_MASK) == (uint32_t)(k - 1)) {
-                            const uint64_t v = ld_sig(r);
-                            const unsigned long long old = atomicAdd(&sm.e.acc[a], (unsigned long long)v);
-                            if (old + v < old) sm.ovf = 1;
-                            ls.pred += 1;
-                        }
+                        if (k >= 1 && (st & DEPTH_MASK) == (uint32_t)(k - 1)) pred |= 1u << j;
                     } else {
-                        const uint32_t old = or_state(r, MEET_BIT);
-                        newmeet = !(old & MEET_BIT);
+                        meet |= 1u << j;
                     }
                 } else {
-                    disc = cas_key(r, kk, newkey);
+                    claim |= 1u << j;
                 }
             }
-            const uint64_t dm = __ballot(disc);
-            if (dm) {
-                const int leader = __ffsll((unsigned long long)dm) - 1;
-                int pos = 0;
-                if (lane == leader) pos = atomicAdd(&sm.tail, __popcll(dm));
-                pos = __shfl(pos, leader);
-                if (disc) {
-                    c.Q[qpos(n, X, pos + (int)mbcnt(dm))] = w;
-                    nd += (unsigned long long)(c.g.rp[w + 1] - c.g.rp[w]);
-                    ls.visited += 1;
+            uint64_t sv[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) sv[j] = (pred >> j & 1) ? ld_sig(c.R + w[j]) : 0ull;
+            uint32_t disc = 0, newmeet = 0;
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                if (claim >> j & 1) disc |= (uint32_t)cas_key(c.R + w[j], kk[j], newkey) << j;
+                if (meet >> j & 1) newmeet |= (uint32_t)!(or_state(c.R + w[j], MEET_BIT) & MEET_BIT) << j;
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                if (pred >> j & 1) {
+                    const unsigned long long old = atomicAdd(&sm.e.acc[a[j]], (unsigned long long)sv[j]);
+                    if (old + sv[j] < old) sm.ovf = 1;
+                    ls.pred += 1;
                 }
             }
-            const uint64_t mm = __ballot(newmeet);
-            if (mm) {
-                const int leader = __ffsll((unsigned long long)mm) - 1;
-                int pos = 0;
-                if (lane == leader) pos = atomicAdd(&sm.mcount, __popcll(mm));
-                pos = __shfl(pos, leader);
-                if (newmeet) {
-                    const int mp = pos + (int)mbcnt(mm);
-                    c.MB[mp] = w;
-                    st_sig(c.R + w, (uint64_t)mp);   // meet vertices are never expanded:
-                }                                    // their sigma field holds the list position
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const bool dj = disc >> j & 1;
+                const uint64_t dm = __ballot(dj);
+                if (dm) {
+                    const int leader = __ffsll((unsigned long long)dm) - 1;
+                    int pos = 0;
+                    if (lane == leader) pos = atomicAdd(&sm.tail, __popcll(dm));
+                    pos = __shfl(pos, leader);
+                    if (dj) c.Q[qpos(n, X, pos + (int)mbcnt(dm))] = w[j];
+                }
+                const bool mj = newmeet >> j & 1;
+                const uint64_t mm = __ballot(mj);
+                if (mm) {
+                    const int leader = __ffsll((unsigned long long)mm) - 1;
+                    int pos = 0;
+                    if (lane == leader) pos = atomicAdd(&sm.mcount, __popcll(mm));
+                    pos = __shfl(pos, leader);
+                    if (mj) {
+                        const int mp = pos + (int)mbcnt(mm);
+                        c.MB[mp] = w[j];
+                        st_sig(c.R + w[j], (uint64_t)mp);   // meet vertices are never expanded:
+                    }                                       // their sigma field holds the list position
+                }
             }
+            int64_t dlo[U], dhi[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                dlo[j] = (disc >> j & 1) ? c.g.rp[w[j]] : 0;
+                dhi[j] = (disc >> j & 1) ? c.g.rp[w[j] + 1] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) nd += (unsigned long long)(dhi[j] - dlo[j]);
+            ls.visited += __popc(disc);
         }
         __syncthreads();
         if (k >= 1 && tid < cnt) st_sig(c.R + sm.e.u[tid], sm.e.acc[tid]);
@@ -279,6 +317,9 @@ template <int BS>
 __device__ void expand_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t lo, int32_t hi,
                           LocalStats &ls)
 {
+    // One lane per frontier vertex (so its sum runs in CSR order); the
+    // row is read V entries at a time with all loads of a batch in flight.
+    constexpr int V = 8;
     const int tid = threadIdx.x;
     const int32_t n = c.g.n;
     const uint32_t xbit = (uint32_t)X << X_SHIFT;
@@ -289,26 +330,41 @@ __device__ void expand_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t 
         const int32_t u = c.Q[qpos(n, X, p)];
         double acc = 0.0;
         const int64_t beg = c.g.rp[u], end = c.g.rp[u + 1];
-        for (int64_t e = beg; e < end; ++e) {
-            const int32_t w = c.g.ci[e];
-            Rec *r = c.R + w;
-            const uint64_t kk = ld_key(r);
-            if ((uint32_t)(kk >> 32) == c.cur) {
-                const uint32_t st = (uint32_t)kk;
-                if ((st & SIDE_BIT) == xbit) {
-                    if (k >= 1 && (st & DEPTH_MASK) == (uint32_t)(k - 1)) {
-                        acc = acc + as_f64(ld_sig(r));
-                        ls.pred += 1;
+        for (int64_t e0 = beg; e0 < end; e0 += V) {
+            const int m = (int)min<int64_t>(V, end - e0);
+            int32_t w[V];
+            uint64_t kk[V];
+#pragma unroll
+            for (int j = 0; j < V; ++j) w[j] = j < m ? c.g.ci[e0 + j] : 0;
+#pragma unroll
+            for (int j = 0; j < V; ++j) kk[j] = j < m ? ld_key(c.R + w[j]) : 0ull;
+            uint32_t pred = 0;
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                if (j >= m) continue;
+                if ((uint32_t)(kk[j] >> 32) == c.cur) {
+                    const uint32_t st = (uint32_t)kk[j];
+                    if ((st & SIDE_BIT) == xbit) {
+                        if (k >= 1 && (st & DEPTH_MASK) == (uint32_t)(k - 1)) pred |= 1u << j;
+                    } else {
+                        const uint32_t old = or_state(c.R + w[j], MEET_BIT);
+                        if (!(old & MEET_BIT)) c.MB[atomicAdd(&sm.mcount, 1)] = w[j];
                     }
-                } else {
-                    const uint32_t old = or_state(r, MEET_BIT);
-                    if (!(old & MEET_BIT)) c.MB[atomicAdd(&sm.mcount, 1)] = w;
+                } else if (cas_key(c.R + w[j], kk[j], newkey)) {
+                    c.Q[qpos(n, X, atomicAdd(&sm.tail, 1))] = w[j];
+                    nd += (unsigned long long)(c.g.rp[w[j] + 1] - c.g.rp[w[j]]);
+                    ls.visited += 1;
                 }
-            } else if (cas_key(r, kk, newkey)) {
-                c.Q[qpos(n, X, atomicAdd(&sm.tail, 1))] = w;
-                nd += (unsigned long long)(c.g.rp[w + 1] - c.g.rp[w]);
-                ls.visited += 1;
             }
+            double sv[V];
+#pragma unroll
+            for (int j = 0; j < V; ++j) sv[j] = (pred >> j & 1) ? as_f64(ld_sig(c.R + w[j])) : 0.0;
+#pragma unroll
+            for (int j = 0; j < V; ++j)
+                if (pred >> j & 1) {       // CSR order within and across batches
+                    acc = acc + sv[j];
+                    ls.pred += 1;
+                }
         }
         if (k >= 1) {
             st_sig(c.R + u, as_u64(acc));
