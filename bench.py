@@ -94,6 +94,7 @@ def main():
     ap.add_argument("--epoch-size", type=int, default=0)
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-allocation arm")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain device copy of known size (counter calibration) and exit")
     args = ap.parse_args()
@@ -154,6 +155,36 @@ def main():
                 "launch_ms": round(per_launch_s * 1e3, 4),
                 "bytes_per_launch": int(per_launch_bytes)}
 
+    learned = None
+    if not args.no_learned:
+        # the same runs with the learned delta allocation (committed network)
+        from paper_1910_11039_amd import learned as LRN
+        params, norm = LRN.load()
+        SL = K.Sampler(G, seed=1, epsilon=eps, delta=0.1, alloc_mode=K.KAD_ALLOC_LEARNED,
+                       timing=0 if args.use_graphs else 1, use_graphs=args.use_graphs,
+                       epoch_size=args.epoch_size, slots=args.slots, block_size=args.block)
+        SL.set_mlp_weights(params, norm)
+        for i in range(args.warmup):
+            SL.reset(1000 + i)
+            SL.run_to_stop()
+        lres = []
+        tl0 = time.perf_counter()
+        for i in range(args.steps):
+            SL.reset(1 + i)
+            lres.append(SL.run_to_stop().as_dict())
+        lwall = time.perf_counter() - tl0
+        SL.close()
+        plain_ms = wall * 1e3 / args.steps
+        l_ms = lwall * 1e3 / args.steps
+        learned = {"time_to_stop_ms": round(l_ms, 3),
+                   "samples_per_run": float(np.mean([r["tau0"] + r["tau"] for r in lres])),
+                   "alloc_ms": round(float(np.mean([r["t_alloc_ms"] for r in lres])), 3),
+                   "fell_back_to_plain": int(sum(r["tau0"] > 0 for r in lres)),
+                   "plain_time_to_stop_ms": round(plain_ms, 3),
+                   "plain_samples_per_run": float(np.mean([r["tau0"] + r["tau"] for r in results])),
+                   "time_ratio_learned_over_plain": round(l_ms / plain_ms, 4)}
+        print(f"# learned arm: {l_ms:.1f} ms per run vs plain {plain_ms:.1f} ms", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         n_s, t = cpu_baseline(g, 1, args.cpu_seconds)
@@ -177,13 +208,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{wname}: {desc}, n={g.n}, m={g.m}", "epsilon": eps, "delta": 0.1,
                    "delta_alloc": "plain (calibration samples)", "epoch_size": r0["epoch_size"],
-                   "slots": r0["slots"], "omega": r0["omega"], "vd_bracket": [r0["vd_lo"], r0["vd_hi"]]},
+                   "slots": r0["slots"], "block_size": r0["block_size"], "pools": r0["pools"],
+                   "omega": r0["omega"], "vd_bracket": [r0["vd_lo"], r0["vd_hi"]]},
         "time_to_stop_ms": round(float(np.mean([r["t_total_ms"] for r in results])), 3),
         "adaptive_samples_per_run": float(np.mean([r["tau"] for r in results])),
         "calibration_samples_per_run": float(np.mean([r["tau0"] for r in results])),
         "edges_scanned_per_s": round(agg["edges_scanned"] / wall, 1),
         "phase_ms": {k: round(float(np.mean([r[k] for r in results])), 3)
                      for k in ("t_omega_ms", "t_alloc_ms", "t_ads_ms")},
+        "learned_alloc": learned,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -161,10 +161,74 @@ def rmat_edges(scale: int, edge_factor: int, seed: int,
     return np.concatenate(us), np.concatenate(vs)
 
 
-def rmat(scale: int, edge_factor: int, seed: int) -> CSRGraph:
+def rmat_numpy(scale: int, edge_factor: int, seed: int) -> CSRGraph:
     """R-MAT (Graph500 a,b,c,d), symmetrised, deduplicated, largest component."""
     u, v = rmat_edges(scale, edge_factor, seed)
     return relabel_and_lcc(1 << scale, u, v, seed, f"rmat_{scale}_{edge_factor}_s{seed}")
+
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_NATIVE = os.path.join(_HERE, "librmatgen.so")
+
+
+def build_native(force: bool = True) -> str:
+    """Compile rmatgen.c (the threaded R-MAT builder) with gcc."""
+    import subprocess
+    if force or not os.path.exists(_NATIVE):
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math",
+                               "-pthread", "-shared", "-fPIC", "-o", _NATIVE,
+                               os.path.join(_HERE, "rmatgen.c")])
+    return _NATIVE
+
+
+def _native_lib():
+    import ctypes
+    if not os.path.exists(_NATIVE):
+        return None
+    lib = ctypes.CDLL(_NATIVE)
+    lib.kg_rmat.restype = ctypes.c_void_p
+    lib.kg_rmat.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double,
+                            ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_int]
+    lib.kg_n.restype = ctypes.c_int32
+    lib.kg_n.argtypes = [ctypes.c_void_p]
+    lib.kg_nnz.restype = ctypes.c_int64
+    lib.kg_nnz.argtypes = [ctypes.c_void_p]
+    lib.kg_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.kg_free.argtypes = [ctypes.c_void_p]
+    return lib
+
+
+def rmat_native(scale: int, edge_factor: int, seed: int, threads: int = 0) -> CSRGraph:
+    """The same graph as rmat_numpy, built by the threaded C builder."""
+    lib = _native_lib()
+    if lib is None:
+        raise RuntimeError("librmatgen.so is not built (graphgen.build_native())")
+    n = 1 << scale
+    perm = np.ascontiguousarray(_rng(seed ^ 0x5EED).permutation(n).astype(np.int64))
+    if threads <= 0:
+        threads = max(1, min(16, os.cpu_count() or 1))
+    h = lib.kg_rmat(scale, edge_factor, seed & (2**64 - 1), GEN_STREAM, 0.57, 0.19, 0.19,
+                    perm.ctypes.data, threads)
+    if not h:
+        raise MemoryError("R-MAT builder failed")
+    try:
+        nn = lib.kg_n(h)
+        nnz = lib.kg_nnz(h)
+        rp = np.empty(nn + 1, dtype=np.int64)
+        ci = np.empty(nnz, dtype=np.int32)
+        lib.kg_copy(h, rp.ctypes.data, ci.ctypes.data)
+    finally:
+        lib.kg_free(h)
+    return CSRGraph(nn, rp, ci, f"rmat_{scale}_{edge_factor}_s{seed}")
+
+
+def rmat(scale: int, edge_factor: int, seed: int) -> CSRGraph:
+    """R-MAT (Graph500 a,b,c,d), symmetrised, deduplicated, largest component
+    (the threaded builder when it is built, else numpy; both give the same
+    graph)."""
+    if _native_lib() is not None:
+        return rmat_native(scale, edge_factor, seed)
+    return rmat_numpy(scale, edge_factor, seed)
 
 
 def road_grid(side: int, seed: int, p_drop: float = 0.05, shortcut_frac: float = 0.001,
@@ -269,6 +333,8 @@ WORKLOADS = {
                  "2048x2048 grid, 5% edges removed, 0.1% shortcuts of offset <= 8"),
     "rmat22": (rmat, dict(scale=22, edge_factor=16, seed=1022),
                "R-MAT scale 22, edge factor 16 (held-out graph for the learned prior)"),
+    "rmat26": (rmat, dict(scale=26, edge_factor=16, seed=26),
+               "R-MAT scale 26, edge factor 16 (about 1e9 undirected edges)"),
 }
 
 

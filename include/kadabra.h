@@ -57,8 +57,9 @@ typedef struct kad_ctx kad_ctx;
 typedef struct kad_graph kad_graph;
 typedef struct kad_sampler kad_sampler;
 
-/* Random-number streams: the Philox key is (seed, stream). */
-enum { KAD_STREAM_ADS = 0, KAD_STREAM_CALIB = 1 };
+/* Random-number streams: the Philox key is (seed, stream).  Stream 5 is
+ * used by the autotuner's trial samples, whose counts are discarded. */
+enum { KAD_STREAM_ADS = 0, KAD_STREAM_CALIB = 1, KAD_STREAM_TUNE = 5 };
 
 /* Allocation of the per-vertex failure probabilities delta_L, delta_U. */
 enum {
@@ -97,7 +98,8 @@ typedef struct {
     uint64_t seed;                /* Philox seed                                  */
     double epsilon;               /* additive error bound, Sec. I                 */
     double delta;                 /* failure probability, Sec. I                  */
-    uint32_t epoch_size;          /* samples per epoch; 0 = autotune              */
+    uint32_t epoch_size;          /* samples per epoch; 0 = autotune (four rounds */
+                                  /* of the slot wave, within [256, 16384])       */
     int32_t alloc_mode;           /* KAD_ALLOC_*                                  */
     double omega_override;        /* > 0: use this omega instead of computing it  */
     int32_t sigma_mode;           /* KAD_SIGMA_*                                  */
@@ -106,7 +108,8 @@ typedef struct {
     int32_t epochs_in_flight;     /* epochs queued ahead of the stop check; 0=auto */
     int32_t use_graphs;           /* 1: replay epochs from a captured hipGraph    */
     int32_t block_size;           /* threads per sampling workgroup (64, 128,     */
-                                  /* 256, 512); 0 = auto                          */
+                                  /* 256, 512, 1024); 0 = autotune over 256, 512, */
+                                  /* 1024 by a timed trial at kad_sampler_init    */
     int32_t timing;               /* 1: time every sampler launch with HIP events */
 } kad_opts;
 
@@ -132,6 +135,8 @@ typedef struct {
     int32_t slots;                /* concurrent samples actually used             */
     int64_t samples_run;          /* samples the kernels finished, speculative    */
                                   /* ones after the stop epoch included           */
+    int32_t block_size;           /* workgroup size used by the sampler           */
+    int32_t pools;                /* slot pools (epochs overlapped across them)   */
 } kad_result;
 
 /* kad_sampler_init: allocate the sampler state for graph g and options o.

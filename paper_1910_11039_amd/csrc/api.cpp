@@ -100,6 +100,8 @@ struct kad_sampler {
     uint32_t launches;
     hipGraphExec_t gexec;
     bool have_graph;
+    bool tune_block;
+    double tune_rate[3];     // samples/s of the trial per candidate block size
 };
 
 extern "C" const char *kad_last_error(void) { return g_err.c_str(); }
@@ -279,6 +281,62 @@ static kad_status reset_epochs(kad_sampler *s)
     return KAD_OK;
 }
 
+static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, uint64_t count,
+                             uint32_t *target, int32_t *paths, int64_t *info, int32_t max_len);
+
+// Autotuner (samples per epoch and workgroup shape).  Workgroup size:
+// each candidate (256, 512, 1024 threads, each with one full wave of
+// slots) samples the same trial -- four rounds of the widest wave -- on
+// the tuning stream (counts discarded), timed with HIP events; the fastest
+// wins.  Fewer, wider workgroups trade parallelism inside a sample for a
+// smaller combined visited-state footprint, and the balance depends on the
+// graph.  Epoch size: four rounds of the chosen wave, rounded to 256 and
+// kept in [256, 16384]: long enough that an epoch's tail, overlapped with
+// the following epochs, costs little, short enough that the stop
+// overshoots tau by a few percent.
+static kad_status autotune(kad_sampler *s)
+{
+    hipStream_t st = s->ctx->stream;
+    if (s->tune_block) {
+        const int cands[3] = {256, 512, 1024};
+        double best = -1.0;
+        int best_b = 256, best_slots = s->slots;
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        const int all_slots = s->slots;
+        const uint64_t N = 4ull * (uint64_t)all_slots;
+        for (int i = 0; i < 3; ++i) {
+            const int b = cands[i];
+            const int sl = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(b));
+            s->block = b;
+            s->slots = sl;
+            HIPCHK(hipMemsetAsync(s->scratch_counts, 0, 4ull * s->g->n, st));
+            HIPCHK(hipEventRecord(e0, st));
+            kad_status r = count_into(s, KAD_STREAM_TUNE, 0, N, s->scratch_counts, nullptr, nullptr, 0);
+            if (r != KAD_OK) return r;
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            const double rate = (double)N / (ms * 1e-3);
+            s->tune_rate[i] = rate;
+            if (rate > best) { best = rate; best_b = b; best_slots = sl; }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        s->block = best_b;
+        s->slots = best_slots;
+        HIPCHK(hipMemsetAsync(s->stats, 0, sizeof(SampleStats), st));
+    }
+    if (s->E == 0) {
+        uint64_t E = 4ull * (uint64_t)s->slots;
+        E = (E + 255) / 256 * 256;
+        s->E = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(E, 256), 16384);
+    }
+    return KAD_OK;
+}
+
 extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const kad_opts *o,
                                        kad_sampler **out)
 {
@@ -288,8 +346,8 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     if (o->alloc_mode < 0 || o->alloc_mode > 2) return fail(KAD_EINVAL, "bad alloc_mode");
     if (o->sigma_mode < 0 || o->sigma_mode > 1) return fail(KAD_EINVAL, "bad sigma_mode");
     const int block = o->block_size ? o->block_size : 256;
-    if (block != 64 && block != 128 && block != 256 && block != 512)
-        return fail(KAD_EINVAL, "block_size must be 64, 128, 256 or 512");
+    if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
+        return fail(KAD_EINVAL, "block_size must be 64, 128, 256, 512 or 1024");
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     kad_sampler *s = new kad_sampler();
@@ -315,26 +373,42 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     s->cap = (unsigned long long)ceil(s->omega);
 
     // Slots: as many concurrent samples as fit the visited-state budget.
+    // Persistent workgroups: more slots than can be resident would only
+    // start once resident ones exit, so the default is one full wave of
+    // them.  With block_size = 0 the pools are sized for the largest wave
+    // among the candidate block sizes and the autotuner picks one below.
     const size_t per_slot = (size_t)n * (sizeof(Rec) + 2 * sizeof(int32_t)) +
                             16ull * (size_t)std::min<int64_t>(n, 1 << 16);
     size_t free_b = 0, total_b = 0;
     HIPCHK(hipMemGetInfo(&free_b, &total_b));
     size_t budget = o->visited_budget_bytes ? (size_t)o->visited_budget_bytes : free_b / 4 * 3;
-    // Persistent workgroups: more slots than can be resident would only
-    // start once resident ones exit, so the default is one full wave of them.
-    int want = o->slots > 0 ? o->slots : ctx->cu_count * sampler_blocks_per_cu(block);
-    // pools: up to 4 while a full wave of slots fits each, at least 2
-    s->slots = std::max(1, std::min(want, (int)std::min<size_t>(budget / (2 * per_slot), 1 << 16)));
-    s->P = (int)std::max<size_t>(2, std::min<size_t>(4, budget / ((size_t)s->slots * per_slot)));
+    s->tune_block = o->block_size == 0;
+    int want = 0;
+    if (o->slots > 0) {
+        want = o->slots;
+    } else if (!s->tune_block) {
+        want = ctx->cu_count * sampler_blocks_per_cu(block);
+    } else {
+        for (int b : {256, 512, 1024}) want = std::max(want, ctx->cu_count * sampler_blocks_per_cu(b));
+    }
+    const size_t fit = budget / per_slot;
+    if (fit < 1) {
+        delete s;
+        return fail(KAD_ENOMEM, "not even one sample slot fits the visited-state budget");
+    }
+    // pools: up to 4 while a full wave of slots fits each (epochs overlap
+    // across pools); a single pool when memory is tight
+    s->slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)want, std::min<size_t>(fit, 1 << 16)));
+    s->P = (int)std::max<size_t>(1, std::min<size_t>(4, fit / (size_t)s->slots));
     if (o->slots > 0 && s->slots < o->slots) {
         delete s;
         return fail(KAD_ENOMEM, "requested slots exceed the visited-state budget");
     }
-    if (o->epoch_size) s->E = o->epoch_size;
-    else s->E = (uint32_t)std::min<unsigned long long>(std::max<unsigned long long>(4ull * s->slots, 1024ull), 16384ull);
+    s->E = o->epoch_size;
     s->inflight = o->epochs_in_flight > 0 ? o->epochs_in_flight : 4;
     s->macc_cap = (int32_t)std::min<int64_t>(n, 1 << 16);   // larger meet sets take the slow path
-    s->hist_cap = (int32_t)((s->cap + s->E - 1) / s->E + 2);
+    // the history is sized for the smallest epoch the autotuner may choose
+    s->hist_cap = (int32_t)((s->cap + (s->E ? s->E : 256) - 1) / (s->E ? s->E : 256) + 2);
 
     auto alloc = [&](void **p, size_t bytes) {
         return hipMalloc(p, std::max<size_t>(bytes, 16)) == hipSuccess;
@@ -368,7 +442,9 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     for (auto &e : s->ev_ring) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCHK(hipMemsetAsync(s->recs, 0, sizeof(Rec) * (size_t)n * s->P * s->slots, st));
     HIPCHK(hipMemsetAsync(s->stamps, 0, 4ull * s->P * s->slots, st));
-    kad_status rs = reset_epochs(s);
+    kad_status rs = autotune(s);
+    if (rs != KAD_OK) { free_sampler(s); return rs; }
+    rs = reset_epochs(s);
     if (rs != KAD_OK) { free_sampler(s); return rs; }
     HIPCHK(hipStreamSynchronize(st));
     s->res.omega = s->omega;
@@ -688,6 +764,8 @@ static kad_status fill_result(kad_sampler *s)
     r.sample_launches = s->launches;
     r.epoch_size = s->E;
     r.slots = s->slots;
+    r.block_size = s->block;
+    r.pools = s->P;
     return KAD_OK;
 }
 

@@ -17,6 +17,8 @@
 // contraction, in the order written.
 #include <math.h>
 
+#include <algorithm>
+
 #include "kad_internal.h"
 #include "philox.h"
 
@@ -273,34 +275,6 @@ __global__ void k_bfs_init(int32_t n, int32_t *dist, int32_t src, int32_t *fr, i
     }
 }
 
-// One BFS level: a wave per frontier vertex, lanes stride its adjacency.
-// sizes = {cur, next, depth}; an empty frontier makes the launch a no-op.
-__global__ void k_bfs_level(DevGraph g, int32_t *dist, const int32_t *fr, int32_t *nf, int32_t *sizes)
-{
-    const int32_t cur = sizes[0];
-    const int32_t depth = sizes[2];
-    const int lane = threadIdx.x & 63;
-    const int32_t wpb = blockDim.x >> 6;
-    for (int32_t i = blockIdx.x * wpb + (threadIdx.x >> 6); i < cur; i += gridDim.x * wpb) {
-        const int32_t u = fr[i];
-        for (int64_t e = g.rp[u] + lane; e < g.rp[u + 1]; e += 64) {
-            const int32_t w = g.ci[e];
-            if (atomicCAS(&dist[w], -1, depth + 1) == -1) nf[atomicAdd(&sizes[1], 1)] = w;
-        }
-    }
-}
-
-__global__ void k_bfs_swap(int32_t *sizes, int32_t *last_depth)
-{
-    if (sizes[0] == 0) return;
-    if (sizes[1] > 0) {
-        sizes[2] += 1;
-        *last_depth = sizes[2];
-    }
-    sizes[0] = sizes[1];
-    sizes[1] = 0;
-}
-
 __global__ void k_min_at_depth(int32_t n, const int32_t *dist, int32_t depth, int32_t *out)
 {
     int32_t b = 0x7fffffff;
@@ -314,6 +288,212 @@ __global__ void k_min_at_depth(int32_t n, const int32_t *dist, int32_t depth, in
         hipError_t ck_ = (expr);                \
         if (ck_ != hipSuccess) return ck_;      \
     } while (0)
+
+// Direction-optimising BFS for the bracket's sweeps, driven on the device:
+// the host enqueues steps without waiting, and every kernel of a step reads
+// the frontier's state from sz and does nothing when the step is not its
+// case.  The frontier at depth k is listed in buf[k & 1] (when listed) and
+// always marked in dist.
+//   sz[0] frontier size      sz[1] next size        sz[2] frontier depth
+//   sz[3] last nonempty depth sz[4] collect cursor  sz[5..6] frontier degree sum
+//   sz[7] heavy rows         sz[8..9] next degree sum  sz[10] listed
+constexpr int32_t SMALL_V = 4096;         // single-workgroup levels: frontier size and
+constexpr int64_t SMALL_D = 16384;        // degree sum at most these
+constexpr int64_t HEAVY = 4096;           // top-down rows longer than this are split
+constexpr int SMALL_LONG = 2048;          // > SMALL_D / 33 rows longer than 32
+
+__device__ __forceinline__ int64_t sz_get64(const int32_t *sz, int i)
+{
+    return ((int64_t)sz[i + 1] << 32) | (uint32_t)sz[i];
+}
+
+__device__ __forceinline__ bool bfs_bottom_up(int32_t fsize, int32_t big_v) { return fsize >= big_v; }
+
+// Small frontiers, many levels in one launch: one workgroup, a thread per
+// frontier vertex for rows of up to 32 entries, a wave per longer row.
+__global__ __launch_bounds__(1024) void k_bfs_small(DevGraph g, int32_t *dist, int32_t *buf0, int32_t *buf1,
+                                                    int32_t *sz)
+{
+    __shared__ int32_t s_next, s_nlong;
+    __shared__ unsigned long long s_deg;
+    __shared__ int32_t s_long[SMALL_LONG];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+    int32_t fsize = sz[0], depth = sz[2], last = sz[3];
+    int64_t fdeg = sz_get64(sz, 5);
+    if (fsize == 0 || sz[10] == 0 || fsize > SMALL_V || fdeg > SMALL_D) return;
+    while (fsize > 0 && fsize <= SMALL_V && fdeg <= SMALL_D) {
+        const int32_t *cur = (depth & 1) ? buf1 : buf0;
+        int32_t *nxt = (depth & 1) ? buf0 : buf1;
+        if (tid == 0) {
+            s_next = 0;
+            s_nlong = 0;
+            s_deg = 0;
+        }
+        __syncthreads();
+        unsigned long long dsum = 0;
+        for (int32_t i = tid; i < fsize; i += blockDim.x) {
+            const int32_t u = cur[i];
+            const int64_t b = g.rp[u], e1 = g.rp[u + 1];
+            if (e1 - b > 32) {
+                const int32_t slot = atomicAdd(&s_nlong, 1);
+                if (slot < SMALL_LONG) {
+                    s_long[slot] = u;
+                    continue;
+                }
+            }
+            for (int64_t e = b; e < e1; ++e) {
+                const int32_t w = g.ci[e];
+                if (atomicCAS(&dist[w], -1, depth + 1) == -1) {
+                    nxt[atomicAdd(&s_next, 1)] = w;
+                    dsum += (unsigned long long)(g.rp[w + 1] - g.rp[w]);
+                }
+            }
+        }
+        __syncthreads();
+        const int32_t nl = min(s_nlong, SMALL_LONG);
+        for (int32_t j = wid; j < nl; j += nw) {
+            const int32_t u = s_long[j];
+            for (int64_t e = g.rp[u] + lane; e < g.rp[u + 1]; e += 64) {
+                const int32_t w = g.ci[e];
+                if (atomicCAS(&dist[w], -1, depth + 1) == -1) {
+                    nxt[atomicAdd(&s_next, 1)] = w;
+                    dsum += (unsigned long long)(g.rp[w + 1] - g.rp[w]);
+                }
+            }
+        }
+        if (dsum) atomicAdd(&s_deg, dsum);
+        __syncthreads();
+        fsize = s_next;
+        fdeg = (int64_t)s_deg;
+        depth += 1;
+        if (fsize > 0) last = depth;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        sz[0] = fsize;
+        sz[1] = 0;
+        sz[2] = depth;
+        sz[3] = last;
+        sz[5] = (int32_t)(uint32_t)(fdeg & 0xffffffff);
+        sz[6] = (int32_t)(fdeg >> 32);
+        sz[10] = 1;
+    }
+}
+
+// List the frontier from dist when the previous level was bottom-up.
+__global__ void k_bfs_collect(int32_t n, const int32_t *dist, int32_t *buf0, int32_t *buf1, int32_t *sz,
+                              int32_t big_v)
+{
+    const int32_t fsize = sz[0], depth = sz[2];
+    if (fsize == 0 || sz[10] != 0 || bfs_bottom_up(fsize, big_v)) return;
+    int32_t *cur = (depth & 1) ? buf1 : buf0;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (dist[v] == depth) cur[atomicAdd(&sz[4], 1)] = v;
+}
+
+// One top-down level: a wave per frontier vertex; rows longer than HEAVY
+// are listed for k_bfs_heavy.
+__global__ void k_bfs_td(DevGraph g, int32_t *dist, int32_t *buf0, int32_t *buf1, int32_t *heavy, int32_t *sz,
+                         int32_t big_v)
+{
+    const int32_t fsize = sz[0], depth = sz[2];
+    if (fsize == 0 || bfs_bottom_up(fsize, big_v)) return;
+    const int32_t *cur = (depth & 1) ? buf1 : buf0;
+    int32_t *nxt = (depth & 1) ? buf0 : buf1;
+    const int lane = threadIdx.x & 63;
+    const int32_t wpb = blockDim.x >> 6;
+    unsigned long long dsum = 0;
+    for (int32_t i = blockIdx.x * wpb + (threadIdx.x >> 6); i < fsize; i += gridDim.x * wpb) {
+        const int32_t u = cur[i];
+        const int64_t b = g.rp[u], e1 = g.rp[u + 1];
+        if (e1 - b > HEAVY) {
+            if (lane == 0) heavy[atomicAdd(&sz[7], 1)] = u;
+            continue;
+        }
+        for (int64_t e = b + lane; e < e1; e += 64) {
+            const int32_t w = g.ci[e];
+            if (atomicCAS(&dist[w], -1, depth + 1) == -1) {
+                nxt[atomicAdd(&sz[1], 1)] = w;
+                dsum += (unsigned long long)(g.rp[w + 1] - g.rp[w]);
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o);
+    if (lane == 0 && dsum) atomicAdd((unsigned long long *)&sz[8], dsum);
+}
+
+// The heavy rows of a top-down level, split across every workgroup.
+__global__ void k_bfs_heavy(DevGraph g, int32_t *dist, const int32_t *heavy, int32_t *buf0, int32_t *buf1,
+                            int32_t *sz, int32_t big_v)
+{
+    const int32_t fsize = sz[0], depth = sz[2], nh = sz[7];
+    if (fsize == 0 || bfs_bottom_up(fsize, big_v) || nh == 0) return;
+    int32_t *nxt = (depth & 1) ? buf0 : buf1;
+    unsigned long long dsum = 0;
+    for (int32_t h = 0; h < nh; ++h) {
+        const int32_t u = heavy[h];
+        const int64_t b = g.rp[u], e1 = g.rp[u + 1];
+        for (int64_t e = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1;
+             e += (int64_t)gridDim.x * blockDim.x) {
+            const int32_t w = g.ci[e];
+            if (atomicCAS(&dist[w], -1, depth + 1) == -1) {
+                nxt[atomicAdd(&sz[1], 1)] = w;
+                dsum += (unsigned long long)(g.rp[w + 1] - g.rp[w]);
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o);
+    if ((threadIdx.x & 63) == 0 && dsum) atomicAdd((unsigned long long *)&sz[8], dsum);
+}
+
+// One bottom-up level: every unreached vertex looks for a neighbour at the
+// frontier's depth and stops at the first one.  Leaves no list.
+__global__ void k_bfs_bu(DevGraph g, int32_t *dist, int32_t *sz, int32_t big_v)
+{
+    const int32_t fsize = sz[0], depth = sz[2];
+    if (fsize == 0 || !bfs_bottom_up(fsize, big_v)) return;
+    int cnt = 0;
+    unsigned long long dsum = 0;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
+        if (dist[v] != -1) continue;
+        const int64_t b = g.rp[v], e1 = g.rp[v + 1];
+        for (int64_t e = b; e < e1; ++e) {
+            if (dist[g.ci[e]] == depth) {
+                dist[v] = depth + 1;
+                cnt += 1;
+                dsum += (unsigned long long)(e1 - b);
+                break;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        cnt += __shfl_xor(cnt, o);
+        dsum += __shfl_xor(dsum, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (cnt) atomicAdd(&sz[1], cnt);
+        if (dsum) atomicAdd((unsigned long long *)&sz[8], dsum);
+    }
+}
+
+// Close a level: the next frontier becomes the current one.
+__global__ void k_bfs_advance(int32_t *sz, int32_t big_v)
+{
+    const int32_t fsize = sz[0];
+    if (fsize == 0) return;
+    const int32_t nsize = sz[1];
+    sz[10] = bfs_bottom_up(fsize, big_v) ? 0 : 1;   // top-down listed the next frontier
+    sz[0] = nsize;
+    sz[1] = 0;
+    sz[2] += 1;
+    if (nsize > 0) sz[3] = sz[2];
+    sz[4] = 0;
+    sz[5] = sz[8];
+    sz[6] = sz[9];
+    sz[7] = 0;
+    sz[8] = 0;
+    sz[9] = 0;
+}
 
 int grid_for(int64_t n, int block, int cap = 8192)
 {
@@ -415,8 +595,10 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
     unsigned long long *best = nullptr;
     if ((e = hipMallocAsync((void **)&dist, sizeof(int32_t) * n, st)) != hipSuccess) return e;
     if ((e = hipMallocAsync((void **)&fa, sizeof(int32_t) * n, st)) != hipSuccess) return e;
-    if ((e = hipMallocAsync((void **)&fb, sizeof(int32_t) * n, st)) != hipSuccess) return e;
-    if ((e = hipMallocAsync((void **)&sizes, sizeof(int32_t) * 8, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&fb, sizeof(int32_t) * (size_t)n, st)) != hipSuccess) return e;
+    int32_t *heavy = nullptr;
+    if ((e = hipMallocAsync((void **)&heavy, sizeof(int32_t) * (size_t)n, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&sizes, sizeof(int32_t) * 12, st)) != hipSuccess) return e;
     if ((e = hipMallocAsync((void **)&best, sizeof(unsigned long long), st)) != hipSuccess) return e;
     CK(hipMemsetAsync(best, 0, sizeof(unsigned long long), st));
     hipLaunchKernelGGL(k_argmax_degree, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, g, best);
@@ -425,22 +607,37 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     const int32_t r = (int32_t)(0xFFFFFFFFull - (hb & 0xFFFFFFFFull));
 
+    // Direction-optimising BFS enqueued in batches of steps; the host only
+    // looks at the frontier size between batches.
+    const int32_t big_v = std::max<int32_t>(n / 16, 1 << 14);
     auto bfs = [&](int32_t src, int32_t *ecc, int32_t *far) -> hipError_t {
         hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, 256)), dim3(256), 0, st, n, dist, src, fa, sizes);
-        hipMemsetAsync(sizes + 3, 0, sizeof(int32_t), st);   // last nonempty depth
-        int32_t *cur = fa, *nxt = fb;
-        for (;;) {
-            for (int i = 0; i < 32; ++i) {
-                hipLaunchKernelGGL(k_bfs_level, dim3(1024), dim3(256), 0, st, g, dist, cur, nxt, sizes);
-                hipLaunchKernelGGL(k_bfs_swap, dim3(1), dim3(1), 0, st, sizes, sizes + 3);
-                int32_t *tmp = cur; cur = nxt; nxt = tmp;
+        int64_t rp2[2];
+        CK(hipMemcpyAsync(rp2, g.rp + src, sizeof(rp2), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        const int64_t d0 = rp2[1] - rp2[0];
+        int32_t hs[12] = {0};
+        hs[0] = 1;
+        hs[5] = (int32_t)(uint32_t)(d0 & 0xffffffff);
+        hs[6] = (int32_t)(d0 >> 32);
+        hs[10] = 1;
+        CK(hipMemcpyAsync(sizes, hs, sizeof(hs), hipMemcpyHostToDevice, st));
+        for (int64_t steps = 0; steps <= (int64_t)n + 1; steps += 8) {
+            for (int k = 0; k < 8; ++k) {
+                hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(1024), 0, st, g, dist, fa, fb, sizes);
+                hipLaunchKernelGGL(k_bfs_collect, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, dist, fa, fb,
+                                   sizes, big_v);
+                hipLaunchKernelGGL(k_bfs_td, dim3(2048), dim3(256), 0, st, g, dist, fa, fb, heavy, sizes, big_v);
+                hipLaunchKernelGGL(k_bfs_heavy, dim3(1024), dim3(256), 0, st, g, dist, heavy, fa, fb, sizes, big_v);
+                hipLaunchKernelGGL(k_bfs_bu, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, g, dist, sizes, big_v);
+                hipLaunchKernelGGL(k_bfs_advance, dim3(1), dim3(1), 0, st, sizes, big_v);
             }
-            int32_t hs[4];
             CK(hipMemcpyAsync(hs, sizes, sizeof(hs), hipMemcpyDeviceToHost, st));
-            hipError_t ee = hipStreamSynchronize(st);
-            if (ee != hipSuccess) return ee;
-            if (hs[0] == 0) { *ecc = hs[3]; break; }
+            CK(hipStreamSynchronize(st));
+            if (hs[0] == 0) break;
         }
+        if (hs[0] != 0) return hipErrorUnknown;   // more levels than vertices: cannot happen
+        *ecc = hs[3];
         int32_t init = 0x7fffffff;
         CK(hipMemcpyAsync(sizes + 4, &init, sizeof(int32_t), hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_min_at_depth, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, dist, *ecc,
@@ -460,6 +657,7 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
     CK(hipFreeAsync(dist, st));
     CK(hipFreeAsync(fa, st));
     CK(hipFreeAsync(fb, st));
+    CK(hipFreeAsync(heavy, st));
     CK(hipFreeAsync(sizes, st));
     CK(hipFreeAsync(best, st));
     return hipGetLastError();

@@ -1167,7 +1167,7 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
 
 }  // namespace
 
-int sampler_max_block() { return 512; }
+int sampler_max_block() { return 1024; }
 
 int sampler_blocks_per_cu(int block)
 {
@@ -1178,6 +1178,7 @@ int sampler_blocks_per_cu(int block)
     case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<128>, 128, 0); break;
     case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<256>, 256, 0); break;
     case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<512>, 512, 0); break;
+    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<1024>, 1024, 0); break;
     default: break;
     }
     return (e == hipSuccess && nb > 0) ? nb : 1;
@@ -1190,6 +1191,7 @@ hipError_t launch_sampler(const SampleLaunch &a, int slots, int block, hipStream
     case 128: hipLaunchKernelGGL(k_sample<128>, dim3(slots), dim3(128), 0, st, a); break;
     case 256: hipLaunchKernelGGL(k_sample<256>, dim3(slots), dim3(256), 0, st, a); break;
     case 512: hipLaunchKernelGGL(k_sample<512>, dim3(slots), dim3(512), 0, st, a); break;
+    case 1024: hipLaunchKernelGGL(k_sample<1024>, dim3(slots), dim3(1024), 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

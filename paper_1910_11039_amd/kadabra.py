@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libkadabra_hip.so")
 KAD_OK = 0
 STATUS = {0: "KAD_OK", -1: "KAD_EINVAL", -2: "KAD_ENOMEM", -3: "KAD_EDEVICE",
           -4: "KAD_ENOTCONNECTED", -5: "KAD_ESTATE", -6: "KAD_EOVERFLOW"}
-KAD_STREAM_ADS, KAD_STREAM_CALIB = 0, 1
+KAD_STREAM_ADS, KAD_STREAM_CALIB, KAD_STREAM_TUNE = 0, 1, 5
 KAD_ALLOC_PLAIN, KAD_ALLOC_EXPLICIT, KAD_ALLOC_LEARNED = 0, 1, 2
 KAD_SIGMA_AUTO, KAD_SIGMA_FP = 0, 1
 KAD_STOP_NONE, KAD_STOP_COND, KAD_STOP_OMEGA = 0, 1, 2
@@ -52,7 +52,8 @@ class kad_result(C.Structure):
                 ("vertices_visited", C.c_int64), ("pred_edges", C.c_int64),
                 ("path_vertices", C.c_int64), ("fp_samples", C.c_int64), ("max_f", C.c_double),
                 ("max_g", C.c_double), ("min_margin", C.c_double), ("epoch_size", C.c_uint32),
-                ("slots", C.c_int32), ("samples_run", C.c_int64)]
+                ("slots", C.c_int32), ("samples_run", C.c_int64), ("block_size", C.c_int32),
+                ("pools", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -173,3 +173,39 @@ def test_learned_allocation_falls_back_to_plain(ctx, oracle):
     S.set_mlp_weights(params, np.array([0, 0, 0, 1, 1, 1], dtype=np.float32))
     r = S.run_to_stop()
     assert r.tau0 == math.ceil(r.omega / 100)
+
+
+def test_trained_prior_beats_plain_calibration(ctx, oracle):
+    """What the committed network gains: on an R-MAT graph held out from its
+    training set (scale 18, seed 1018; training used seeds 101..120), the
+    learned allocation stops after fewer total samples (tau0 + tau) than the
+    plain calibration on the same seeds, and on a small held-out R-MAT both
+    arms stay within eps of exact betweenness."""
+    params, norm = L.load()
+    g = gg.cached(gg.rmat, scale=18, edge_factor=16, seed=1018)
+    G = K.Graph(ctx, g)
+    tot = {}
+    for arm, mode in (("plain", K.KAD_ALLOC_PLAIN), ("learned", K.KAD_ALLOC_LEARNED)):
+        S = K.Sampler(G, seed=1, epsilon=0.01, delta=0.1, alloc_mode=mode, epoch_size=1024)
+        if mode == K.KAD_ALLOC_LEARNED:
+            S.set_mlp_weights(params, norm)
+        t = 0
+        for seed in (1, 2, 3):
+            S.reset(seed)
+            r = S.run_to_stop()
+            assert r.stop_reason == K.KAD_STOP_COND
+            assert (r.tau0 == 0) == (mode == K.KAD_ALLOC_LEARNED)
+            t += r.tau0 + r.tau
+        tot[arm] = t
+        S.close()
+    assert tot["learned"] < 0.95 * tot["plain"], tot
+    small = gg.rmat(11, 16, 1011)
+    Gs = K.Graph(ctx, small)
+    bc = oracle.brandes(small)
+    for mode in (K.KAD_ALLOC_PLAIN, K.KAD_ALLOC_LEARNED):
+        S = K.Sampler(Gs, seed=4, epsilon=0.01, delta=0.1, alloc_mode=mode)
+        if mode == K.KAD_ALLOC_LEARNED:
+            S.set_mlp_weights(params, norm)
+        S.run_to_stop()
+        assert np.abs(S.btilde() - bc).max() <= 0.01
+        S.close()

@@ -122,7 +122,7 @@ def test_meet_sets_beyond_lds_capacity(ctx, oracle, mode):
     assert info[:, 5].max() == k
 
 
-@pytest.mark.parametrize("block,slots", [(64, 7), (128, 50), (256, 0), (512, 13)])
+@pytest.mark.parametrize("block,slots", [(64, 7), (128, 50), (256, 0), (512, 13), (1024, 0), (1024, 3)])
 def test_launch_shapes_give_identical_counts(ctx, oracle, block, slots):
     g = gg.rmat(12, 16, 3)
     G = upload(ctx, g)
@@ -247,3 +247,13 @@ def test_grid2048_sampled_paths_at_full_size(ctx, oracle):
     g = gg.workload("grid2048")
     info = compare_paths(ctx, oracle, g, 0, count=24, seed=1, first=5000)
     assert info[:, 4].sum() >= 20
+
+
+@pytest.mark.parametrize("name", ["rmat20", "grid2048"])
+def test_vd_bracket_at_full_size(ctx, oracle, name):
+    """The bracket's three sweeps on the benchmark graphs: R-MAT's wide
+    levels take the bottom-up steps, the grid's thousands of narrow levels
+    the single-workgroup and top-down ones; both equal the oracle's."""
+    g = gg.workload(name)
+    G = K.Graph(ctx, g)
+    assert K.kad_vd_bracket(ctx.h, G.h) == oracle.vd_bracket(g)
