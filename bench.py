@@ -33,6 +33,9 @@ WORKLOADS = {
     "er2048": ("er2048", 0.01, "Erdos-Renyi G(2048, 16384), largest component"),
     "grid2048": ("grid2048", 0.01, "2048x2048 grid, 5% edges removed, 0.1% shortcuts of offset <= 8, "
                                    "largest component"),
+    "rmat22": ("rmat22", 0.01, "R-MAT scale 22, edge factor 16, Graph500 parameters, largest component "
+                               "(held out from the learned prior's training graphs)"),
+    "rmat26": ("rmat26", 0.01, "R-MAT scale 26, edge factor 16, Graph500 parameters, largest component"),
 }
 
 

@@ -597,24 +597,14 @@ static kad_status learned_prior(kad_sampler *s)
     return KAD_OK;
 }
 
-// Checks the allocation's budget on the host: every delta in (0, 1) and
-// the (compensated) sum of delta_L + delta_U below delta / 2.
+// Checks the allocation's budget on the device: every delta in (0, 1) and
+// the sum of delta_L + delta_U below delta / 2.
 static bool alloc_is_valid(kad_sampler *s)
 {
-    const int32_t n = s->g->n;
-    std::vector<double> LL(n), LU(n);
-    if (hipMemcpy(LL.data(), s->LL, 8ull * n, hipMemcpyDeviceToHost) != hipSuccess) return false;
-    if (hipMemcpy(LU.data(), s->LU, 8ull * n, hipMemcpyDeviceToHost) != hipSuccess) return false;
-    double sum = 0.0, comp = 0.0;
-    for (int32_t v = 0; v < n; ++v) {
-        if (!std::isfinite(LL[v]) || !std::isfinite(LU[v]) || LL[v] <= 0.0 || LU[v] <= 0.0) return false;
-        const double x = exp(-LL[v]) + exp(-LU[v]);
-        const double y = x - comp;
-        const double t = sum + y;
-        comp = (t - sum) - y;
-        sum = t;
-    }
-    return sum <= 0.5 * s->o.delta;
+    double sum = 0.0;
+    bool finite = false;
+    if (alloc_budget(s->g->n, s->LL, s->LU, s->ctx->stream, &sum, &finite) != hipSuccess) return false;
+    return finite && sum <= 0.5 * s->o.delta;
 }
 
 static kad_status ensure_delta(kad_sampler *s)

@@ -18,6 +18,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "kad_internal.h"
 #include "philox.h"
@@ -297,6 +298,7 @@ __global__ void k_min_at_depth(int32_t n, const int32_t *dist, int32_t depth, in
 //   sz[0] frontier size      sz[1] next size        sz[2] frontier depth
 //   sz[3] last nonempty depth sz[4] collect cursor  sz[5..6] frontier degree sum
 //   sz[7] heavy rows         sz[8..9] next degree sum  sz[10] listed
+//   sz[11] the frontier's bitmap is in bits[k & 1]
 constexpr int32_t SMALL_V = 4096;         // single-workgroup levels: frontier size and
 constexpr int64_t SMALL_D = 16384;        // degree sum at most these
 constexpr int64_t HEAVY = 4096;           // top-down rows longer than this are split
@@ -377,6 +379,7 @@ __global__ __launch_bounds__(1024) void k_bfs_small(DevGraph g, int32_t *dist, i
         sz[5] = (int32_t)(uint32_t)(fdeg & 0xffffffff);
         sz[6] = (int32_t)(fdeg >> 32);
         sz[10] = 1;
+        sz[11] = 0;
     }
 }
 
@@ -446,25 +449,56 @@ __global__ void k_bfs_heavy(DevGraph g, int32_t *dist, const int32_t *heavy, int
     if ((threadIdx.x & 63) == 0 && dsum) atomicAdd((unsigned long long *)&sz[8], dsum);
 }
 
-// One bottom-up level: every unreached vertex looks for a neighbour at the
-// frontier's depth and stops at the first one.  Leaves no list.
-__global__ void k_bfs_bu(DevGraph g, int32_t *dist, int32_t *sz, int32_t big_v)
+// Frontier bitmap of the current depth from dist (before a bottom-up level
+// that follows a top-down one).  A wave covers 64 consecutive vertices and
+// stores their bits as one word.
+__global__ void k_bfs_mark(int32_t n, const int32_t *dist, uint64_t *bits0, uint64_t *bits1, int32_t *sz,
+                           int32_t big_v)
+{
+    const int32_t fsize = sz[0], depth = sz[2];
+    if (fsize == 0 || !bfs_bottom_up(fsize, big_v) || sz[11] != 0) return;
+    uint64_t *cur = (depth & 1) ? bits1 : bits0;
+    const int32_t nw = (n + 63) >> 6;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < 64ll * nw;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const bool in = v < n && dist[v] == depth;
+        const uint64_t m = __ballot(in);
+        if ((threadIdx.x & 63) == 0) cur[v >> 6] = m;
+    }
+}
+
+// One bottom-up level: every unreached vertex looks for a neighbour in the
+// frontier bitmap and stops at the first one; the new vertices' bits form
+// the next bitmap.
+__global__ void k_bfs_bu(DevGraph g, int32_t *dist, uint64_t *bits0, uint64_t *bits1, int32_t *sz, int32_t big_v)
 {
     const int32_t fsize = sz[0], depth = sz[2];
     if (fsize == 0 || !bfs_bottom_up(fsize, big_v)) return;
+    const uint64_t *cur = (depth & 1) ? bits1 : bits0;
+    uint64_t *nxt = (depth & 1) ? bits0 : bits1;
+    const int32_t nw = (g.n + 63) >> 6;
     int cnt = 0;
     unsigned long long dsum = 0;
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
-        if (dist[v] != -1) continue;
-        const int64_t b = g.rp[v], e1 = g.rp[v + 1];
-        for (int64_t e = b; e < e1; ++e) {
-            if (dist[g.ci[e]] == depth) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < 64ll * nw;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        bool found = false;
+        if (v < g.n && dist[v] == -1) {
+            const int64_t b = g.rp[v], e1 = g.rp[v + 1];
+            for (int64_t e = b; e < e1; ++e) {
+                const int32_t u = g.ci[e];
+                if ((cur[u >> 6] >> (u & 63)) & 1ull) {
+                    found = true;
+                    break;
+                }
+            }
+            if (found) {
                 dist[v] = depth + 1;
                 cnt += 1;
                 dsum += (unsigned long long)(e1 - b);
-                break;
             }
         }
+        const uint64_t m = __ballot(found);
+        if ((threadIdx.x & 63) == 0) nxt[v >> 6] = m;
     }
     for (int o = 32; o > 0; o >>= 1) {
         cnt += __shfl_xor(cnt, o);
@@ -483,6 +517,7 @@ __global__ void k_bfs_advance(int32_t *sz, int32_t big_v)
     if (fsize == 0) return;
     const int32_t nsize = sz[1];
     sz[10] = bfs_bottom_up(fsize, big_v) ? 0 : 1;   // top-down listed the next frontier
+    sz[11] = bfs_bottom_up(fsize, big_v) ? 1 : 0;   // bottom-up left its bitmap
     sz[0] = nsize;
     sz[1] = 0;
     sz[2] += 1;
@@ -587,6 +622,67 @@ hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host)
 
 size_t alloc_partials(int32_t n) { return (size_t)((n + 4095) / 4096); }
 
+namespace {
+// Budget check of an allocation: per workgroup, the sum of delta_L + delta_U
+// over its vertices (Kahan per thread, then a pairwise tree), and a flag for
+// any L that is not finite and positive.
+constexpr int CB = 256;
+__global__ __launch_bounds__(CB) void k_alloc_check(int32_t n, const double *LL, const double *LU,
+                                                    double *partial, int32_t *bad)
+{
+    __shared__ double sh[CB];
+    double sum = 0.0, comp = 0.0;
+    int flag = 0;
+    for (int32_t v = blockIdx.x * CB + threadIdx.x; v < n; v += gridDim.x * CB) {
+        const double a = LL[v], b = LU[v];
+        if (!(a > 0.0) || !(b > 0.0) || !isfinite(a) || !isfinite(b)) flag = 1;
+        const double x = exp(-a) + exp(-b);
+        const double y = x - comp;
+        const double t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+    }
+    if (flag) atomicOr(bad, 1);
+    sh[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = CB / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+}  // namespace
+
+hipError_t alloc_budget(int32_t n, const double *LL, const double *LU, hipStream_t st, double *sum_out,
+                        bool *finite_out)
+{
+    hipError_t e;
+    const int nb = grid_for(n, CB, 1024);
+    double *part = nullptr;
+    int32_t *bad = nullptr;
+    if ((e = hipMallocAsync((void **)&part, sizeof(double) * nb, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&bad, sizeof(int32_t), st)) != hipSuccess) return e;
+    CK(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_alloc_check, dim3(nb), dim3(CB), 0, st, n, LL, LU, part, bad);
+    std::vector<double> hp(nb);
+    int32_t hb = 0;
+    CK(hipMemcpyAsync(hp.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    CK(hipFreeAsync(part, st));
+    CK(hipFreeAsync(bad, st));
+    double sum = 0.0, comp = 0.0;
+    for (int i = 0; i < nb; ++i) {
+        const double y = hp[i] - comp;
+        const double t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+    }
+    *sum_out = sum;
+    *finite_out = hb == 0;
+    return hipSuccess;
+}
+
 hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, int64_t *vd_hi)
 {
     hipError_t e;
@@ -598,6 +694,10 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
     if ((e = hipMallocAsync((void **)&fb, sizeof(int32_t) * (size_t)n, st)) != hipSuccess) return e;
     int32_t *heavy = nullptr;
     if ((e = hipMallocAsync((void **)&heavy, sizeof(int32_t) * (size_t)n, st)) != hipSuccess) return e;
+    uint64_t *bits0 = nullptr, *bits1 = nullptr;
+    const size_t nwords = ((size_t)n + 63) / 64;
+    if ((e = hipMallocAsync((void **)&bits0, sizeof(uint64_t) * nwords, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&bits1, sizeof(uint64_t) * nwords, st)) != hipSuccess) return e;
     if ((e = hipMallocAsync((void **)&sizes, sizeof(int32_t) * 12, st)) != hipSuccess) return e;
     if ((e = hipMallocAsync((void **)&best, sizeof(unsigned long long), st)) != hipSuccess) return e;
     CK(hipMemsetAsync(best, 0, sizeof(unsigned long long), st));
@@ -629,7 +729,10 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
                                    sizes, big_v);
                 hipLaunchKernelGGL(k_bfs_td, dim3(2048), dim3(256), 0, st, g, dist, fa, fb, heavy, sizes, big_v);
                 hipLaunchKernelGGL(k_bfs_heavy, dim3(1024), dim3(256), 0, st, g, dist, heavy, fa, fb, sizes, big_v);
-                hipLaunchKernelGGL(k_bfs_bu, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, g, dist, sizes, big_v);
+                hipLaunchKernelGGL(k_bfs_mark, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, dist, bits0,
+                                   bits1, sizes, big_v);
+                hipLaunchKernelGGL(k_bfs_bu, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, g, dist, bits0, bits1,
+                                   sizes, big_v);
                 hipLaunchKernelGGL(k_bfs_advance, dim3(1), dim3(1), 0, st, sizes, big_v);
             }
             CK(hipMemcpyAsync(hs, sizes, sizeof(hs), hipMemcpyDeviceToHost, st));
@@ -658,6 +761,8 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
     CK(hipFreeAsync(fa, st));
     CK(hipFreeAsync(fb, st));
     CK(hipFreeAsync(heavy, st));
+    CK(hipFreeAsync(bits0, st));
+    CK(hipFreeAsync(bits1, st));
     CK(hipFreeAsync(sizes, st));
     CK(hipFreeAsync(best, st));
     return hipGetLastError();

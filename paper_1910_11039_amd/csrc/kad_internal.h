@@ -127,6 +127,11 @@ struct AllocArgs {
     double *LL, *LU;     // out
 };
 hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host);
+// Sum over v of delta_L(v) + delta_U(v) = e^-LL + e^-LU on the device
+// (compensated per thread, pairwise across threads), and whether every L is
+// finite and positive.
+hipError_t alloc_budget(int32_t n, const double *LL, const double *LU, hipStream_t st, double *sum_out,
+                        bool *finite_out);
 
 // Vertex-diameter bracket by BFS sweeps on the device.
 hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, int64_t *vd_hi);
