@@ -223,15 +223,29 @@ __global__ __launch_bounds__(AB) void k_alloc_sum(AllocArgs a, int32_t chunk)
     if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
 }
 
-__global__ void k_alloc_update(double *lo_hi, const double *partials, int32_t nb, double target)
+// One bisection step: the partial sums added in a fixed order (thread t
+// takes partials t, t + AB, ... in turn, then a pairwise tree).
+__global__ __launch_bounds__(AB) void k_alloc_update(double *lo_hi, const double *partials, int32_t nb,
+                                                     double target)
 {
+    __shared__ double red[AB];
     if (lo_hi[2] != 0.0) return;
     const double lo = lo_hi[0], hi = lo_hi[1];
     const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) { lo_hi[2] = 1.0; return; }
     double s = 0.0;
-    for (int32_t b = 0; b < nb; ++b) s = s + partials[b];
-    if (s <= target) lo_hi[1] = mid; else lo_hi[0] = mid;
+    for (int32_t b = threadIdx.x; b < nb; b += AB) s = s + partials[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = AB / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    if (mid <= lo || mid >= hi) {
+        lo_hi[2] = 1.0;
+        return;
+    }
+    if (red[0] <= target) lo_hi[1] = mid; else lo_hi[0] = mid;
 }
 
 __global__ void k_alloc_delta(AllocArgs a, double C)
@@ -301,7 +315,8 @@ __global__ void k_min_at_depth(int32_t n, const int32_t *dist, int32_t depth, in
 //   sz[11] the frontier's bitmap is in bits[k & 1]
 constexpr int32_t SMALL_V = 4096;         // single-workgroup levels: frontier size and
 constexpr int64_t SMALL_D = 16384;        // degree sum at most these
-constexpr int64_t HEAVY = 4096;           // top-down rows longer than this are split
+constexpr int64_t HEAVY = 512;            // top-down rows longer than this are split
+constexpr int64_t PIECE = 2048;           // into pieces of this many entries
 constexpr int SMALL_LONG = 2048;          // > SMALL_D / 33 rows longer than 32
 
 __device__ __forceinline__ int64_t sz_get64(const int32_t *sz, int i)
@@ -425,28 +440,64 @@ __global__ void k_bfs_td(DevGraph g, int32_t *dist, int32_t *buf0, int32_t *buf1
     if (lane == 0 && dsum) atomicAdd((unsigned long long *)&sz[8], dsum);
 }
 
-// The heavy rows of a top-down level, split across every workgroup.
-__global__ void k_bfs_heavy(DevGraph g, int32_t *dist, const int32_t *heavy, int32_t *buf0, int32_t *buf1,
-                            int32_t *sz, int32_t big_v)
+// The heavy rows of a top-down level, cut into pieces of PIECE entries that
+// are dealt round-robin to the workgroups.  Rows are taken 256 at a time:
+// every workgroup stages the same 256 rows with the prefix of their piece
+// counts and then handles pieces blockIdx.x, blockIdx.x + gridDim.x, ...
+__global__ __launch_bounds__(256) void k_bfs_heavy(DevGraph g, int32_t *dist, const int32_t *heavy,
+                                                   int32_t *buf0, int32_t *buf1, int32_t *sz, int32_t big_v)
 {
+    __shared__ int64_t s_beg[256], s_end[256], s_pre[257];
+    __shared__ int64_t s_wsum[4];
     const int32_t fsize = sz[0], depth = sz[2], nh = sz[7];
     if (fsize == 0 || bfs_bottom_up(fsize, big_v) || nh == 0) return;
     int32_t *nxt = (depth & 1) ? buf0 : buf1;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     unsigned long long dsum = 0;
-    for (int32_t h = 0; h < nh; ++h) {
-        const int32_t u = heavy[h];
-        const int64_t b = g.rp[u], e1 = g.rp[u + 1];
-        for (int64_t e = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1;
-             e += (int64_t)gridDim.x * blockDim.x) {
-            const int32_t w = g.ci[e];
-            if (atomicCAS(&dist[w], -1, depth + 1) == -1) {
-                nxt[atomicAdd(&sz[1], 1)] = w;
-                dsum += (unsigned long long)(g.rp[w + 1] - g.rp[w]);
+    for (int32_t h0 = 0; h0 < nh; h0 += 256) {
+        int64_t b = 0, e1 = 0, pc = 0;
+        if (h0 + tid < nh) {
+            const int32_t u = heavy[h0 + tid];
+            b = g.rp[u];
+            e1 = g.rp[u + 1];
+            pc = (e1 - b + PIECE - 1) / PIECE;
+        }
+        s_beg[tid] = b;
+        s_end[tid] = e1;
+        // inclusive scan of the piece counts
+        int64_t x = pc;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_wsum[wid] = x;
+        __syncthreads();
+        int64_t before = 0;
+        for (int i = 0; i < wid; ++i) before += s_wsum[i];
+        s_pre[tid + 1] = before + x;
+        if (tid == 0) s_pre[0] = 0;
+        __syncthreads();
+        const int64_t total = s_pre[256];
+        for (int64_t gp = blockIdx.x; gp < total; gp += gridDim.x) {
+            int lo_i = 0, hi_i = 255;       // row r with s_pre[r] <= gp < s_pre[r + 1]
+            while (lo_i < hi_i) {
+                const int mid = (lo_i + hi_i + 1) >> 1;
+                if (s_pre[mid] <= gp) lo_i = mid; else hi_i = mid - 1;
+            }
+            const int64_t pb = s_beg[lo_i] + (gp - s_pre[lo_i]) * PIECE;
+            const int64_t pe = min(pb + PIECE, s_end[lo_i]);
+            for (int64_t e = pb + tid; e < pe; e += 256) {
+                const int32_t w = g.ci[e];
+                if (atomicCAS(&dist[w], -1, depth + 1) == -1) {
+                    nxt[atomicAdd(&sz[1], 1)] = w;
+                    dsum += (unsigned long long)(g.rp[w + 1] - g.rp[w]);
+                }
             }
         }
+        __syncthreads();
     }
     for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o);
-    if ((threadIdx.x & 63) == 0 && dsum) atomicAdd((unsigned long long *)&sz[8], dsum);
+    if (lane == 0 && dsum) atomicAdd((unsigned long long *)&sz[8], dsum);
 }
 
 // Frontier bitmap of the current depth from dist (before a bottom-up level
@@ -601,7 +652,7 @@ hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host)
         const int32_t nb = (a.n + chunk - 1) / chunk;
         for (int it = 0; it < 200; ++it) {
             hipLaunchKernelGGL(k_alloc_sum, dim3(nb), dim3(AB), 0, st, a, chunk);
-            hipLaunchKernelGGL(k_alloc_update, dim3(1), dim3(1), 0, st, a.lo_hi, a.partials, nb, target);
+            hipLaunchKernelGGL(k_alloc_update, dim3(1), dim3(AB), 0, st, a.lo_hi, a.partials, nb, target);
             if ((it & 31) == 31) {
                 double fin[3];
                 CK(hipMemcpyAsync(fin, a.lo_hi, sizeof(fin), hipMemcpyDeviceToHost, st));

@@ -42,6 +42,7 @@ namespace {
 
 constexpr int MCAP = 1024;                 // meet sets up to this size are ranked in LDS
 constexpr int LMAX = 30;                   // layers whose queue offsets are kept in LDS
+constexpr int MEDGE = 1024;                // meet edges of one frontier chunk folded in LDS
 constexpr double BIG = 0x1p400;
 constexpr double SHRINK = 0x1p-400;
 constexpr uint32_t X_SHIFT = 31;
@@ -121,7 +122,9 @@ struct Smem {
     int64_t sdeg[2], psdeg[2];
     int32_t lo[2], hi[2], dep[2], plo[2], phi[2];
     int32_t loff[2][LMAX + 2];   // layer j of a side = queue positions [loff[j], loff[j+1])
-    int32_t tail, mcount, ovf, err, w, wmin, mpath;
+    int32_t me_a[MEDGE];         // meet edges of the current chunk: owner index in the chunk,
+    int32_t me_w[MEDGE];         // and the meet vertex
+    int32_t tail, mcount, ovf, err, w, wmin, mpath, nme, fold_bad;
     uint32_t stamp;
     int32_t s, t;
 };
@@ -201,6 +204,13 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
     const uint32_t xbit = (uint32_t)X << X_SHIFT;
     const uint64_t newkey = ((uint64_t)c.cur << 32) | xbit | (uint32_t)(k + 1);
     unsigned long long nd = 0;
+    // sigma_X of the meet vertices, should this expansion meet: every meet
+    // edge (u, w) adds sigma(u) to w's slot once u's sigma is complete
+    for (int32_t i = tid; i < MCAP; i += BS) sm.m.w[i] = 0;
+    if (tid == 0) {
+        sm.nme = 0;
+        sm.fold_bad = 0;
+    }
     for (int32_t base = lo; base < hi; base += BS) {
         const int cnt = min(BS, hi - base);
         int32_t u = -1;
@@ -282,6 +292,13 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
                     pos = __shfl(pos, leader);
                     if (dj) c.Q[qpos(n, X, pos + (int)mbcnt(dm))] = w[j];
                 }
+                if (meet >> j & 1) {
+                    const int32_t slot = atomicAdd(&sm.nme, 1);
+                    if (slot < MEDGE) {
+                        sm.me_a[slot] = a[j];
+                        sm.me_w[slot] = w[j];
+                    }
+                }
                 const bool mj = newmeet >> j & 1;
                 const uint64_t mm = __ballot(mj);
                 if (mm) {
@@ -308,7 +325,24 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
         }
         __syncthreads();
         if (k >= 1 && tid < cnt) st_sig(c.R + sm.e.u[tid], sm.e.acc[tid]);
+        const int32_t nme = sm.nme;
+        if (nme > 0) {
+            // the chunk's sigmas are complete; meet positions were written
+            // by the lanes that set the meet bits, before the barrier
+            if (nme > MEDGE && tid == 0) sm.fold_bad = 1;
+            for (int32_t i = tid; i < min(nme, MEDGE); i += BS) {
+                const uint64_t su = (k >= 1) ? (uint64_t)sm.e.acc[sm.me_a[i]] : 1ull;
+                const uint64_t mp = ld_sig(c.R + sm.me_w[i]);
+                if (mp < (uint64_t)MCAP) {
+                    const unsigned long long old = atomicAdd(&sm.m.w[mp], (unsigned long long)su);
+                    if (old + su < old) sm.ovf = 1;
+                } else {
+                    sm.fold_bad = 1;
+                }
+            }
+        }
         __syncthreads();
+        if (tid == 0) sm.nme = 0;
     }
     if (nd) atomicAdd(&sm.nextdeg, nd);
 }
@@ -554,22 +588,27 @@ __device__ void meet_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t 
     }
     unsigned long long *accX = path == 0 ? sm.m.w : gacc;
     unsigned long long *accY = path == 0 ? sm.m.w2 : gacc + macc_cap;
+    // the expansion folded sigma_X of every meet vertex into sm.m.w unless
+    // the meet edges overflowed its buffer (then it is recomputed here)
+    const bool foldX = path == 0 && !sm.fold_bad;
     uint64_t dsum = 0;
     for (int32_t i = tid; i < m; i += BS) {
         const int32_t w = c.MB[i];
         dsum += (uint64_t)(c.g.rp[w + 1] - c.g.rp[w]);
-        accX[i] = 0;
+        if (!foldX) accX[i] = 0;
         accY[i] = 0;
         if (path == 0) sm.m.id[i] = w;
     }
     const uint64_t dM = block_sum_u64<BS>(sm, dsum);
     const int Y = 1 - X;
-    const bool pushX = (uint64_t)sm.sdeg[X] <= dM;
+    const bool pushX = !foldX && (uint64_t)sm.sdeg[X] <= dM;
+    const bool pullX = !foldX && !pushX;
     const bool pushY = kY >= 1 && (uint64_t)sm.psdeg[Y] <= dM;
+    const bool pullY = kY >= 1 && !pushY;
     if (pushX) push_to_meet<BS>(sm, c, X, sm.lo[X], sm.hi[X], accX);
     if (pushY) push_to_meet<BS>(sm, c, Y, sm.plo[Y], sm.phi[Y], accY);
-    if (!pushX || (kY >= 1 && !pushY))
-        pull_to_meet<BS>(sm, c, X, kX, kY, m, pushX ? nullptr : accX, (kY >= 1 && !pushY) ? accY : nullptr);
+    if (pullX || pullY)
+        pull_to_meet<BS>(sm, c, X, kX, kY, m, pullX ? accX : nullptr, pullY ? accY : nullptr);
     __syncthreads();
     for (int32_t i = tid; i < m; i += BS) {
         const uint64_t ax = accX[i];
