@@ -111,6 +111,8 @@ typedef struct {
                                   /* 256, 512, 1024); 0 = autotune over 256, 512, */
                                   /* 1024 by a timed trial at kad_sampler_init    */
     int32_t timing;               /* 1: time every sampler launch with HIP events */
+    int32_t pools;                /* slot pools = sampler launches that may       */
+                                  /* overlap (1..4); 0 = as many as memory allows */
 } kad_opts;
 
 typedef struct {

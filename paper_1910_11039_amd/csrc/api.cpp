@@ -400,6 +400,17 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     // across pools); a single pool when memory is tight
     s->slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)want, std::min<size_t>(fit, 1 << 16)));
     s->P = (int)std::max<size_t>(1, std::min<size_t>(4, fit / (size_t)s->slots));
+    if (o->pools < 0 || o->pools > 4) {
+        delete s;
+        return fail(KAD_EINVAL, "pools must be 0 (auto) or 1..4");
+    }
+    if (o->pools > 0) {
+        if ((size_t)o->pools * (size_t)s->slots > fit) {
+            delete s;
+            return fail(KAD_ENOMEM, "requested pools exceed the visited-state budget");
+        }
+        s->P = o->pools;
+    }
     if (o->slots > 0 && s->slots < o->slots) {
         delete s;
         return fail(KAD_ENOMEM, "requested slots exceed the visited-state budget");

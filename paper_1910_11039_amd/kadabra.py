@@ -39,7 +39,8 @@ class kad_opts(C.Structure):
                 ("epoch_size", C.c_uint32), ("alloc_mode", C.c_int32),
                 ("omega_override", C.c_double), ("sigma_mode", C.c_int32), ("slots", C.c_int32),
                 ("visited_budget_bytes", C.c_uint64), ("epochs_in_flight", C.c_int32),
-                ("use_graphs", C.c_int32), ("block_size", C.c_int32), ("timing", C.c_int32)]
+                ("use_graphs", C.c_int32), ("block_size", C.c_int32), ("timing", C.c_int32),
+                ("pools", C.c_int32)]
 
 
 class kad_result(C.Structure):
@@ -156,9 +157,9 @@ def kad_graph_free(g):
 
 def make_opts(seed=1, epsilon=0.01, delta=0.1, epoch_size=0, alloc_mode=KAD_ALLOC_PLAIN,
               omega_override=0.0, sigma_mode=KAD_SIGMA_AUTO, slots=0, visited_budget_bytes=0,
-              epochs_in_flight=0, use_graphs=0, block_size=0, timing=0) -> kad_opts:
+              epochs_in_flight=0, use_graphs=0, block_size=0, timing=0, pools=0) -> kad_opts:
     return kad_opts(seed, epsilon, delta, epoch_size, alloc_mode, omega_override, sigma_mode, slots,
-                    visited_budget_bytes, epochs_in_flight, use_graphs, block_size, timing)
+                    visited_budget_bytes, epochs_in_flight, use_graphs, block_size, timing, pools)
 
 
 def kad_sampler_init(ctx, g, opts: kad_opts):

@@ -217,6 +217,17 @@ def test_graph_run_matches_plain_loop(ctx, oracle):
     assert t0 == t1 and e0 == e1 and np.array_equal(c0, c1)
 
 
+@pytest.mark.parametrize("pools", [1, 2, 4])
+def test_overlapped_pools_give_the_oracle_run(ctx, oracle, pools):
+    """Epochs overlapped across 1, 2 or 4 slot pools and streams: the stop
+    epoch, tau and every counter equal the oracle's sequential run."""
+    g = gg.rmat(12, 16, 6)
+    G = upload(ctx, g)
+    S, omega = explicit_sampler(G, g, oracle, eps=0.02, epoch=256, pools=pools, slots=40)
+    r, _ = _run_and_compare(S, g, oracle, omega, 0.02, 256)
+    assert r.pools == pools
+
+
 def test_rejects_bad_inputs(ctx, oracle):
     g = gg.from_edges(4, np.array([0, 2]), np.array([1, 3]))
     with pytest.raises(K.KadError) as ei:
@@ -232,6 +243,9 @@ def test_rejects_bad_inputs(ctx, oracle):
         S.run_to_stop()          # EXPLICIT without arrays
     with pytest.raises(K.KadError):
         K.Sampler(G, epsilon=0.0, delta=0.1)
+    with pytest.raises(K.KadError) as ei:
+        K.Sampler(G, epsilon=0.01, delta=0.1, pools=5)
+    assert ei.value.status == -1
 
 
 def test_rmat20_sampled_paths_at_full_size(ctx, oracle):
