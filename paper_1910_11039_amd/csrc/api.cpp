@@ -51,9 +51,12 @@ struct kad_graph {
     int device;
     int32_t n;
     int64_t nnz;
-    int64_t *d_rp;
+    int64_t *d_rp;       // internal (hub-first) numbering
     int32_t *d_ci;
-    DevGraph dev() const { return DevGraph{n, nnz, d_rp, d_ci}; }
+    int32_t *d_orig;     // internal id -> caller id
+    int32_t *d_newid;    // caller id -> internal id
+    int32_t *d_cci;      // rows in the caller's order
+    DevGraph dev() const { return DevGraph{n, nnz, d_rp, d_ci, d_orig, d_newid, d_cci}; }
 };
 
 struct kad_sampler {
@@ -183,22 +186,60 @@ extern "C" kad_status kad_graph_upload(kad_ctx *ctx, int32_t n, int64_t nnz, con
         if (st != KAD_OK) return st;
     }
     HIPCHK(hipSetDevice(ctx->device));
+    // hub-first numbering: a stable counting sort by descending degree
+    std::vector<int32_t> orig(n), newid(n);
+    std::vector<int64_t> rp2((size_t)n + 1);
+    {
+        int64_t maxdeg = 0;
+        for (int32_t v = 0; v < n; ++v) maxdeg = std::max<int64_t>(maxdeg, h_row_ptr[v + 1] - h_row_ptr[v]);
+        std::vector<int64_t> pos((size_t)maxdeg + 2, 0);
+        for (int32_t v = 0; v < n; ++v) pos[(size_t)(maxdeg - (h_row_ptr[v + 1] - h_row_ptr[v])) + 1]++;
+        for (size_t d = 1; d < pos.size(); ++d) pos[d] += pos[d - 1];
+        for (int32_t v = 0; v < n; ++v) {
+            const int32_t i = (int32_t)pos[(size_t)(maxdeg - (h_row_ptr[v + 1] - h_row_ptr[v]))]++;
+            orig[i] = v;
+            newid[v] = i;
+        }
+        rp2[0] = 0;
+        for (int32_t i = 0; i < n; ++i) rp2[i + 1] = rp2[i] + (h_row_ptr[orig[i] + 1] - h_row_ptr[orig[i]]);
+    }
     kad_graph *g = new kad_graph();
     g->ctx = ctx;
     g->device = ctx->device;
     g->n = n;
     g->nnz = nnz;
+    int64_t *t_rp = nullptr;
+    int32_t *t_ci = nullptr;
+    const size_t ci_bytes = sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1);
     if (hipMalloc((void **)&g->d_rp, sizeof(int64_t) * ((size_t)n + 1)) != hipSuccess ||
-        hipMalloc((void **)&g->d_ci, sizeof(int32_t) * std::max<int64_t>(nnz, 1)) != hipSuccess) {
+        hipMalloc((void **)&g->d_ci, ci_bytes) != hipSuccess ||
+        hipMalloc((void **)&g->d_orig, sizeof(int32_t) * (size_t)n) != hipSuccess ||
+        hipMalloc((void **)&g->d_newid, sizeof(int32_t) * (size_t)n) != hipSuccess ||
+        hipMalloc((void **)&g->d_cci, ci_bytes) != hipSuccess ||
+        hipMalloc((void **)&t_rp, sizeof(int64_t) * ((size_t)n + 1)) != hipSuccess ||
+        hipMalloc((void **)&t_ci, ci_bytes) != hipSuccess) {
+        hipFree(g->d_rp);
+        hipFree(g->d_ci);
+        hipFree(g->d_orig);
+        hipFree(g->d_newid);
+        hipFree(g->d_cci);
+        hipFree(t_rp);
+        hipFree(t_ci);
         delete g;
         return fail(KAD_ENOMEM, "graph allocation failed");
     }
-    HIPCHK(hipMemcpyAsync(g->d_rp, h_row_ptr, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice,
-                          ctx->stream));
-    if (nnz > 0)
-        HIPCHK(hipMemcpyAsync(g->d_ci, h_col_idx, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice,
-                              ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    hipStream_t st = ctx->stream;
+    HIPCHK(hipMemcpyAsync(t_rp, h_row_ptr, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, st));
+    if (nnz > 0) HIPCHK(hipMemcpyAsync(t_ci, h_col_idx, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(g->d_rp, rp2.data(), sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(g->d_orig, orig.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(g->d_newid, newid.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_relabel_rows(n, t_rp, t_ci, g->d_orig, g->d_newid, g->d_rp, g->d_cci, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipFree(t_rp));
+    HIPCHK(hipFree(t_ci));
+    if (nnz > 0) HIPCHK(sort_rows(n, nnz, g->d_rp, g->d_cci, g->d_ci, st));
+    HIPCHK(hipStreamSynchronize(st));
     *out = g;
     return KAD_OK;
 }
@@ -209,6 +250,9 @@ extern "C" void kad_graph_free(kad_graph *g)
     hipSetDevice(g->device);
     hipFree(g->d_rp);
     hipFree(g->d_ci);
+    hipFree(g->d_orig);
+    hipFree(g->d_newid);
+    hipFree(g->d_cci);
     delete g;
 }
 
@@ -567,10 +611,15 @@ extern "C" kad_status kad_set_delta(kad_sampler *s, const double *h_delta_L, con
         return fail(KAD_EINVAL, "sum of delta_L + delta_U must stay below delta / 2");
     HIPCHK(hipSetDevice(s->ctx->device));
     hipStream_t st = s->ctx->stream;
-    HIPCHK(hipMemcpyAsync(s->prior, h_delta_L, 8ull * n, hipMemcpyHostToDevice, st));
+    double *t = nullptr;
+    HIPCHK(hipMallocAsync((void **)&t, 8ull * n, st));
+    HIPCHK(hipMemcpyAsync(t, h_delta_L, 8ull * n, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_from_caller_f64(n, s->g->d_orig, t, s->prior, st));
     HIPCHK(launch_neglog(n, s->prior, s->LL, st));
-    HIPCHK(hipMemcpyAsync(s->prior, h_delta_U, 8ull * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(t, h_delta_U, 8ull * n, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_from_caller_f64(n, s->g->d_orig, t, s->prior, st));
     HIPCHK(launch_neglog(n, s->prior, s->LU, st));
+    HIPCHK(hipFreeAsync(t, st));
     HIPCHK(hipStreamSynchronize(st));
     s->delta_ready = true;
     return KAD_OK;
@@ -863,6 +912,30 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
     return KAD_OK;
 }
 
+// Copies an n-sized per-vertex device array (internal numbering) to the
+// host in the caller's numbering.
+static kad_status copy_to_caller(const kad_graph *g, const uint32_t *d_in, uint32_t *h_out, hipStream_t st)
+{
+    uint32_t *t = nullptr;
+    HIPCHK(hipMallocAsync((void **)&t, 4ull * g->n, st));
+    HIPCHK(launch_to_caller_u32(g->n, g->d_orig, d_in, t, st));
+    HIPCHK(hipMemcpyAsync(h_out, t, 4ull * g->n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipFreeAsync(t, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return KAD_OK;
+}
+
+static kad_status copy_to_caller(const kad_graph *g, const double *d_in, double *h_out, hipStream_t st)
+{
+    double *t = nullptr;
+    HIPCHK(hipMallocAsync((void **)&t, 8ull * g->n, st));
+    HIPCHK(launch_to_caller_f64(g->n, g->d_orig, d_in, t, st));
+    HIPCHK(hipMemcpyAsync(h_out, t, 8ull * g->n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipFreeAsync(t, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return KAD_OK;
+}
+
 extern "C" kad_status kad_fetch_result(const kad_sampler *s, kad_result *out)
 {
     if (!s || !out) return fail(KAD_EINVAL, "null argument");
@@ -875,7 +948,8 @@ extern "C" kad_status kad_fetch_counts(const kad_sampler *s, uint32_t *h_c, uint
     if (!s || !h_c) return fail(KAD_EINVAL, "null argument");
     HIPCHK(hipSetDevice(s->ctx->device));
     EpochState es;
-    HIPCHK(hipMemcpyAsync(h_c, s->c, 4ull * s->g->n, hipMemcpyDeviceToHost, s->ctx->stream));
+    kad_status r = copy_to_caller(s->g, s->c, h_c, s->ctx->stream);
+    if (r != KAD_OK) return r;
     HIPCHK(hipMemcpyAsync(&es, s->es, sizeof(es), hipMemcpyDeviceToHost, s->ctx->stream));
     HIPCHK(hipStreamSynchronize(s->ctx->stream));
     if (h_tau) *h_tau = es.tau;
@@ -903,10 +977,10 @@ extern "C" kad_status kad_fetch_btilde(const kad_sampler *s, double *h_b)
     double *d = nullptr;
     HIPCHK(hipMallocAsync((void **)&d, 8ull * s->g->n, st));
     HIPCHK(launch_btilde(s->g->n, s->c, tau, d, st));
-    HIPCHK(hipMemcpyAsync(h_b, d, 8ull * s->g->n, hipMemcpyDeviceToHost, st));
+    r = copy_to_caller(s->g, d, h_b, st);
     HIPCHK(hipFreeAsync(d, st));
     HIPCHK(hipStreamSynchronize(st));
-    return KAD_OK;
+    return r;
 }
 
 extern "C" kad_status kad_fetch_fg(const kad_sampler *s, double *h_f, double *h_g)
@@ -922,12 +996,12 @@ extern "C" kad_status kad_fetch_fg(const kad_sampler *s, double *h_f, double *h_
     HIPCHK(hipMallocAsync((void **)&f, 8ull * s->g->n, st));
     HIPCHK(hipMallocAsync((void **)&g, 8ull * s->g->n, st));
     HIPCHK(launch_fg(s->g->n, s->c, tau, s->LL, s->LU, s->omega, f, g, st));
-    HIPCHK(hipMemcpyAsync(h_f, f, 8ull * s->g->n, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_g, g, 8ull * s->g->n, hipMemcpyDeviceToHost, st));
+    r = copy_to_caller(s->g, f, h_f, st);
+    if (r == KAD_OK) r = copy_to_caller(s->g, g, h_g, st);
     HIPCHK(hipFreeAsync(f, st));
     HIPCHK(hipFreeAsync(g, st));
     HIPCHK(hipStreamSynchronize(st));
-    return KAD_OK;
+    return r;
 }
 
 extern "C" kad_status kad_fetch_delta(const kad_sampler *s, double *h_lnInvDL, double *h_lnInvDU)
@@ -935,10 +1009,9 @@ extern "C" kad_status kad_fetch_delta(const kad_sampler *s, double *h_lnInvDL, d
     if (!s || !h_lnInvDL || !h_lnInvDU) return fail(KAD_EINVAL, "null argument");
     if (!s->delta_ready) return fail(KAD_ESTATE, "delta allocation not done");
     HIPCHK(hipSetDevice(s->ctx->device));
-    HIPCHK(hipMemcpyAsync(h_lnInvDL, s->LL, 8ull * s->g->n, hipMemcpyDeviceToHost, s->ctx->stream));
-    HIPCHK(hipMemcpyAsync(h_lnInvDU, s->LU, 8ull * s->g->n, hipMemcpyDeviceToHost, s->ctx->stream));
-    HIPCHK(hipStreamSynchronize(s->ctx->stream));
-    return KAD_OK;
+    kad_status r = copy_to_caller(s->g, s->LL, h_lnInvDL, s->ctx->stream);
+    if (r == KAD_OK) r = copy_to_caller(s->g, s->LU, h_lnInvDU, s->ctx->stream);
+    return r;
 }
 
 extern "C" kad_status kad_fetch_history(const kad_sampler *s, uint32_t epochs, double *h_hist)
@@ -973,8 +1046,8 @@ extern "C" kad_status kad_fetch_calibration(const kad_sampler *s, uint32_t *h_cp
         return fail(KAD_ESTATE, "no calibration has run");
     HIPCHK(hipSetDevice(s->ctx->device));
     if (h_cprime) {
-        HIPCHK(hipMemcpyAsync(h_cprime, s->cprime, 4ull * s->g->n, hipMemcpyDeviceToHost, s->ctx->stream));
-        HIPCHK(hipStreamSynchronize(s->ctx->stream));
+        kad_status r = copy_to_caller(s->g, s->cprime, h_cprime, s->ctx->stream);
+        if (r != KAD_OK) return r;
     }
     if (h_tau0) *h_tau0 = s->res.tau0;
     if (h_C) *h_C = s->C;
@@ -995,7 +1068,8 @@ extern "C" kad_status kad_count_samples(kad_sampler *s, uint64_t stream, uint64_
     r = check_stats_error(s);
     if (r != KAD_OK) return r;
     std::vector<uint32_t> tmp(n);
-    HIPCHK(hipMemcpy(tmp.data(), s->scratch_counts, 4ull * n, hipMemcpyDeviceToHost));
+    r = copy_to_caller(s->g, s->scratch_counts, tmp.data(), st);
+    if (r != KAD_OK) return r;
     for (int32_t v = 0; v < n; ++v) h_c[v] += tmp[v];
     return KAD_OK;
 }
@@ -1069,11 +1143,15 @@ extern "C" kad_status kad_features(kad_ctx *ctx, const kad_graph *g, float *d_ou
     if (!ctx || !g || (!d_out && !h_out)) return fail(KAD_EINVAL, "null argument");
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
-    float *d = d_out;
-    if (!d) HIPCHK(hipMallocAsync((void **)&d, sizeof(float) * 3 * (size_t)g->n, st));
-    HIPCHK(launch_features(g->dev(), d, st));
+    const size_t bytes = sizeof(float) * 3 * (size_t)g->n;
+    float *t = nullptr, *d = d_out;
+    HIPCHK(hipMallocAsync((void **)&t, bytes, st));
+    if (!d) HIPCHK(hipMallocAsync((void **)&d, bytes, st));
+    HIPCHK(launch_features(g->dev(), t, st));
+    HIPCHK(launch_to_caller_f32x3(g->n, g->d_orig, t, d, st));
+    HIPCHK(hipFreeAsync(t, st));
     if (!d_out) {
-        HIPCHK(hipMemcpyAsync(h_out, d, sizeof(float) * 3 * (size_t)g->n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h_out, d, bytes, hipMemcpyDeviceToHost, st));
         HIPCHK(hipFreeAsync(d, st));
     }
     HIPCHK(hipStreamSynchronize(st));

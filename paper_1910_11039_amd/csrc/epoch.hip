@@ -268,7 +268,8 @@ __global__ void k_argmax_degree(DevGraph g, unsigned long long *best)
     unsigned long long b = 0;
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x) {
         const unsigned long long deg = (unsigned long long)(g.rp[v + 1] - g.rp[v]);
-        const unsigned long long key = (deg << 32) | (0xFFFFFFFFull - (unsigned long long)v);
+        // ties go to the smallest caller id
+        const unsigned long long key = (deg << 32) | (0xFFFFFFFFull - (unsigned long long)g.orig[v]);
         b = key > b ? key : b;
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -290,11 +291,12 @@ __global__ void k_bfs_init(int32_t n, int32_t *dist, int32_t src, int32_t *fr, i
     }
 }
 
-__global__ void k_min_at_depth(int32_t n, const int32_t *dist, int32_t depth, int32_t *out)
+// Smallest caller id among the vertices at `depth`.
+__global__ void k_min_at_depth(int32_t n, const int32_t *dist, const int32_t *orig, int32_t depth, int32_t *out)
 {
     int32_t b = 0x7fffffff;
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        if (dist[v] == depth && v < b) b = v;
+        if (dist[v] == depth && orig[v] < b) b = orig[v];
     if (b != 0x7fffffff) atomicMin(out, b);
 }
 
@@ -756,7 +758,12 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
     unsigned long long hb = 0;
     CK(hipMemcpyAsync(&hb, best, sizeof(hb), hipMemcpyDeviceToHost, st));
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    const int32_t r = (int32_t)(0xFFFFFFFFull - (hb & 0xFFFFFFFFull));
+    int32_t r = 0;     // internal id of the caller-smallest vertex of maximum degree
+    {
+        const int32_t r_caller = (int32_t)(0xFFFFFFFFull - (hb & 0xFFFFFFFFull));
+        CK(hipMemcpyAsync(&r, g.newid + r_caller, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    }
 
     // Direction-optimising BFS enqueued in batches of steps; the host only
     // looks at the frontier size between batches.
@@ -794,9 +801,12 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
         *ecc = hs[3];
         int32_t init = 0x7fffffff;
         CK(hipMemcpyAsync(sizes + 4, &init, sizeof(int32_t), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_min_at_depth, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, dist, *ecc,
+        hipLaunchKernelGGL(k_min_at_depth, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, dist, g.orig, *ecc,
                            sizes + 4);
-        CK(hipMemcpyAsync(far, sizes + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        int32_t far_caller = 0;
+        CK(hipMemcpyAsync(&far_caller, sizes + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        CK(hipMemcpyAsync(far, g.newid + far_caller, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         return hipStreamSynchronize(st);
     };
     int32_t er, ea, eb, a, b, cfar;

@@ -44,12 +44,39 @@ struct SampleStats {
     int pad[3];
 };
 
+// The graph as the kernels see it.  Vertices are renumbered at upload in
+// descending degree (ties: ascending caller id), so that the visited-state
+// records of the hubs, which most adjacency probes reach, share a few cache
+// lines, and a wave's probes along a sorted row fall on neighbouring
+// records.  Two copies of the adjacency:
+//  * ci:  every row in ascending internal id (set-valued work: expansion,
+//         integer path counts, adjacency tests, BFS);
+//  * cci: every row in the caller's order, ascending caller id (steps whose
+//         result depends on the order: predecessor picks, FP sums).
+// Every rule that orders vertices by id compares caller ids (orig), so
+// results are those of the caller's numbering.
 struct DevGraph {
     int32_t n;
     int64_t nnz;
     const int64_t *rp;
     const int32_t *ci;
+    const int32_t *orig;    // internal id -> caller id
+    const int32_t *newid;   // caller id -> internal id
+    const int32_t *cci;
 };
+
+// Relabelled CSR from the caller's (device) CSR: row i of the output is
+// row orig[i] of the input with every entry mapped through newid.
+hipError_t launch_relabel_rows(int32_t n, const int64_t *rp_in, const int32_t *ci_in, const int32_t *orig,
+                               const int32_t *newid, const int64_t *rp_out, int32_t *ci_out, hipStream_t st);
+// Per-vertex arrays between the two numberings: to_caller writes
+// out[orig[i]] = in[i]; from_caller writes out[i] = in[orig[i]].
+// Sorts every row of a CSR (int32 entries) into ascending order.
+hipError_t sort_rows(int32_t n, int64_t nnz, const int64_t *rp, const int32_t *in, int32_t *out, hipStream_t st);
+hipError_t launch_to_caller_u32(int32_t n, const int32_t *orig, const uint32_t *in, uint32_t *out, hipStream_t st);
+hipError_t launch_to_caller_f64(int32_t n, const int32_t *orig, const double *in, double *out, hipStream_t st);
+hipError_t launch_to_caller_f32x3(int32_t n, const int32_t *orig, const float *in, float *out, hipStream_t st);
+hipError_t launch_from_caller_f64(int32_t n, const int32_t *orig, const double *in, double *out, hipStream_t st);
 
 // Arguments of one sampler launch.
 struct SampleLaunch {

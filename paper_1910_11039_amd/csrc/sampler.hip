@@ -369,7 +369,7 @@ __device__ void expand_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t 
             int32_t w[V];
             uint64_t kk[V];
 #pragma unroll
-            for (int j = 0; j < V; ++j) w[j] = j < m ? c.g.ci[e0 + j] : 0;
+            for (int j = 0; j < V; ++j) w[j] = j < m ? c.g.cci[e0 + j] : 0;
 #pragma unroll
             for (int j = 0; j < V; ++j) kk[j] = j < m ? ld_key(c.R + w[j]) : 0ull;
             uint32_t pred = 0;
@@ -597,7 +597,7 @@ __device__ void meet_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t 
         dsum += (uint64_t)(c.g.rp[w + 1] - c.g.rp[w]);
         if (!foldX) accX[i] = 0;
         accY[i] = 0;
-        if (path == 0) sm.m.id[i] = w;
+        if (path == 0) sm.m.id[i] = c.g.orig[w];
     }
     const uint64_t dM = block_sum_u64<BS>(sm, dsum);
     const int Y = 1 - X;
@@ -632,7 +632,7 @@ __device__ void meet_weights_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, i
         const int32_t w = c.MB[i];
         double ax = 0.0, ay = 0.0;
         for (int64_t e = c.g.rp[w]; e < c.g.rp[w + 1]; ++e) {
-            const int32_t x = c.g.ci[e];
+            const int32_t x = c.g.cci[e];
             Rec *r = c.R + x;
             const uint64_t kk = ld_key(r);
             if ((uint32_t)(kk >> 32) != c.cur) continue;
@@ -646,7 +646,8 @@ __device__ void meet_weights_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, i
     (void)sm;
 }
 
-// Smallest meet-list id above `last` (all threads call; uniform result).
+// Smallest caller id of the meet list above `last` (all threads call;
+// uniform result).
 template <int BS>
 __device__ int32_t next_min(Smem<BS> &sm, const Ctx &c, int32_t m, int32_t last)
 {
@@ -654,7 +655,7 @@ __device__ int32_t next_min(Smem<BS> &sm, const Ctx &c, int32_t m, int32_t last)
     __syncthreads();
     int32_t best = 0x7fffffff;
     for (int32_t i = threadIdx.x; i < m; i += BS) {
-        const int32_t id = c.MB[i];
+        const int32_t id = c.g.orig[c.MB[i]];
         if (id > last && id < best) best = id;
     }
     if (best != 0x7fffffff) atomicMin(&sm.wmin, best);
@@ -675,7 +676,7 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
         if (c.fp) {   // integer mode filled ids and weights in LDS already
             for (int32_t i = tid; i < m; i += BS) {
                 const int32_t w = c.MB[i];
-                sm.m.id[i] = w;
+                sm.m.id[i] = c.g.orig[w];
                 sm.m.w[i] = ld_sig(c.R + w);
             }
         }
@@ -696,7 +697,7 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
                 myw[j] = sm.m.w[i];
             }
         }
-        // rank (and, in integer mode, exclusive prefix) in ascending id
+        // rank (and, in integer mode, exclusive prefix) in ascending caller id
         for (int32_t jj = 0; jj < m; ++jj) {
             const int32_t idj = sm.m.id[jj];
             const uint64_t wj = sm.m.w[jj];
@@ -712,7 +713,7 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
             const uint64_t r = __umul64hi(u2, (uint64_t)sm.sigst);
 #pragma unroll
             for (int j = 0; j < PER; ++j)
-                if (myid[j] >= 0 && mypre[j] <= r && r - mypre[j] < myw[j]) sm.w = myid[j];
+                if (myid[j] >= 0 && mypre[j] <= r && r - mypre[j] < myw[j]) sm.w = c.g.newid[myid[j]];
             __syncthreads();
             return;
         }
@@ -737,14 +738,15 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
                 if (a != 0.0) pick = sm.m.id[i];
                 if (pre > r) { pick = sm.m.id[i]; break; }
             }
-            sm.w = pick;
+            sm.w = pick >= 0 ? c.g.newid[pick] : pick;
         }
         __syncthreads();
         return;
     }
-    // Large meet sets, integer mode: the chosen vertex is the smallest id x
-    // at which the weight of the meet vertices with id <= x exceeds r;
-    // binary search over the id range, one block-wide sum per step.
+    // Large meet sets, integer mode: the chosen vertex is the smallest
+    // caller id x at which the weight of the meet vertices with caller id
+    // <= x exceeds r; binary search over the id range, one block-wide sum
+    // per step.
     if (!c.fp) {
         const uint64_t r = __umul64hi(u2, (uint64_t)sm.sigst);
         const bool global_w = sm.mpath == 1;    // weights in the slot buffer, else in sigma fields
@@ -753,13 +755,13 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
             const int32_t mid = lo + ((hi - lo) >> 1);
             uint64_t part = 0;
             for (int32_t i = tid; i < m; i += BS) {
-                const int32_t id = c.MB[i];
-                if (id <= mid) part += global_w ? (uint64_t)gacc[i] : ld_sig(c.R + id);
+                const int32_t w = c.MB[i];
+                if (c.g.orig[w] <= mid) part += global_w ? (uint64_t)gacc[i] : ld_sig(c.R + w);
             }
             const uint64_t tot = block_sum_u64<BS>(sm, part);
             if (tot > r) hi = mid; else lo = mid + 1;
         }
-        if (tid == 0) sm.w = lo;
+        if (tid == 0) sm.w = c.g.newid[lo];
         __syncthreads();
         return;
     }
@@ -768,7 +770,7 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
     double tot = 0.0;
     for (int32_t step = 0, last = -1; step < m; ++step) {
         const int32_t id = next_min<BS>(sm, c, m, last);
-        tot = tot + as_f64(ld_sig(c.R + id));
+        tot = tot + as_f64(ld_sig(c.R + c.g.newid[id]));
         last = id;
     }
     const double r = unit53(u2) * tot;
@@ -776,13 +778,13 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
     int32_t pick = -1;
     for (int32_t step = 0, last = -1; step < m; ++step) {
         const int32_t id = next_min<BS>(sm, c, m, last);
-        const double a = as_f64(ld_sig(c.R + id));
+        const double a = as_f64(ld_sig(c.R + c.g.newid[id]));
         pre = pre + a;
         if (a != 0.0) pick = id;
         if (pre > r) { pick = id; break; }
         last = id;
     }
-    if (tid == 0) sm.w = pick;
+    if (tid == 0) sm.w = pick >= 0 ? c.g.newid[pick] : pick;
     __syncthreads();
 }
 
@@ -797,7 +799,7 @@ __device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint6
             const int64_t e = c0 + lane;
             uint64_t wt = 0;
             if (e < end) {
-                Rec *r = c.R + c.g.ci[e];
+                Rec *r = c.R + c.g.cci[e];
                 const uint64_t kk = ld_key(r);
                 if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) wt = ld_sig(r);
             }
@@ -810,7 +812,7 @@ __device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint6
             uint64_t wt = 0;
             int32_t x = -1;
             if (e < end) {
-                x = c.g.ci[e];
+                x = c.g.cci[e];
                 Rec *rc = c.R + x;
                 const uint64_t kk = ld_key(rc);
                 if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) wt = ld_sig(rc);
@@ -828,7 +830,7 @@ __device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint6
         double wt = 0.0;
         bool cand = false;
         if (e < end) {
-            Rec *r = c.R + c.g.ci[e];
+            Rec *r = c.R + c.g.cci[e];
             const uint64_t kk = ld_key(r);
             if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) {
                 cand = true;
@@ -851,7 +853,7 @@ __device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint6
         bool cand = false;
         int32_t x = -1;
         if (e < end) {
-            x = c.g.ci[e];
+            x = c.g.cci[e];
             Rec *rc = c.R + x;
             const uint64_t kk = ld_key(rc);
             if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) {
@@ -914,7 +916,7 @@ __device__ int32_t pick_pred_layer(Smem<BS> &sm, const Ctx &c, int side, int32_t
         if (ncand + k > BS) return -2;
         if (cand) {
             const int32_t slot = ncand + (int32_t)mbcnt(cm);
-            sm.e.u[slot] = x;
+            sm.e.u[slot] = c.g.orig[x];    // ranked by caller id (= CSR order)
             sm.e.acc[slot] = wt;
         }
         ncand += k;
@@ -941,7 +943,7 @@ __device__ int32_t pick_pred_layer(Smem<BS> &sm, const Ctx &c, int side, int32_t
     }
     __builtin_amdgcn_wave_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    return pick;
+    return pick >= 0 ? c.g.newid[pick] : pick;
 }
 
 template <int BS>
@@ -989,8 +991,8 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
             const int32_t s = (int32_t)__umul64hi(u0, (uint64_t)n);
             int32_t t = (int32_t)__umul64hi(u1, (uint64_t)(n - 1));
             if (t >= s) t += 1;
-            sm.s = s;
-            sm.t = t;
+            sm.s = a.g.newid[s];   // the pair is drawn in caller ids
+            sm.t = a.g.newid[t];
         }
         uint64_t t_exp = 0, t_mw = 0, t_ch = 0, t_walk = 0, t_mark = 0;
         int X = 0;
@@ -1122,9 +1124,9 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                 else if (lane == 0) a.stats->error = 2;
             }
             if (prow && lane == 0) {
-                prow[0] = s;
-                prow[d] = t;
-                prow[dep[0]] = w;
+                prow[0] = a.g.orig[s];
+                prow[d] = a.g.orig[t];
+                prow[dep[0]] = a.g.orig[w];
             }
             unsigned long long cnt = 0;
             if (w != s && w != t) {
@@ -1152,7 +1154,7 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                     }
                     if (lane == 0) {
                         atomicAdd(sf + p, 1u);
-                        if (prow) prow[side == 0 ? (l - 1) : (d - (l - 1))] = p;
+                        if (prow) prow[side == 0 ? (l - 1) : (d - (l - 1))] = a.g.orig[p];
                     }
                     cnt += 1;
                     v = p;
@@ -1160,10 +1162,10 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
             }
             if (lane == 0 && a.info) {
                 int64_t *inf = a.info + (size_t)sid * KAD_INFO_WIDTH;
-                inf[0] = s;
-                inf[1] = t;
+                inf[0] = a.g.orig[s];
+                inf[1] = a.g.orig[t];
                 inf[2] = d;
-                inf[3] = w;
+                inf[3] = a.g.orig[w];
                 inf[4] = fp;
                 inf[5] = m;
                 inf[6] = steps;
