@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 METRIC = "samples/s + time-to-stop at eps=0.01,delta=0.1; learned vs plain delta alloc"
 HBM_PEAK_GBS = 8000.0
 
+# epoch size fixed by a workload's configuration (others: autotuned)
+FIXED_EPOCH = {"er2048": 1024}
+
 WORKLOADS = {
     # name: (graphgen workload, eps, description)
     "rmat20": ("rmat20", 0.005, "R-MAT scale 20, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), "
@@ -52,19 +55,29 @@ def algorithmic_bytes(r) -> int:
                + 4 * r["path_vertices"])
 
 
-def counter_traffic(workload: str, epoch_size: int):
+def csrc_sha256() -> str:
+    """Hash of the native sources (every file of csrc/, in name order)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1910_11039_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".cpp", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()
+
+
+def counter_traffic(workload: str, epoch_size: int, block: int):
     """HBM bytes per sampler dispatch from the committed rocprofv3 counter
     profile (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or None when
-    the sampler source has changed since the counters were taken, or the
+    the native sources have changed since the counters were taken, or the
     launch configuration differs."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"k_sample_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     prof = json.load(open(path))
-    src = os.path.join(ROOT, "paper_1910_11039_amd", "csrc", "sampler.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if sha != prof.get("sampler_hip_sha256") or prof.get("epoch_size") != epoch_size:
+    if (prof.get("csrc_sha256") != csrc_sha256() or prof.get("epoch_size") != epoch_size
+            or prof.get("block_size") != block):
         return None
     return float(prof["traffic_bytes_per_dispatch"])
 
@@ -118,6 +131,8 @@ def main():
     g = gg.workload(wname)
     ctx = K.Context(0)
     G = K.Graph(ctx, g)
+    if args.epoch_size == 0:
+        args.epoch_size = FIXED_EPOCH.get(args.workload, 0)
     S = K.Sampler(G, seed=1, epsilon=eps, delta=0.1, timing=0 if args.use_graphs else 1,
                   use_graphs=args.use_graphs, epoch_size=args.epoch_size, slots=args.slots,
                   block_size=args.block)
@@ -150,7 +165,7 @@ def main():
         per_launch_bytes = algorithmic_bytes(agg) / agg["sample_launches"]
         per_launch_s = agg["t_sample_kernel_ms"] / 1e3 / agg["sample_launches"]
         achieved = per_launch_bytes / per_launch_s / 1e9
-        traffic = counter_traffic(args.workload, results[0]["epoch_size"])
+        traffic = counter_traffic(args.workload, results[0]["epoch_size"], results[0]["block_size"])
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": None if traffic is None else round(traffic),

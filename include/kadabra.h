@@ -98,7 +98,7 @@ typedef struct {
     uint64_t seed;                /* Philox seed                                  */
     double epsilon;               /* additive error bound, Sec. I                 */
     double delta;                 /* failure probability, Sec. I                  */
-    uint32_t epoch_size;          /* samples per epoch; 0 = autotune (four rounds */
+    uint32_t epoch_size;          /* samples per epoch; 0 = autotune (eight rounds*/
                                   /* of the slot wave, within [256, 16384])       */
     int32_t alloc_mode;           /* KAD_ALLOC_*                                  */
     double omega_override;        /* > 0: use this omega instead of computing it  */

@@ -56,7 +56,8 @@ struct kad_graph {
     int32_t *d_orig;     // internal id -> caller id
     int32_t *d_newid;    // caller id -> internal id
     int32_t *d_cci;      // rows in the caller's order
-    DevGraph dev() const { return DevGraph{n, nnz, d_rp, d_ci, d_orig, d_newid, d_cci}; }
+    uint32_t *d_deg;
+    DevGraph dev() const { return DevGraph{n, nnz, d_rp, d_ci, d_orig, d_newid, d_cci, d_deg}; }
 };
 
 struct kad_sampler {
@@ -98,6 +99,12 @@ struct kad_sampler {
     double C;
     std::vector<float> mlp_params, mlp_norm;
     bool have_mlp;
+    // the learned prior's network output, computed on `aux` while the
+    // bracket's BFS runs (it does not depend on omega)
+    hipStream_t aux;
+    hipEvent_t ev_aux;
+    float *yhat;
+    bool yhat_pending;
     kad_result res;
     double t_kernel_ms;
     uint32_t launches;
@@ -138,10 +145,10 @@ extern "C" kad_status kad_create(int device, void *hip_stream, kad_ctx **out)
 extern "C" void kad_destroy(kad_ctx *ctx)
 {
     if (!ctx) return;
-    hipSetDevice(ctx->device);
+    (void)hipSetDevice(ctx->device);
     if (ctx->own_stream) {
-        hipStreamSynchronize(ctx->stream);
-        hipStreamDestroy(ctx->stream);
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipStreamDestroy(ctx->stream);
     }
     delete ctx;
 }
@@ -216,15 +223,17 @@ extern "C" kad_status kad_graph_upload(kad_ctx *ctx, int32_t n, int64_t nnz, con
         hipMalloc((void **)&g->d_orig, sizeof(int32_t) * (size_t)n) != hipSuccess ||
         hipMalloc((void **)&g->d_newid, sizeof(int32_t) * (size_t)n) != hipSuccess ||
         hipMalloc((void **)&g->d_cci, ci_bytes) != hipSuccess ||
+        hipMalloc((void **)&g->d_deg, sizeof(uint32_t) * (size_t)n) != hipSuccess ||
         hipMalloc((void **)&t_rp, sizeof(int64_t) * ((size_t)n + 1)) != hipSuccess ||
         hipMalloc((void **)&t_ci, ci_bytes) != hipSuccess) {
-        hipFree(g->d_rp);
-        hipFree(g->d_ci);
-        hipFree(g->d_orig);
-        hipFree(g->d_newid);
-        hipFree(g->d_cci);
-        hipFree(t_rp);
-        hipFree(t_ci);
+        (void)hipFree(g->d_rp);
+        (void)hipFree(g->d_ci);
+        (void)hipFree(g->d_orig);
+        (void)hipFree(g->d_newid);
+        (void)hipFree(g->d_cci);
+        (void)hipFree(g->d_deg);
+        (void)hipFree(t_rp);
+        (void)hipFree(t_ci);
         delete g;
         return fail(KAD_ENOMEM, "graph allocation failed");
     }
@@ -239,6 +248,7 @@ extern "C" kad_status kad_graph_upload(kad_ctx *ctx, int32_t n, int64_t nnz, con
     HIPCHK(hipFree(t_rp));
     HIPCHK(hipFree(t_ci));
     if (nnz > 0) HIPCHK(sort_rows(n, nnz, g->d_rp, g->d_cci, g->d_ci, st));
+    HIPCHK(launch_degrees(n, g->d_rp, g->d_deg, st));
     HIPCHK(hipStreamSynchronize(st));
     *out = g;
     return KAD_OK;
@@ -247,12 +257,13 @@ extern "C" kad_status kad_graph_upload(kad_ctx *ctx, int32_t n, int64_t nnz, con
 extern "C" void kad_graph_free(kad_graph *g)
 {
     if (!g) return;
-    hipSetDevice(g->device);
-    hipFree(g->d_rp);
-    hipFree(g->d_ci);
-    hipFree(g->d_orig);
-    hipFree(g->d_newid);
-    hipFree(g->d_cci);
+    (void)hipSetDevice(g->device);
+    (void)hipFree(g->d_rp);
+    (void)hipFree(g->d_ci);
+    (void)hipFree(g->d_orig);
+    (void)hipFree(g->d_newid);
+    (void)hipFree(g->d_cci);
+    (void)hipFree(g->d_deg);
     delete g;
 }
 
@@ -279,27 +290,35 @@ extern "C" kad_status kad_vd_bracket(kad_ctx *ctx, const kad_graph *g, int64_t *
     return KAD_OK;
 }
 
+static kad_status enqueue_network(kad_sampler *s, hipStream_t st);
+
 static void free_sampler(kad_sampler *s)
 {
-    if (s->have_graph) hipGraphExecDestroy(s->gexec);
-    for (hipEvent_t e : s->ev_ring) hipEventDestroy(e);
-    for (hipEvent_t e : s->ev_merge) if (e) hipEventDestroy(e);
-    for (int i = 1; i < 4; ++i) if (s->sts[i]) hipStreamDestroy(s->sts[i]);
-    if (s->h_status) hipHostFree(s->h_status);
+    if (s->have_graph) (void)hipGraphExecDestroy(s->gexec);
+    for (hipEvent_t e : s->ev_ring) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->ev_merge) if (e) (void)hipEventDestroy(e);
+    for (int i = 1; i < 4; ++i) if (s->sts[i]) (void)hipStreamDestroy(s->sts[i]);
+    if (s->aux) {
+        (void)hipStreamSynchronize(s->aux);
+        (void)hipStreamDestroy(s->aux);
+    }
+    if (s->ev_aux) (void)hipEventDestroy(s->ev_aux);
+    if (s->yhat) (void)hipFree(s->yhat);
+    if (s->h_status) (void)hipHostFree(s->h_status);
     void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->sf[2], s->sf[3], s->cprime, s->scratch_counts, s->LL, s->LU, s->lo_hi, s->macc,
                     s->partials, s->prior, s->recs, s->queues, s->mbufs, s->stamps, s->work_ctr,
                     s->stats, s->es, s->hist};
     for (void *p : ptrs)
-        if (p) hipFree(p);
-    if (s->h_es) hipHostFree(s->h_es);
+        if (p) (void)hipFree(p);
+    if (s->h_es) (void)hipHostFree(s->h_es);
     delete s;
 }
 
 extern "C" void kad_sampler_free(kad_sampler *s)
 {
     if (!s) return;
-    hipSetDevice(s->device);
-    hipDeviceSynchronize();
+    (void)hipSetDevice(s->device);
+    (void)hipDeviceSynchronize();
     free_sampler(s);
 }
 
@@ -365,16 +384,24 @@ static kad_status autotune(kad_sampler *s)
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             const double rate = (double)N / (ms * 1e-3);
             s->tune_rate[i] = rate;
-            if (rate > best) { best = rate; best_b = b; best_slots = sl; }
+            best = std::max(best, rate);
         }
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        // the largest block within 5% of the best rate: timing noise between
+        // near-equal shapes does not flip the choice from run to run
+        for (int i = 0; i < 3; ++i) {
+            if (s->tune_rate[i] >= 0.95 * best) {
+                best_b = cands[i];
+                best_slots = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(cands[i]));
+            }
+        }
         s->block = best_b;
         s->slots = best_slots;
         HIPCHK(hipMemsetAsync(s->stats, 0, sizeof(SampleStats), st));
     }
     if (s->E == 0) {
-        uint64_t E = 4ull * (uint64_t)s->slots;
+        uint64_t E = 8ull * (uint64_t)s->slots;   // eight rounds of the slot wave
         E = (E + 255) / 256 * 256;
         s->E = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(E, 256), 16384);
     }
@@ -495,6 +522,8 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     }
     s->ev_ring.resize(std::max(s->inflight, s->P) + 1);
     for (auto &e : s->ev_ring) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipStreamCreate(&s->aux));
+    HIPCHK(hipEventCreateWithFlags(&s->ev_aux, hipEventDisableTiming));
     HIPCHK(hipMemsetAsync(s->recs, 0, sizeof(Rec) * (size_t)n * s->P * s->slots, st));
     HIPCHK(hipMemsetAsync(s->stamps, 0, 4ull * s->P * s->slots, st));
     kad_status rs = autotune(s);
@@ -519,6 +548,14 @@ extern "C" kad_status kad_sampler_reset(kad_sampler *s, uint64_t seed)
     HIPCHK(hipStreamSynchronize(st));
     s->o.seed = seed;
     const double t0 = now_ms();
+    if (s->o.alloc_mode == KAD_ALLOC_LEARNED && s->have_mlp) {
+        // the network does not need omega: run it beside the bracket's BFS
+        HIPCHK(hipStreamSynchronize(s->aux));
+        kad_status r = enqueue_network(s, s->aux);
+        if (r != KAD_OK) return r;
+        HIPCHK(hipEventRecord(s->ev_aux, s->aux));
+        s->yhat_pending = true;
+    }
     if (!(s->o.omega_override > 0.0)) {
         HIPCHK(device_vd_bracket(s->g->dev(), st, &s->vd_lo, &s->vd_hi));
         const double om = kad_omega(s->vd_lo, s->vd_hi, s->o.epsilon, s->o.delta);
@@ -628,32 +665,50 @@ extern "C" kad_status kad_set_delta(kad_sampler *s, const double *h_delta_L, con
 extern "C" kad_status kad_set_mlp_weights(kad_sampler *s, const float *h_params, const float *h_norm)
 {
     if (!s || !h_params || !h_norm) return fail(KAD_EINVAL, "null argument");
+    if (s->aux) HIPCHK(hipStreamSynchronize(s->aux));   // a pending output used the old weights
+    s->yhat_pending = false;
     s->mlp_params.assign(h_params, h_params + 4481);
     s->mlp_norm.assign(h_norm, h_norm + 6);
     s->have_mlp = true;
     return KAD_OK;
 }
 
-// Learned prior: features -> standardise -> MLP -> b_hat = max(0, e^y - 1/omega).
-static kad_status learned_prior(kad_sampler *s)
+// Network output of the learned prior, y = MLP(standardised features),
+// enqueued on stream `st` into s->yhat.
+static kad_status enqueue_network(kad_sampler *s, hipStream_t st)
 {
-    hipStream_t st = s->ctx->stream;
     const int32_t n = s->g->n;
-    float *feat = nullptr, *params = nullptr, *norm = nullptr, *yhat = nullptr;
+    if (!s->yhat && hipMalloc((void **)&s->yhat, sizeof(float) * (size_t)n) != hipSuccess)
+        return fail(KAD_ENOMEM, "network output allocation failed");
+    float *feat = nullptr, *params = nullptr, *norm = nullptr;
     HIPCHK(hipMallocAsync((void **)&feat, sizeof(float) * 3 * (size_t)n, st));
-    HIPCHK(hipMallocAsync((void **)&yhat, sizeof(float) * (size_t)n, st));
     HIPCHK(hipMallocAsync((void **)&params, sizeof(float) * 4481, st));
     HIPCHK(hipMallocAsync((void **)&norm, sizeof(float) * 6, st));
     HIPCHK(hipMemcpyAsync(params, s->mlp_params.data(), sizeof(float) * 4481, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(norm, s->mlp_norm.data(), sizeof(float) * 6, hipMemcpyHostToDevice, st));
     HIPCHK(launch_features(s->g->dev(), feat, st));
     HIPCHK(launch_normalize(n, feat, norm, st));
-    HIPCHK(launch_mlp_forward(params, feat, n, yhat, st));
-    HIPCHK(launch_prior_from_mlp(n, yhat, s->omega, s->prior, st));
+    HIPCHK(launch_mlp_forward(params, feat, n, s->yhat, st));
     HIPCHK(hipFreeAsync(feat, st));
-    HIPCHK(hipFreeAsync(yhat, st));
     HIPCHK(hipFreeAsync(params, st));
     HIPCHK(hipFreeAsync(norm, st));
+    return KAD_OK;
+}
+
+// Learned prior: features -> standardise -> MLP -> b_hat = max(0, e^y - 1/omega).
+// The network part was started by the reset on the side stream when it
+// is pending; otherwise it runs here.
+static kad_status learned_prior(kad_sampler *s)
+{
+    hipStream_t st = s->ctx->stream;
+    if (s->yhat_pending) {
+        HIPCHK(hipStreamWaitEvent(st, s->ev_aux, 0));
+        s->yhat_pending = false;
+    } else {
+        kad_status r = enqueue_network(s, st);
+        if (r != KAD_OK) return r;
+    }
+    HIPCHK(launch_prior_from_mlp(s->g->n, s->yhat, s->omega, s->prior, st));
     return KAD_OK;
 }
 
@@ -751,13 +806,14 @@ static kad_status enqueue_epoch_k(kad_sampler *s, unsigned long long k, hipEvent
     a.count = count;
     a.sf[0] = a.sf[1] = s->sf[p];
     a.stop_flag = &s->es->stopped;
-    HIPCHK(hipMemsetAsync(a.work_ctr, 0, sizeof(unsigned long long), st));
+    // the pool's sample counter is zero here: set by the reset, then cleared
+    // by the merge of this stream's previous epoch
     if (ev0) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_sampler(a, (int)std::min<unsigned long long>(s->slots, count), s->block, st));
     if (ev1) HIPCHK(hipEventRecord(ev1, st));
     if (k > 0) HIPCHK(hipStreamWaitEvent(st, s->ev_merge[(p + s->P - 1) % s->P], 0));
     HIPCHK(launch_merge_stop_impl(s->g->dev(), s->c, s->sf[p], s->sf[p], s->LL, s->LU, s->omega,
-                                  s->o.epsilon, s->cap, s->E, s->es, nullptr, s->hist, s->hist_cap,
+                                  s->o.epsilon, s->cap, s->E, s->es, a.work_ctr, s->hist, s->hist_cap,
                                   s->d_status, st));
     HIPCHK(hipEventRecord(s->ev_merge[p], st));
     HIPCHK(hipEventRecord(s->ev_ring[k % s->ev_ring.size()], st));
@@ -827,7 +883,7 @@ static kad_status build_graph(kad_sampler *s)
     for (int i = 0; i < s->inflight; ++i) {
         kad_status r = enqueue_epoch(s, nullptr, nullptr);
         if (r != KAD_OK) {
-            hipStreamEndCapture(st, &graph);
+            (void)hipStreamEndCapture(st, &graph);
             return r;
         }
     }
@@ -900,7 +956,7 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
             s->t_kernel_ms += ms;
             s->launches += 1;
         }
-        for (hipEvent_t e : evs) hipEventDestroy(e);
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
     }
     r = check_stats_error(s);
     if (r != KAD_OK) return r;
@@ -1095,8 +1151,8 @@ extern "C" kad_status kad_sample_paths(kad_sampler *s, uint64_t stream, uint64_t
         HIPCHK(hipMemcpyAsync(h_info, di, sizeof(int64_t) * (size_t)count * KAD_INFO_WIDTH,
                               hipMemcpyDeviceToHost, st));
     }
-    hipFreeAsync(dp, st);
-    hipFreeAsync(di, st);
+    (void)hipFreeAsync(dp, st);
+    (void)hipFreeAsync(di, st);
     HIPCHK(hipStreamSynchronize(st));
     if (r == KAD_OK) {
         int khz = 0;
@@ -1181,14 +1237,14 @@ extern "C" kad_status kad_mlp_create(kad_ctx *ctx, const float *h_params, kad_ml
 extern "C" void kad_mlp_free(kad_mlp *m)
 {
     if (!m) return;
-    hipSetDevice(m->device);
-    hipDeviceSynchronize();
-    hipFree(m->params);
-    hipFree(m->grad);
-    hipFree(m->m);
-    hipFree(m->v);
-    hipFree(m->loss);
-    if (m->scratch) hipFree(m->scratch);
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(m->params);
+    (void)hipFree(m->grad);
+    (void)hipFree(m->m);
+    (void)hipFree(m->v);
+    (void)hipFree(m->loss);
+    if (m->scratch) (void)hipFree(m->scratch);
     delete m;
 }
 
@@ -1205,7 +1261,7 @@ static kad_status mlp_scratch(kad_mlp *m, int64_t rows)
 {
     const size_t need = mlp_scratch_floats(rows);
     if (need > m->scratch_cap) {
-        if (m->scratch) hipFree(m->scratch);
+        if (m->scratch) (void)hipFree(m->scratch);
         m->scratch = nullptr;
         if (hipMalloc((void **)&m->scratch, need * sizeof(float)) != hipSuccess)
             return fail(KAD_ENOMEM, "mlp scratch allocation failed");

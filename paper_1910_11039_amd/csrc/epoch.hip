@@ -364,7 +364,7 @@ __global__ __launch_bounds__(1024) void k_bfs_small(DevGraph g, int32_t *dist, i
                 const int32_t w = g.ci[e];
                 if (atomicCAS(&dist[w], -1, depth + 1) == -1) {
                     nxt[atomicAdd(&s_next, 1)] = w;
-                    dsum += (unsigned long long)(g.rp[w + 1] - g.rp[w]);
+                    dsum += (unsigned long long)g.deg[w];
                 }
             }
         }
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(1024) void k_bfs_small(DevGraph g, int32_t *dist, i
                 const int32_t w = g.ci[e];
                 if (atomicCAS(&dist[w], -1, depth + 1) == -1) {
                     nxt[atomicAdd(&s_next, 1)] = w;
-                    dsum += (unsigned long long)(g.rp[w + 1] - g.rp[w]);
+                    dsum += (unsigned long long)g.deg[w];
                 }
             }
         }
@@ -434,7 +434,7 @@ __global__ void k_bfs_td(DevGraph g, int32_t *dist, int32_t *buf0, int32_t *buf1
             const int32_t w = g.ci[e];
             if (atomicCAS(&dist[w], -1, depth + 1) == -1) {
                 nxt[atomicAdd(&sz[1], 1)] = w;
-                dsum += (unsigned long long)(g.rp[w + 1] - g.rp[w]);
+                dsum += (unsigned long long)g.deg[w];
             }
         }
     }
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(256) void k_bfs_heavy(DevGraph g, int32_t *dist, co
                 const int32_t w = g.ci[e];
                 if (atomicCAS(&dist[w], -1, depth + 1) == -1) {
                     nxt[atomicAdd(&sz[1], 1)] = w;
-                    dsum += (unsigned long long)(g.rp[w + 1] - g.rp[w]);
+                    dsum += (unsigned long long)g.deg[w];
                 }
             }
         }

@@ -25,6 +25,12 @@ __global__ void k_relabel_rows(int32_t n, const int64_t *rp_in, const int32_t *c
     }
 }
 
+__global__ void k_degrees(int32_t n, const int64_t *rp, uint32_t *deg)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        deg[v] = (uint32_t)(rp[v + 1] - rp[v]);
+}
+
 template <typename T>
 __global__ void k_to_caller(int32_t n, const int32_t *orig, const T *in, T *out)
 {
@@ -77,6 +83,12 @@ hipError_t sort_rows(int32_t n, int64_t nnz, const int64_t *rp, const int32_t *i
     e = hipcub::DeviceSegmentedSort::SortKeys(tmp, bytes, in, out, (int)nnz, (int)n, rp, rp + 1, st);
     const hipError_t f = hipFreeAsync(tmp, st);
     return e != hipSuccess ? e : f;
+}
+
+hipError_t launch_degrees(int32_t n, const int64_t *rp, uint32_t *deg, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_degrees, dim3(blocks_for(n)), dim3(256), 0, st, n, rp, deg);
+    return hipGetLastError();
 }
 
 hipError_t launch_to_caller_u32(int32_t n, const int32_t *orig, const uint32_t *in, uint32_t *out, hipStream_t st)

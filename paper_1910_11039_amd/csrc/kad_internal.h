@@ -63,6 +63,7 @@ struct DevGraph {
     const int32_t *orig;    // internal id -> caller id
     const int32_t *newid;   // caller id -> internal id
     const int32_t *cci;
+    const uint32_t *deg;    // degree of every vertex (4 bytes: stays in cache)
 };
 
 // Relabelled CSR from the caller's (device) CSR: row i of the output is
@@ -71,6 +72,8 @@ hipError_t launch_relabel_rows(int32_t n, const int64_t *rp_in, const int32_t *c
                                const int32_t *newid, const int64_t *rp_out, int32_t *ci_out, hipStream_t st);
 // Per-vertex arrays between the two numberings: to_caller writes
 // out[orig[i]] = in[i]; from_caller writes out[i] = in[orig[i]].
+// deg[v] = rp[v + 1] - rp[v].
+hipError_t launch_degrees(int32_t n, const int64_t *rp, uint32_t *deg, hipStream_t st);
 // Sorts every row of a CSR (int32 entries) into ascending order.
 hipError_t sort_rows(int32_t n, int64_t nnz, const int64_t *rp, const int32_t *in, int32_t *out, hipStream_t st);
 hipError_t launch_to_caller_u32(int32_t n, const int32_t *orig, const uint32_t *in, uint32_t *out, hipStream_t st);

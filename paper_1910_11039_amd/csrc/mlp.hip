@@ -28,15 +28,10 @@ constexpr int NP = 4481;        // parameters
 constexpr int PSTRIDE = NP + 1; // per-block partial: gradient then loss
 constexpr int OFF_W1 = 0, OFF_B1 = 192, OFF_W2 = 256, OFF_B2 = 4352, OFF_W3 = 4416, OFF_B3 = 4480;
 
-__global__ void k_degrees(DevGraph g, uint32_t *deg)
-{
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * blockDim.x)
-        deg[v] = (uint32_t)(g.rp[v + 1] - g.rp[v]);
-}
-
-// The neighbour degrees are gathered from a 4-byte array (small enough to
-// stay in the last-level cache on large graphs) rather than from row_ptr.
-__global__ void k_features(DevGraph g, const uint32_t *deg, float *out)
+// The neighbour degrees are gathered from the graph's 4-byte degree array
+// (small enough to stay in the last-level cache on large graphs) rather
+// than from row_ptr.
+__global__ void k_features(DevGraph g, float *out)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -45,7 +40,7 @@ __global__ void k_features(DevGraph g, const uint32_t *deg, float *out)
         const int64_t beg = g.rp[v], end = g.rp[v + 1];
         double acc = 0.0, sd = 0.0;
         for (int64_t e = beg + lane; e < end; e += 64) {
-            const double du = (double)deg[g.ci[e]];
+            const double du = (double)g.deg[g.ci[e]];
             acc += log1p(du);
             sd += du;
         }
@@ -276,15 +271,9 @@ size_t mlp_scratch_floats(int64_t rows) { return (size_t)blocks_for_rows(rows) *
 
 hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st)
 {
-    uint32_t *deg = nullptr;
-    hipError_t e = hipMallocAsync((void **)&deg, sizeof(uint32_t) * (size_t)std::max<int32_t>(g.n, 1), st);
-    if (e != hipSuccess) return e;
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_degrees, dim3((unsigned)blocks), dim3(256), 0, st, g, deg);
     const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(g.n, 1 << 16));
-    hipLaunchKernelGGL(k_features, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, deg, out);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    return hipFreeAsync(deg, st);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_normalize(int32_t n, float *x, const float *norm, hipStream_t st)

@@ -124,7 +124,7 @@ struct Smem {
     int32_t loff[2][LMAX + 2];   // layer j of a side = queue positions [loff[j], loff[j+1])
     int32_t me_a[MEDGE];         // meet edges of the current chunk: owner index in the chunk,
     int32_t me_w[MEDGE];         // and the meet vertex
-    int32_t tail, mcount, ovf, err, w, wmin, mpath, nme, fold_bad;
+    int32_t tail, mcount, ovf, err, w, wmin, mpath, nme, fold_bad, pathc;
     uint32_t stamp;
     int32_t s, t;
 };
@@ -313,14 +313,8 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
                     }                                       // their sigma field holds the list position
                 }
             }
-            int64_t dlo[U], dhi[U];
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
-                dlo[j] = (disc >> j & 1) ? c.g.rp[w[j]] : 0;
-                dhi[j] = (disc >> j & 1) ? c.g.rp[w[j] + 1] : 0;
-            }
-#pragma unroll
-            for (int j = 0; j < U; ++j) nd += (unsigned long long)(dhi[j] - dlo[j]);
+            for (int j = 0; j < U; ++j) nd += (disc >> j & 1) ? (unsigned long long)c.g.deg[w[j]] : 0ull;
             ls.visited += __popc(disc);
         }
         __syncthreads();
@@ -386,7 +380,7 @@ __device__ void expand_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t 
                     }
                 } else if (cas_key(c.R + w[j], kk[j], newkey)) {
                     c.Q[qpos(n, X, atomicAdd(&sm.tail, 1))] = w[j];
-                    nd += (unsigned long long)(c.g.rp[w[j] + 1] - c.g.rp[w[j]]);
+                    nd += (unsigned long long)c.g.deg[w[j]];
                     ls.visited += 1;
                 }
             }
@@ -890,11 +884,12 @@ __device__ __forceinline__ bool row_contains(const DevGraph &g, int32_t row, int
 // are the vertices of layer l - 1 of `side` (queue positions [lo, hi))
 // adjacent to v, found by binary search in the shorter of the two rows;
 // the pick is the same as scanning v's row (ascending id = CSR order).
-// Wave 0 only; candidates go to the (idle) expansion LDS area.  Returns -2
-// when there are more candidates than fit (the caller scans v's row).
+// One wave; candidates go to its part [base, base + cap) of the (idle)
+// expansion LDS area.  Returns -2 when there are more candidates than fit
+// (the caller scans v's row).
 template <int BS>
 __device__ int32_t pick_pred_layer(Smem<BS> &sm, const Ctx &c, int side, int32_t v, int32_t lo,
-                                   int32_t hi, uint64_t u, int lane)
+                                   int32_t hi, uint64_t u, int lane, int32_t base, int32_t cap)
 {
     const int32_t n = c.g.n;
     const int64_t dv = c.g.rp[v + 1] - c.g.rp[v];
@@ -913,9 +908,9 @@ __device__ int32_t pick_pred_layer(Smem<BS> &sm, const Ctx &c, int side, int32_t
         }
         const uint64_t cm = __ballot(cand);
         const int32_t k = __popcll(cm);
-        if (ncand + k > BS) return -2;
+        if (ncand + k > cap) return -2;
         if (cand) {
-            const int32_t slot = ncand + (int32_t)mbcnt(cm);
+            const int32_t slot = base + ncand + (int32_t)mbcnt(cm);
             sm.e.u[slot] = c.g.orig[x];    // ranked by caller id (= CSR order)
             sm.e.acc[slot] = wt;
         }
@@ -931,11 +926,11 @@ __device__ int32_t pick_pred_layer(Smem<BS> &sm, const Ctx &c, int side, int32_t
         bool hit = false;
         int32_t id = -1;
         if (i < ncand) {
-            id = sm.e.u[i];
-            const uint64_t wi = sm.e.acc[i];
+            id = sm.e.u[base + i];
+            const uint64_t wi = sm.e.acc[base + i];
             uint64_t pre = 0;
             for (int32_t j = 0; j < ncand; ++j)
-                if (sm.e.u[j] < id) pre += sm.e.acc[j];
+                if (sm.e.u[base + j] < id) pre += sm.e.acc[base + j];
             hit = pre <= r && r - pre < wi;
         }
         const uint64_t hm = __ballot(hit);
@@ -1106,14 +1101,19 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
         }
         t_ch = wall_clock64() - t_mark;
         t_mark = wall_clock64();
-        // walk back and count (wave 0)
+        // walk back and count: the two sides are independent (their draw
+        // indices are fixed by the depths), so wave 0 walks to s and wave 1
+        // to t at the same time (one wave does both when BS is 64)
         const int32_t d = kX + 1 + kY;
         if (sm.w < 0) {   // no meet vertex chosen: report instead of walking
             if (tid == 0) a.stats->error = 3;
             __syncthreads();
             continue;
         }
-        if (wid == 0) {
+        if (tid == 0) sm.pathc = 0;
+        __syncthreads();
+        constexpr int WALKERS = BS >= 128 ? 2 : 1;
+        if (wid < WALKERS) {
             const int32_t s = sm.s, t = sm.t, w = sm.w;
             int32_t dep[2];
             dep[X] = kX + 1;
@@ -1123,20 +1123,24 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                 if (d + 1 <= a.max_len) prow = a.paths + (size_t)sid * (size_t)a.max_len;
                 else if (lane == 0) a.stats->error = 2;
             }
-            if (prow && lane == 0) {
-                prow[0] = a.g.orig[s];
-                prow[d] = a.g.orig[t];
-                prow[dep[0]] = a.g.orig[w];
-            }
             unsigned long long cnt = 0;
-            if (w != s && w != t) {
-                if (lane == 0) atomicAdd(sf + w, 1u);
-                cnt += 1;
+            if (wid == 0) {
+                if (prow && lane == 0) {
+                    prow[0] = a.g.orig[s];
+                    prow[d] = a.g.orig[t];
+                    prow[dep[0]] = a.g.orig[w];
+                }
+                if (w != s && w != t) {
+                    if (lane == 0) atomicAdd(sf + w, 1u);
+                    cnt += 1;
+                }
             }
             SampleDraws dr;
             dr.init(a.seed, a.stream, idx);
-            uint64_t j = 3;
-            for (int side = 0; side < 2; ++side) {
+            const int32_t cap = (int32_t)(sizeof(sm.e.u) / sizeof(sm.e.u[0])) / WALKERS;
+            for (int side = (WALKERS == 2 ? wid : 0); side < (WALKERS == 2 ? wid + 1 : 2); ++side) {
+                // draws 3, 4, ... go to the s side first, then to the t side
+                uint64_t j = 3 + (side == 1 ? (uint64_t)(dep[0] >= 2 ? dep[0] - 1 : 0) : 0);
                 int32_t v = w;
                 for (int32_t l = dep[side]; l >= 2; --l) {
                     const uint64_t u = dr.get(j++);
@@ -1145,7 +1149,7 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                         const int32_t llo = sm.loff[side][l - 1], lhi = sm.loff[side][l];
                         const int64_t dv = a.g.rp[v + 1] - a.g.rp[v];
                         if (2 * (int64_t)(lhi - llo) < dv)
-                            p = pick_pred_layer<BS>(sm, c, side, v, llo, lhi, u, lane);
+                            p = pick_pred_layer<BS>(sm, c, side, v, llo, lhi, u, lane, wid * cap, cap);
                     }
                     if (p == -2) p = pick_pred(c, side, v, l, u, lane);
                     if (p < 0) {   // no predecessor found: report, stop this walk
@@ -1160,12 +1164,17 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                     v = p;
                 }
             }
-            if (lane == 0 && a.info) {
+            if (lane == 0 && cnt) atomicAdd(&sm.pathc, (int32_t)cnt);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            st_path += (unsigned long long)sm.pathc;
+            if (a.info) {
                 int64_t *inf = a.info + (size_t)sid * KAD_INFO_WIDTH;
-                inf[0] = a.g.orig[s];
-                inf[1] = a.g.orig[t];
+                inf[0] = a.g.orig[sm.s];
+                inf[1] = a.g.orig[sm.t];
                 inf[2] = d;
-                inf[3] = a.g.orig[w];
+                inf[3] = a.g.orig[sm.w];
                 inf[4] = fp;
                 inf[5] = m;
                 inf[6] = steps;
@@ -1178,7 +1187,6 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                 inf[12] = (int64_t)t_ch;
                 inf[13] = (int64_t)t_walk;
             }
-            st_path += cnt;
         }
         st_edges += edges;
         st_fp += fp ? 1 : 0;
