@@ -98,8 +98,11 @@ typedef struct {
     uint64_t seed;                /* Philox seed                                  */
     double epsilon;               /* additive error bound, Sec. I                 */
     double delta;                 /* failure probability, Sec. I                  */
-    uint32_t epoch_size;          /* samples per epoch; 0 = autotune (eight rounds*/
-                                  /* of the slot wave, within [256, 16384])       */
+    uint32_t epoch_size;          /* samples per epoch; 0 = autotune: two rounds  */
+                                  /* of the slot wave when a sample takes a slot  */
+                                  /* over 10 ms at the trial's rate, else sixteen */
+                                  /* rounds but at most omega / 16; rounded up to */
+                                  /* a multiple of 256, within [256, 16384]       */
     int32_t alloc_mode;           /* KAD_ALLOC_*                                  */
     double omega_override;        /* > 0: use this omega instead of computing it  */
     int32_t sigma_mode;           /* KAD_SIGMA_*                                  */

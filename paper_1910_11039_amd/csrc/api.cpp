@@ -357,11 +357,17 @@ static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, ui
 // kept in [256, 16384]: long enough that an epoch's tail, overlapped with
 // the following epochs, costs little, short enough that the stop
 // overshoots tau by a few percent.
+static int cands_block(int i)
+{
+    static const int c[3] = {256, 512, 1024};
+    return c[i];
+}
+
 static kad_status autotune(kad_sampler *s)
 {
     hipStream_t st = s->ctx->stream;
     if (s->tune_block) {
-        const int cands[3] = {256, 512, 1024};
+        const int cands[3] = {cands_block(0), cands_block(1), cands_block(2)};
         double best = -1.0;
         int best_b = 256, best_slots = s->slots;
         hipEvent_t e0, e1;
@@ -388,20 +394,37 @@ static kad_status autotune(kad_sampler *s)
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        // the largest block within 5% of the best rate: timing noise between
-        // near-equal shapes does not flip the choice from run to run
-        for (int i = 0; i < 3; ++i) {
-            if (s->tune_rate[i] >= 0.95 * best) {
-                best_b = cands[i];
-                best_slots = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(cands[i]));
-            }
-        }
+        // the fastest shape, except that the 1024-thread one is kept when it
+        // is within 5% of the fastest: timing noise between near-equal
+        // shapes does not flip the choice from run to run
+        int pick = 0;
+        for (int i = 1; i < 3; ++i)
+            if (s->tune_rate[i] > s->tune_rate[pick]) pick = i;
+        if (s->tune_rate[2] >= 0.95 * best) pick = 2;
+        best_b = cands[pick];
+        best_slots = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(cands[pick]));
         s->block = best_b;
         s->slots = best_slots;
         HIPCHK(hipMemsetAsync(s->stats, 0, sizeof(SampleStats), st));
     }
     if (s->E == 0) {
-        uint64_t E = 8ull * (uint64_t)s->slots;   // eight rounds of the slot wave
+        // Long samples (a slot takes over 10 ms per sample at the trial's
+        // rate, as on high-diameter graphs) get two rounds of the slot wave
+        // per epoch, so the stop is not overshot by much.  Otherwise sixteen
+        // rounds, which amortise the merge and the epoch's tail, but at
+        // most omega / 16 samples so that the stop epoch's overshoot stays
+        // small against the run.
+        double rate = 0.0;
+        for (int i = 0; i < 3; ++i)
+            if (s->tune_block && cands_block(i) == s->block) rate = s->tune_rate[i];
+        const bool long_samples = rate > 0.0 && (double)s->slots / rate > 0.010;
+        uint64_t E;
+        if (long_samples) {
+            E = 2ull * (uint64_t)s->slots;
+        } else {
+            E = 16ull * (uint64_t)s->slots;
+            E = std::min<uint64_t>(E, (uint64_t)(s->omega / 16.0));
+        }
         E = (E + 255) / 256 * 256;
         s->E = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(E, 256), 16384);
     }
@@ -468,9 +491,15 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
         return fail(KAD_ENOMEM, "not even one sample slot fits the visited-state budget");
     }
     // pools: up to 4 while a full wave of slots fits each (epochs overlap
-    // across pools); a single pool when memory is tight
+    // across pools); when fewer than two full waves fit, two pools of half
+    // the slots (two concurrent epochs still cover every CU and fill each
+    // other's tails); a single pool only when even that does not fit
     s->slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)want, std::min<size_t>(fit, 1 << 16)));
     s->P = (int)std::max<size_t>(1, std::min<size_t>(4, fit / (size_t)s->slots));
+    if (s->P == 1 && o->slots <= 0 && o->pools != 1 && fit / 2 >= (size_t)std::max(1, ctx->cu_count / 2)) {
+        s->slots = (int)std::min<size_t>((size_t)s->slots, fit / 2);
+        s->P = 2;
+    }
     if (o->pools < 0 || o->pools > 4) {
         delete s;
         return fail(KAD_EINVAL, "pools must be 0 (auto) or 1..4");

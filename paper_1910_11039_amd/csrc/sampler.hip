@@ -787,6 +787,46 @@ __device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint6
 {
     const uint32_t want = ((uint32_t)side << X_SHIFT) | (uint32_t)(l - 1);
     const int64_t beg = c.g.rp[v], end = c.g.rp[v + 1];
+    if (end - beg <= 64) {
+        // a row that fits one wave: read once, total and pick from registers
+        const int64_t e = beg + lane;
+        int32_t x = -1;
+        uint64_t bits = 0;
+        bool cand = false;
+        if (e < end) {
+            x = c.g.cci[e];
+            Rec *r = c.R + x;
+            const uint64_t kk = ld_key(r);
+            if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) {
+                cand = true;
+                bits = ld_sig(r);
+            }
+        }
+        if (!c.fp) {
+            const uint64_t wt = cand ? bits : 0ull;
+            const uint64_t tot = wave_sum_u64(wt);
+            const uint64_t r = __umul64hi(u, tot);
+            const uint64_t incl = wave_incl_scan_u64(wt, lane);
+            const uint64_t hit = __ballot(wt != 0 && incl > r);
+            return hit ? __shfl(x, __ffsll((unsigned long long)hit) - 1) : -1;
+        }
+        const double wt = cand ? as_f64(bits) : 0.0;
+        const uint64_t mask = __ballot(cand);
+        double tot = 0.0;
+        for (uint64_t mm = mask; mm; mm &= mm - 1) tot = tot + __shfl(wt, __ffsll((unsigned long long)mm) - 1);
+        const double r = unit53(u) * tot;
+        double pre = 0.0;
+        int32_t last_nz = -1;
+        for (uint64_t mm = mask; mm; mm &= mm - 1) {
+            const int j = __ffsll((unsigned long long)mm) - 1;
+            const double a = __shfl(wt, j);
+            const int32_t xj = __shfl(x, j);
+            pre = pre + a;
+            if (a != 0.0) last_nz = xj;
+            if (pre > r) return xj;
+        }
+        return last_nz;
+    }
     if (!c.fp) {
         uint64_t tot = 0;
         for (int64_t c0 = beg; c0 < end; c0 += 64) {
@@ -941,8 +981,10 @@ __device__ int32_t pick_pred_layer(Smem<BS> &sm, const Ctx &c, int side, int32_t
     return pick >= 0 ? c.g.newid[pick] : pick;
 }
 
+// The 256-thread shape is held to three waves per SIMD (three workgroups
+// per CU): the high-diameter graphs depend on that many samples in flight.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
+__global__ __launch_bounds__(BS, (BS == 256 ? 3 : 1)) void k_sample(SampleLaunch a)
 {
     __shared__ Smem<BS> sm;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -1021,6 +1063,10 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                 sm.ovf = 0;
                 sm.err = 0;
                 sm.sigst = 0;
+                sm.tail = 1;          // set-up of the first step (both sides hold one vertex)
+                sm.mcount = 0;
+                sm.nextdeg = 0;
+                sm.fmax_bits = 0;
             }
             __syncthreads();
             c.cur = sm.stamp;
@@ -1033,14 +1079,8 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                 edges += (unsigned long long)sm.sdeg[X];
                 st_exp += (unsigned long long)(hi - lo);
                 steps += 1;
-                __syncthreads();
-                if (tid == 0) {
-                    sm.tail = hi;
-                    sm.mcount = 0;
-                    sm.nextdeg = 0;
-                    sm.fmax_bits = 0;
-                }
-                __syncthreads();
+                // tail, mcount, nextdeg and fmax_bits were set for this step
+                // by the previous step's bookkeeping (or the attempt's set-up)
                 t_mark = wall_clock64();
                 if (!fp) expand_int<BS>(sm, c, X, k, lo, hi, ls);
                 else expand_fp<BS>(sm, c, X, k, lo, hi, ls);
@@ -1066,6 +1106,12 @@ __global__ __launch_bounds__(BS) void k_sample(SampleLaunch a)
                     sm.dep[X] = k + 1;
                     sm.sdeg[X] = (int64_t)sm.nextdeg;
                     if (k + 2 <= LMAX + 1) sm.loff[X][k + 2] = sm.tail;
+                    // set up the next step
+                    const int nx = (sm.sdeg[0] <= sm.sdeg[1]) ? 0 : 1;
+                    sm.tail = sm.hi[nx];
+                    sm.mcount = 0;
+                    sm.nextdeg = 0;
+                    sm.fmax_bits = 0;
                 }
                 __syncthreads();
             }
