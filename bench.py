@@ -173,6 +173,8 @@ def main():
                 "launch_ms": round(per_launch_s * 1e3, 4),
                 "bytes_per_launch": int(per_launch_bytes)}
 
+    r0 = results[0]
+    S.close()          # frees the plain arm's visited state before the learned arm sizes its own
     learned = None
     if not args.no_learned:
         # the same runs with the learned delta allocation (committed network)
@@ -210,7 +212,6 @@ def main():
                "sample": f"first {n_s} samples of the adaptive stream (seed 1) on the same graph, "
                          f"oracle sample loop, one host thread, {t:.1f} s"}
 
-    r0 = results[0]
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -239,7 +240,6 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    S.close()
     G.close()
     ctx.close()
 

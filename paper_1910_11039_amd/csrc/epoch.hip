@@ -317,8 +317,8 @@ __global__ void k_min_at_depth(int32_t n, const int32_t *dist, const int32_t *or
 //   sz[11] the frontier's bitmap is in bits[k & 1]
 constexpr int32_t SMALL_V = 4096;         // single-workgroup levels: frontier size and
 constexpr int64_t SMALL_D = 16384;        // degree sum at most these
-constexpr int64_t HEAVY = 512;            // top-down rows longer than this are split
-constexpr int64_t PIECE = 2048;           // into pieces of this many entries
+constexpr int64_t HEAVY = 8192;           // top-down rows longer than this are split
+constexpr int64_t PIECE = 4096;           // into pieces of this many entries
 constexpr int SMALL_LONG = 2048;          // > SMALL_D / 33 rows longer than 32
 
 __device__ __forceinline__ int64_t sz_get64(const int32_t *sz, int i)
@@ -326,7 +326,17 @@ __device__ __forceinline__ int64_t sz_get64(const int32_t *sz, int i)
     return ((int64_t)sz[i + 1] << 32) | (uint32_t)sz[i];
 }
 
-__device__ __forceinline__ bool bfs_bottom_up(int32_t fsize, int32_t big_v) { return fsize >= big_v; }
+// A level goes bottom-up when its frontier is large in vertices or in
+// adjacency entries (then most unreached vertices find a parent in the
+// first few entries of their own rows).
+struct BfsLim {
+    int32_t big_v;   // frontier vertices
+    int64_t big_e;   // frontier adjacency entries
+};
+__device__ __forceinline__ bool bfs_bottom_up(const int32_t *sz, BfsLim L)
+{
+    return sz[0] >= L.big_v || sz_get64(sz, 5) >= L.big_e;
+}
 
 // Small frontiers, many levels in one launch: one workgroup, a thread per
 // frontier vertex for rows of up to 32 entries, a wave per longer row.
@@ -402,10 +412,10 @@ __global__ __launch_bounds__(1024) void k_bfs_small(DevGraph g, int32_t *dist, i
 
 // List the frontier from dist when the previous level was bottom-up.
 __global__ void k_bfs_collect(int32_t n, const int32_t *dist, int32_t *buf0, int32_t *buf1, int32_t *sz,
-                              int32_t big_v)
+                              BfsLim lim)
 {
     const int32_t fsize = sz[0], depth = sz[2];
-    if (fsize == 0 || sz[10] != 0 || bfs_bottom_up(fsize, big_v)) return;
+    if (fsize == 0 || sz[10] != 0 || bfs_bottom_up(sz, lim)) return;
     int32_t *cur = (depth & 1) ? buf1 : buf0;
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
         if (dist[v] == depth) cur[atomicAdd(&sz[4], 1)] = v;
@@ -414,10 +424,10 @@ __global__ void k_bfs_collect(int32_t n, const int32_t *dist, int32_t *buf0, int
 // One top-down level: a wave per frontier vertex; rows longer than HEAVY
 // are listed for k_bfs_heavy.
 __global__ void k_bfs_td(DevGraph g, int32_t *dist, int32_t *buf0, int32_t *buf1, int32_t *heavy, int32_t *sz,
-                         int32_t big_v)
+                         BfsLim lim)
 {
     const int32_t fsize = sz[0], depth = sz[2];
-    if (fsize == 0 || bfs_bottom_up(fsize, big_v)) return;
+    if (fsize == 0 || bfs_bottom_up(sz, lim)) return;
     const int32_t *cur = (depth & 1) ? buf1 : buf0;
     int32_t *nxt = (depth & 1) ? buf0 : buf1;
     const int lane = threadIdx.x & 63;
@@ -447,12 +457,12 @@ __global__ void k_bfs_td(DevGraph g, int32_t *dist, int32_t *buf0, int32_t *buf1
 // every workgroup stages the same 256 rows with the prefix of their piece
 // counts and then handles pieces blockIdx.x, blockIdx.x + gridDim.x, ...
 __global__ __launch_bounds__(256) void k_bfs_heavy(DevGraph g, int32_t *dist, const int32_t *heavy,
-                                                   int32_t *buf0, int32_t *buf1, int32_t *sz, int32_t big_v)
+                                                   int32_t *buf0, int32_t *buf1, int32_t *sz, BfsLim lim)
 {
     __shared__ int64_t s_beg[256], s_end[256], s_pre[257];
     __shared__ int64_t s_wsum[4];
     const int32_t fsize = sz[0], depth = sz[2], nh = sz[7];
-    if (fsize == 0 || bfs_bottom_up(fsize, big_v) || nh == 0) return;
+    if (fsize == 0 || bfs_bottom_up(sz, lim) || nh == 0) return;
     int32_t *nxt = (depth & 1) ? buf0 : buf1;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     unsigned long long dsum = 0;
@@ -506,10 +516,10 @@ __global__ __launch_bounds__(256) void k_bfs_heavy(DevGraph g, int32_t *dist, co
 // that follows a top-down one).  A wave covers 64 consecutive vertices and
 // stores their bits as one word.
 __global__ void k_bfs_mark(int32_t n, const int32_t *dist, uint64_t *bits0, uint64_t *bits1, int32_t *sz,
-                           int32_t big_v)
+                           BfsLim lim)
 {
     const int32_t fsize = sz[0], depth = sz[2];
-    if (fsize == 0 || !bfs_bottom_up(fsize, big_v) || sz[11] != 0) return;
+    if (fsize == 0 || !bfs_bottom_up(sz, lim) || sz[11] != 0) return;
     uint64_t *cur = (depth & 1) ? bits1 : bits0;
     const int32_t nw = (n + 63) >> 6;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < 64ll * nw;
@@ -523,10 +533,10 @@ __global__ void k_bfs_mark(int32_t n, const int32_t *dist, uint64_t *bits0, uint
 // One bottom-up level: every unreached vertex looks for a neighbour in the
 // frontier bitmap and stops at the first one; the new vertices' bits form
 // the next bitmap.
-__global__ void k_bfs_bu(DevGraph g, int32_t *dist, uint64_t *bits0, uint64_t *bits1, int32_t *sz, int32_t big_v)
+__global__ void k_bfs_bu(DevGraph g, int32_t *dist, uint64_t *bits0, uint64_t *bits1, int32_t *sz, BfsLim lim)
 {
     const int32_t fsize = sz[0], depth = sz[2];
-    if (fsize == 0 || !bfs_bottom_up(fsize, big_v)) return;
+    if (fsize == 0 || !bfs_bottom_up(sz, lim)) return;
     const uint64_t *cur = (depth & 1) ? bits1 : bits0;
     uint64_t *nxt = (depth & 1) ? bits0 : bits1;
     const int32_t nw = (g.n + 63) >> 6;
@@ -564,13 +574,13 @@ __global__ void k_bfs_bu(DevGraph g, int32_t *dist, uint64_t *bits0, uint64_t *b
 }
 
 // Close a level: the next frontier becomes the current one.
-__global__ void k_bfs_advance(int32_t *sz, int32_t big_v)
+__global__ void k_bfs_advance(int32_t *sz, BfsLim lim)
 {
     const int32_t fsize = sz[0];
     if (fsize == 0) return;
     const int32_t nsize = sz[1];
-    sz[10] = bfs_bottom_up(fsize, big_v) ? 0 : 1;   // top-down listed the next frontier
-    sz[11] = bfs_bottom_up(fsize, big_v) ? 1 : 0;   // bottom-up left its bitmap
+    sz[10] = bfs_bottom_up(sz, lim) ? 0 : 1;   // top-down listed the next frontier
+    sz[11] = bfs_bottom_up(sz, lim) ? 1 : 0;   // bottom-up left its bitmap
     sz[0] = nsize;
     sz[1] = 0;
     sz[2] += 1;
@@ -767,7 +777,9 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
 
     // Direction-optimising BFS enqueued in batches of steps; the host only
     // looks at the frontier size between batches.
-    const int32_t big_v = std::max<int32_t>(n / 16, 1 << 14);
+    BfsLim lim;
+    lim.big_v = std::max<int32_t>(n / 16, 1 << 14);
+    lim.big_e = std::max<int64_t>(g.nnz / 16, (int64_t)1 << 20);
     auto bfs = [&](int32_t src, int32_t *ecc, int32_t *far) -> hipError_t {
         hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, 256)), dim3(256), 0, st, n, dist, src, fa, sizes);
         int64_t rp2[2];
@@ -784,14 +796,14 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
             for (int k = 0; k < 8; ++k) {
                 hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(1024), 0, st, g, dist, fa, fb, sizes);
                 hipLaunchKernelGGL(k_bfs_collect, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, dist, fa, fb,
-                                   sizes, big_v);
-                hipLaunchKernelGGL(k_bfs_td, dim3(2048), dim3(256), 0, st, g, dist, fa, fb, heavy, sizes, big_v);
-                hipLaunchKernelGGL(k_bfs_heavy, dim3(1024), dim3(256), 0, st, g, dist, heavy, fa, fb, sizes, big_v);
+                                   sizes, lim);
+                hipLaunchKernelGGL(k_bfs_td, dim3(2048), dim3(256), 0, st, g, dist, fa, fb, heavy, sizes, lim);
+                hipLaunchKernelGGL(k_bfs_heavy, dim3(1024), dim3(256), 0, st, g, dist, heavy, fa, fb, sizes, lim);
                 hipLaunchKernelGGL(k_bfs_mark, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, dist, bits0,
-                                   bits1, sizes, big_v);
+                                   bits1, sizes, lim);
                 hipLaunchKernelGGL(k_bfs_bu, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, g, dist, bits0, bits1,
-                                   sizes, big_v);
-                hipLaunchKernelGGL(k_bfs_advance, dim3(1), dim3(1), 0, st, sizes, big_v);
+                                   sizes, lim);
+                hipLaunchKernelGGL(k_bfs_advance, dim3(1), dim3(1), 0, st, sizes, lim);
             }
             CK(hipMemcpyAsync(hs, sizes, sizeof(hs), hipMemcpyDeviceToHost, st));
             CK(hipStreamSynchronize(st));

@@ -47,3 +47,27 @@ def test_omega_entry_point_matches_oracle(oracle):
         pytest.skip("library not built")
     for lo, hi in [(6, 6), (5, 9), (3197, 3600), (2, 2), (10, 40)]:
         assert K.kad_omega(lo, hi, 0.01, 0.1) == oracle.omega_bracket(lo, hi, 0.01, 0.1)
+
+
+def _struct_fields(name):
+    text = open(os.path.join(ROOT, "include", "kadabra.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", text, flags=re.S).group(1)
+    fields = []
+    for t, names in re.findall(r"\b([a-z_0-9]+)\s+([a-z_0-9,\s]+);", body):
+        fields += [(t, n.strip()) for n in names.split(",")]
+    return fields
+
+
+@pytest.mark.parametrize("name", ["kad_opts", "kad_result"])
+def test_binding_structs_match_the_header(name):
+    """Field names, order and C types of the ctypes mirrors equal the header's."""
+    import ctypes as C
+    from paper_1910_11039_amd import kadabra as K
+    ctype = {"uint64_t": C.c_uint64, "int64_t": C.c_int64, "uint32_t": C.c_uint32, "int32_t": C.c_int32,
+             "double": C.c_double}
+    want = _struct_fields(name)
+    got = getattr(K, name)._fields_
+    assert [n for _, n in want] == [n for n, _ in got]
+    for (t, n), (_, ct) in zip(want, got):
+        assert ctype[t] == ct, (n, t, ct)
