@@ -39,10 +39,22 @@ __global__ void k_features(DevGraph g, float *out)
     for (int64_t v = wave; v < g.n; v += waves) {
         const int64_t beg = g.rp[v], end = g.rp[v + 1];
         double acc = 0.0, sd = 0.0;
-        for (int64_t e = beg + lane; e < end; e += 64) {
-            const double du = (double)g.deg[g.ci[e]];
-            acc += log1p(du);
-            sd += du;
+        // eight entries per lane in flight: a hub's row is a long serial
+        // loop for its one wave, and the loads dominate it
+        constexpr int B = 8;
+        for (int64_t e0 = beg + lane; e0 < end; e0 += 64 * B) {
+            int32_t u[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) u[j] = (e0 + 64 * j < end) ? g.ci[e0 + 64 * j] : -1;
+            uint32_t du[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) du[j] = u[j] >= 0 ? g.deg[u[j]] : 0u;
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                if (u[j] < 0) continue;
+                acc += log1p((double)du[j]);
+                sd += (double)du[j];
+            }
         }
         for (int o = 32; o > 0; o >>= 1) {
             acc += __shfl_xor(acc, o);
@@ -271,7 +283,7 @@ size_t mlp_scratch_floats(int64_t rows) { return (size_t)blocks_for_rows(rows) *
 
 hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st)
 {
-    const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(g.n, 1 << 16));
+    const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(g.n, 1 << 18));
     hipLaunchKernelGGL(k_features, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, out);
     return hipGetLastError();
 }
