@@ -28,16 +28,66 @@ constexpr int NP = 4481;        // parameters
 constexpr int PSTRIDE = NP + 1; // per-block partial: gradient then loss
 constexpr int OFF_W1 = 0, OFF_B1 = 192, OFF_W2 = 256, OFF_B2 = 4352, OFF_W3 = 4416, OFF_B3 = 4480;
 
-// The neighbour degrees are gathered from the graph's 4-byte degree array
-// (small enough to stay in the last-level cache on large graphs) rather
-// than from row_ptr.
-__global__ void k_features(DevGraph g, float *out)
+// Per-vertex ln(1 + deg) and deg (FP64), computed once, so that the
+// feature pass gathers one 16-byte pair per adjacency entry instead of
+// evaluating a logarithm per entry.
+__global__ void k_logdeg(DevGraph g, double2 *ld)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * blockDim.x) {
+        const double d = (double)g.deg[v];
+        ld[v] = make_double2(log1p(d), d);
+    }
+}
+
+constexpr int64_t FPIECE = 8192;   // rows longer than this are summed in pieces
+
+__device__ __forceinline__ void write_features(float *out, int64_t v, double dv, double acc, double sd)
+{
+    out[3 * v + 0] = (float)log1p(dv);
+    out[3 * v + 1] = (float)(dv > 0 ? acc / dv : 0.0);
+    out[3 * v + 2] = (float)log1p(sd);
+}
+
+constexpr int64_t FSHORT = 32;     // rows up to this long: a thread per vertex
+
+// Short rows (most vertices of a power-law graph): a thread per vertex, its
+// entries eight at a time.
+__global__ void k_features_short(DevGraph g, const double2 *ld, float *out)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t beg = g.rp[v], end = g.rp[v + 1];
+        if (end - beg > FSHORT) continue;
+        double acc = 0.0, sd = 0.0;
+        constexpr int B = 8;
+        for (int64_t e0 = beg; e0 < end; e0 += B) {
+            int32_t u[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) u[j] = (e0 + j < end) ? g.ci[e0 + j] : -1;
+            double2 p[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? ld[u[j]] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                if (u[j] < 0) continue;
+                acc += p[j].x;
+                sd += p[j].y;
+            }
+        }
+        write_features(out, v, (double)(end - beg), acc, sd);
+    }
+}
+
+// Rows of FSHORT + 1 .. FPIECE entries: a wave per vertex.  (Vertices are
+// numbered by descending degree, so the long rows are those of vertices
+// 0 .. H-1.)
+__global__ void k_features(DevGraph g, const double2 *ld, float *out)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t v = wave; v < g.n; v += waves) {
         const int64_t beg = g.rp[v], end = g.rp[v + 1];
+        if (end - beg > FPIECE || end - beg <= FSHORT) continue;
         double acc = 0.0, sd = 0.0;
         // eight entries per lane in flight: a hub's row is a long serial
         // loop for its one wave, and the loads dominate it
@@ -46,26 +96,117 @@ __global__ void k_features(DevGraph g, float *out)
             int32_t u[B];
 #pragma unroll
             for (int j = 0; j < B; ++j) u[j] = (e0 + 64 * j < end) ? g.ci[e0 + 64 * j] : -1;
-            uint32_t du[B];
+            double2 p[B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) du[j] = u[j] >= 0 ? g.deg[u[j]] : 0u;
+            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? ld[u[j]] : make_double2(0.0, 0.0);
 #pragma unroll
             for (int j = 0; j < B; ++j) {
                 if (u[j] < 0) continue;
-                acc += log1p((double)du[j]);
-                sd += (double)du[j];
+                acc += p[j].x;
+                sd += p[j].y;
             }
         }
         for (int o = 32; o > 0; o >>= 1) {
             acc += __shfl_xor(acc, o);
             sd += __shfl_xor(sd, o);
         }
-        if (lane == 0) {
-            const double dv = (double)(end - beg);
-            out[3 * v + 0] = (float)log1p(dv);
-            out[3 * v + 1] = (float)(dv > 0 ? acc / dv : 0.0);
-            out[3 * v + 2] = (float)log1p(sd);
+        if (lane == 0) write_features(out, v, (double)(end - beg), acc, sd);
+    }
+}
+
+// Long rows, in three steps: (1) one workgroup finds H, the number of
+// vertices with more than FPIECE entries, and the prefix of their piece
+// counts; (2) a wave per piece sums its entries; (3) a thread per long row
+// adds its pieces in order.
+__global__ __launch_bounds__(1024) void k_feat_pieces(DevGraph g, int64_t *pref, int32_t *H_out)
+{
+    __shared__ int32_t sH;
+    __shared__ int64_t s_run;
+    __shared__ int64_t s_w[16];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) {
+        int32_t lo = 0, hi = g.n;      // first vertex with at most FPIECE entries
+        while (lo < hi) {
+            const int32_t mid = lo + ((hi - lo) >> 1);
+            if ((int64_t)g.deg[mid] > FPIECE) lo = mid + 1; else hi = mid;
         }
+        sH = lo;
+        s_run = 0;
+        *H_out = lo;
+    }
+    __syncthreads();
+    const int32_t H = sH;
+    for (int32_t b0 = 0; b0 < H; b0 += 1024) {
+        const int32_t v = b0 + tid;
+        int64_t x = v < H ? ((int64_t)g.deg[v] + FPIECE - 1) / FPIECE : 0;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_w[wid] = x;
+        __syncthreads();
+        int64_t before = s_run;
+        for (int i = 0; i < wid; ++i) before += s_w[i];
+        if (v < H) pref[v + 1] = before + x;
+        __syncthreads();
+        if (tid == 1023) s_run = before + x;
+        __syncthreads();
+    }
+    if (tid == 0) pref[0] = 0;
+}
+
+__global__ void k_feat_sum(DevGraph g, const double2 *ld, const int64_t *pref, const int32_t *H_in,
+                           double2 *part)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t H = *H_in;
+    if (H == 0) return;
+    const int64_t total = pref[H];
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t q = wave; q < total; q += waves) {
+        int32_t lo = 0, hi = H - 1;     // the row v with pref[v] <= q < pref[v + 1]
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (pref[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        const int64_t b = g.rp[lo] + (q - pref[lo]) * FPIECE;
+        const int64_t e = min(b + FPIECE, g.rp[lo + 1]);
+        double acc = 0.0, sd = 0.0;
+        constexpr int B = 8;
+        for (int64_t e0 = b + lane; e0 < e; e0 += 64 * B) {
+            int32_t u[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) u[j] = (e0 + 64 * j < e) ? g.ci[e0 + 64 * j] : -1;
+            double2 p[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? ld[u[j]] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                if (u[j] < 0) continue;
+                acc += p[j].x;
+                sd += p[j].y;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            acc += __shfl_xor(acc, o);
+            sd += __shfl_xor(sd, o);
+        }
+        if (lane == 0) part[q] = make_double2(acc, sd);
+    }
+}
+
+__global__ void k_feat_combine(DevGraph g, const int64_t *pref, const int32_t *H_in, const double2 *part,
+                               float *out)
+{
+    const int32_t H = *H_in;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < H; v += gridDim.x * blockDim.x) {
+        double acc = 0.0, sd = 0.0;
+        for (int64_t q = pref[v]; q < pref[v + 1]; ++q) {
+            acc += part[q].x;
+            sd += part[q].y;
+        }
+        write_features(out, v, (double)(g.rp[v + 1] - g.rp[v]), acc, sd);
     }
 }
 
@@ -283,9 +424,31 @@ size_t mlp_scratch_floats(int64_t rows) { return (size_t)blocks_for_rows(rows) *
 
 hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st)
 {
-    const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(g.n, 1 << 18));
-    hipLaunchKernelGGL(k_features, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, out);
-    return hipGetLastError();
+    double2 *ld = nullptr;
+    hipError_t e = hipMallocAsync((void **)&ld, sizeof(double2) * (size_t)std::max<int32_t>(g.n, 1), st);
+    if (e != hipSuccess) return e;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_logdeg, dim3((unsigned)blocks), dim3(256), 0, st, g, ld);
+    hipLaunchKernelGGL(k_features_short, dim3((unsigned)blocks), dim3(256), 0, st, g, ld, out);
+    const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(g.n, 1 << 16));
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, ld, out);
+    // long rows: every such row has more than FPIECE entries, so there are
+    // at most nnz / FPIECE of them and at most 2 nnz / FPIECE + 1 pieces
+    const int64_t hmax = g.nnz / FPIECE + 1, pmax = 2 * (g.nnz / FPIECE) + 1;
+    int64_t *pref = nullptr;
+    int32_t *H = nullptr;
+    double2 *part = nullptr;
+    if ((e = hipMallocAsync((void **)&pref, sizeof(int64_t) * (size_t)(hmax + 1), st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&H, sizeof(int32_t), st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&part, sizeof(double2) * (size_t)pmax, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_feat_pieces, dim3(1), dim3(1024), 0, st, g, pref, H);
+    hipLaunchKernelGGL(k_feat_sum, dim3(2048), dim3(256), 0, st, g, ld, pref, H, part);
+    hipLaunchKernelGGL(k_feat_combine, dim3(64), dim3(256), 0, st, g, pref, H, part, out);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    (void)hipFreeAsync(pref, st);
+    (void)hipFreeAsync(H, st);
+    (void)hipFreeAsync(part, st);
+    return hipFreeAsync(ld, st);
 }
 
 hipError_t launch_normalize(int32_t n, float *x, const float *norm, hipStream_t st)

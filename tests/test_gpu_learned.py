@@ -57,6 +57,22 @@ def test_features_match_oracle(ctx, oracle):
     assert np.allclose(x, xo, rtol=1e-6, atol=1e-7)
 
 
+def test_features_of_long_rows_match_oracle(ctx, oracle):
+    """Rows longer than the 8192-entry pieces (two hubs of 20 000 and 9 000
+    neighbours) are summed piece by piece; all features equal the oracle's."""
+    n = 30000
+    hub_a = np.zeros(20000, dtype=np.int64)
+    hub_b = np.full(9000, 1, dtype=np.int64)
+    r = np.random.default_rng(5)
+    u = np.concatenate([hub_a, hub_b, r.integers(2, n, 40000), np.arange(2, n - 1)])
+    v = np.concatenate([np.arange(2, 20002), np.arange(10, 9010), r.integers(2, n, 40000), np.arange(3, n)])
+    g = gg.from_edges(n, u, v)
+    G = K.Graph(ctx, g)
+    x = K.kad_features(ctx.h, G.h, g.n)
+    xo = oracle.features(g)
+    assert np.allclose(x, xo, rtol=1e-6, atol=1e-7)
+
+
 @pytest.mark.parametrize("rows", [1, 63, 64, 1000, 70000])
 def test_mlp_forward_matches_oracle(ctx, oracle, rows):
     p = L.init_params(3)
