@@ -347,16 +347,14 @@ static kad_status reset_epochs(kad_sampler *s)
 static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, uint64_t count,
                              uint32_t *target, int32_t *paths, int64_t *info, int32_t max_len);
 
-// Autotuner (samples per epoch and workgroup shape).  Workgroup size:
+// Autotuner (workgroup shape and samples per epoch).  Workgroup size:
 // each candidate (256, 512, 1024 threads, each with one full wave of
 // slots) samples the same trial -- four rounds of the widest wave -- on
-// the tuning stream (counts discarded), timed with HIP events; the fastest
-// wins.  Fewer, wider workgroups trade parallelism inside a sample for a
-// smaller combined visited-state footprint, and the balance depends on the
-// graph.  Epoch size: four rounds of the chosen wave, rounded to 256 and
-// kept in [256, 16384]: long enough that an epoch's tail, overlapped with
-// the following epochs, costs little, short enough that the stop
-// overshoots tau by a few percent.
+// the tuning stream (counts discarded), timed with HIP events.  Fewer,
+// wider workgroups trade parallelism inside a sample for a smaller combined
+// visited-state footprint, and the balance depends on the graph.  The
+// fastest shape wins, but 1024 is kept within 5% of it.  Epoch size: see
+// the end of autotune().
 static int cands_block(int i)
 {
     static const int c[3] = {256, 512, 1024};
@@ -574,7 +572,7 @@ extern "C" kad_status kad_sampler_reset(kad_sampler *s, uint64_t seed)
     if (!s) return fail(KAD_EINVAL, "null argument");
     HIPCHK(hipSetDevice(s->device));
     hipStream_t st = s->ctx->stream;
-    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < s->P; ++i) HIPCHK(hipStreamSynchronize(s->sts[i]));
     s->o.seed = seed;
     const double t0 = now_ms();
     if (s->o.alloc_mode == KAD_ALLOC_LEARNED && s->have_mlp) {
@@ -824,7 +822,7 @@ static kad_status enqueue_epoch(kad_sampler *s, hipEvent_t ev0, hipEvent_t ev1)
 // merge of epoch k - 1, so c~ grows and the rule is checked in epoch order
 // on exactly samples [0, tau).  A sampler whose epoch turns out to follow
 // the stop quits at its next sample; its frame is never merged.
-static kad_status enqueue_epoch_k(kad_sampler *s, unsigned long long k, hipEvent_t ev0, hipEvent_t ev1)
+static kad_status enqueue_sampler_k(kad_sampler *s, unsigned long long k, hipEvent_t ev0, hipEvent_t ev1)
 {
     const int p = (int)(k % (unsigned long long)s->P);
     hipStream_t st = s->sts[p];
@@ -840,13 +838,29 @@ static kad_status enqueue_epoch_k(kad_sampler *s, unsigned long long k, hipEvent
     if (ev0) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_sampler(a, (int)std::min<unsigned long long>(s->slots, count), s->block, st));
     if (ev1) HIPCHK(hipEventRecord(ev1, st));
+    return KAD_OK;
+}
+
+// The merge of epoch k: after epoch k - 1's merge (in host order too, so
+// that the event it waits on is already recorded).
+static kad_status enqueue_merge_k(kad_sampler *s, unsigned long long k)
+{
+    const int p = (int)(k % (unsigned long long)s->P);
+    hipStream_t st = s->sts[p];
     if (k > 0) HIPCHK(hipStreamWaitEvent(st, s->ev_merge[(p + s->P - 1) % s->P], 0));
     HIPCHK(launch_merge_stop_impl(s->g->dev(), s->c, s->sf[p], s->sf[p], s->LL, s->LU, s->omega,
-                                  s->o.epsilon, s->cap, s->E, s->es, a.work_ctr, s->hist, s->hist_cap,
+                                  s->o.epsilon, s->cap, s->E, s->es, s->work_ctr + p, s->hist, s->hist_cap,
                                   s->d_status, st));
     HIPCHK(hipEventRecord(s->ev_merge[p], st));
     HIPCHK(hipEventRecord(s->ev_ring[k % s->ev_ring.size()], st));
     return KAD_OK;
+}
+
+static kad_status enqueue_epoch_k(kad_sampler *s, unsigned long long k, hipEvent_t ev0, hipEvent_t ev1)
+{
+    kad_status r = enqueue_sampler_k(s, k, ev0, ev1);
+    if (r != KAD_OK) return r;
+    return enqueue_merge_k(s, k);
 }
 
 static kad_status read_state(kad_sampler *s)
@@ -929,14 +943,14 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
     HIPCHK(hipSetDevice(s->ctx->device));
     hipStream_t st = s->ctx->stream;
     const double t_start = now_ms();
+    const bool timing = s->o.timing != 0;
+    std::vector<hipEvent_t> evs;
     kad_status r = ensure_delta(s);
     if (r != KAD_OK) return r;
     const double t_ads0 = now_ms();
     r = read_state(s);
     if (r != KAD_OK) return r;
     const unsigned long long epoch_at_start = s->h_es->epoch;
-    const bool timing = s->o.timing != 0;
-    std::vector<hipEvent_t> evs;
     if (s->o.use_graphs && !timing && !s->have_graph) {
         r = build_graph(s);
         if (r != KAD_OK) return r;
