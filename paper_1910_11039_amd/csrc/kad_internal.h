@@ -39,7 +39,7 @@ struct SampleStats {
     unsigned long long path_vertices;  // interior vertices counted
     unsigned long long fp_samples;     // samples in FP mode
     unsigned long long samples;        // samples finished
-    unsigned long long edges_all;      // adjacency entries read including redone attempts
+    unsigned long long edges_all;      // adjacency entries read including redone attempts and rescans
     int error;                         // nonzero: a sample found the graph disconnected
     int pad[3];
 };

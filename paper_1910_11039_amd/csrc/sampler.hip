@@ -191,9 +191,13 @@ struct LocalStats {
 // One expansion of side X from its layer k (frontier = queue positions
 // [lo, hi)).  Discovered vertices are appended from position hi on; meet
 // vertices go to the meet list.  Computes sigma for layer k (k >= 1).
+// With `probe` set nothing is claimed: the scan finds the meet set, the
+// meet edges and sigma of layer k, which is all a step that meets needs
+// (its new layer is never used); a probe that finds no meet is followed
+// by the claiming scan.
 template <int BS>
 __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t lo, int32_t hi,
-                           LocalStats &ls)
+                           LocalStats &ls, bool probe)
 {
     // Each lane takes U adjacency entries per iteration (64 apart, so every
     // load stays coalesced across the wave) and issues their loads
@@ -260,7 +264,7 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
                     } else {
                         meet |= 1u << j;
                     }
-                } else {
+                } else if (!probe) {
                     claim |= 1u << j;
                 }
             }
@@ -1082,9 +1086,21 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : 1)) void k_sample(SampleLaunch
                 // tail, mcount, nextdeg and fmax_bits were set for this step
                 // by the previous step's bookkeeping (or the attempt's set-up)
                 t_mark = wall_clock64();
-                if (!fp) expand_int<BS>(sm, c, X, k, lo, hi, ls);
+                // A step whose two frontiers are likely to meet (the product
+                // of their degree sums reaches the number of adjacency
+                // entries) is scanned without claiming first.
+                const bool probe = !fp && (double)sm.sdeg[X] * (double)sm.sdeg[1 - X] >= (double)c.g.nnz;
+                if (!fp) expand_int<BS>(sm, c, X, k, lo, hi, ls, probe);
                 else expand_fp<BS>(sm, c, X, k, lo, hi, ls);
                 __syncthreads();
+                if (probe && !sm.ovf && sm.mcount == 0) {
+                    __syncthreads();
+                    const unsigned long long pred_before = ls.pred;   // the rescan meets the
+                    expand_int<BS>(sm, c, X, k, lo, hi, ls, false);  // same predecessor edges
+                    ls.pred = pred_before;
+                    __syncthreads();
+                    st_all += (unsigned long long)sm.sdeg[X];
+                }
                 t_exp += wall_clock64() - t_mark;
                 if (fp && k >= 1 && as_f64(sm.fmax_bits) > BIG) {
                     for (int32_t p = lo + tid; p < hi; p += BS) {
