@@ -43,6 +43,16 @@ namespace {
 constexpr int MCAP = 1024;                 // meet sets up to this size are ranked in LDS
 constexpr int LMAX = 30;                   // layers whose queue offsets are kept in LDS
 constexpr int MEDGE = 1024;                // meet edges of one frontier chunk folded in LDS
+
+// Bit filter of the vertices a sample has reached: bit (v mod its size) is
+// set whenever v is claimed.  A clear bit proves v unreached, so a probe
+// scan skips that entry without reading its record.  64 KiB for the
+// one-workgroup-per-CU shapes, 8 KiB where three workgroups share a CU.
+template <int BS>
+struct Filter {
+    static constexpr int WORDS = (BS >= 512) ? 16384 : (BS == 256 ? 2048 : 1024);
+    static constexpr uint32_t MASK = (uint32_t)WORDS * 32u - 1u;
+};
 constexpr double BIG = 0x1p400;
 constexpr double SHRINK = 0x1p-400;
 constexpr uint32_t X_SHIFT = 31;
@@ -82,6 +92,19 @@ __device__ __forceinline__ double unit53(uint64_t u) { return (double)(u >> 11) 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <int BS>
+__device__ __forceinline__ bool filt_test(const uint32_t *f, int32_t v)
+{
+    const uint32_t b = (uint32_t)v & Filter<BS>::MASK;
+    return (f[b >> 5] >> (b & 31)) & 1u;
+}
+template <int BS>
+__device__ __forceinline__ void filt_set(uint32_t *f, int32_t v)
+{
+    const uint32_t b = (uint32_t)v & Filter<BS>::MASK;
+    atomicOr(&f[b >> 5], 1u << (b & 31));
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
@@ -124,6 +147,7 @@ struct Smem {
     int32_t loff[2][LMAX + 2];   // layer j of a side = queue positions [loff[j], loff[j+1])
     int32_t me_a[MEDGE];         // meet edges of the current chunk: owner index in the chunk,
     int32_t me_w[MEDGE];         // and the meet vertex
+    uint32_t filt[Filter<BS>::WORDS];
     int32_t tail, mcount, ovf, err, w, wmin, mpath, nme, fold_bad, pathc;
     uint32_t stamp;
     int32_t s, t;
@@ -252,6 +276,11 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
                     w[j] = c.g.ci[sm.e.rs[lo_i] + (e - sm.e.off[lo_i])];
                 }
             }
+            if (probe) {
+#pragma unroll
+                for (int j = 0; j < U; ++j)
+                    if ((act >> j & 1) && !filt_test<BS>(sm.filt, w[j])) act &= ~(1u << j);
+            }
 #pragma unroll
             for (int j = 0; j < U; ++j) kk[j] = (act >> j & 1) ? ld_key(c.R + w[j]) : 0ull;
 #pragma unroll
@@ -274,7 +303,11 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
             uint32_t disc = 0, newmeet = 0;
 #pragma unroll
             for (int j = 0; j < U; ++j) {
-                if (claim >> j & 1) disc |= (uint32_t)cas_key(c.R + w[j], kk[j], newkey) << j;
+                if (claim >> j & 1) {
+                    const bool won = cas_key(c.R + w[j], kk[j], newkey);
+                    disc |= (uint32_t)won << j;
+                    if (won) filt_set<BS>(sm.filt, w[j]);
+                }
                 if (meet >> j & 1) newmeet |= (uint32_t)!(or_state(c.R + w[j], MEET_BIT) & MEET_BIT) << j;
             }
 #pragma unroll
@@ -1043,6 +1076,8 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : 1)) void k_sample(SampleLaunch
         bool failed = false;
         for (;;) {  // attempt (integer mode, then FP mode if it overflowed)
             attempts += 1;
+            for (int i = tid; i < Filter<BS>::WORDS; i += BS) sm.filt[i] = 0;
+            __syncthreads();
             if (tid == 0) {
                 const uint32_t cur = a.stamps[slot] + 1;
                 a.stamps[slot] = cur;
@@ -1054,6 +1089,8 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : 1)) void k_sample(SampleLaunch
                 st_sig(c.R + t, fp ? as_u64(1.0) : 1ull);
                 c.Q[0] = s;
                 c.Q[n - 1] = t;
+                filt_set<BS>(sm.filt, s);
+                filt_set<BS>(sm.filt, t);
                 sm.lo[0] = sm.lo[1] = 0;
                 sm.hi[0] = sm.hi[1] = 1;
                 sm.plo[0] = sm.plo[1] = 0;
