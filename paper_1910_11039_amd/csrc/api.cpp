@@ -350,7 +350,8 @@ static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, ui
 // Autotuner (workgroup shape and samples per epoch).  Workgroup size:
 // each candidate (256, 512, 1024 threads, each with one full wave of
 // slots) samples the same trial -- four rounds of the widest wave -- on
-// the tuning stream (counts discarded), timed with HIP events.  Fewer,
+// the tuning stream (counts discarded), timed with HIP events; when
+// samples are short, each then samples sixteen rounds of its own wave.  Fewer,
 // wider workgroups trade parallelism inside a sample for a smaller combined
 // visited-state footprint, and the balance depends on the graph.  The
 // fastest shape wins, but 1024 is kept within 5% of it.  Epoch size: see
@@ -373,22 +374,37 @@ static kad_status autotune(kad_sampler *s)
         HIPCHK(hipEventCreate(&e1));
         const int all_slots = s->slots;
         const uint64_t N = 4ull * (uint64_t)all_slots;
-        for (int i = 0; i < 3; ++i) {
-            const int b = cands[i];
-            const int sl = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(b));
-            s->block = b;
-            s->slots = sl;
-            HIPCHK(hipMemsetAsync(s->scratch_counts, 0, 4ull * s->g->n, st));
-            HIPCHK(hipEventRecord(e0, st));
-            kad_status r = count_into(s, KAD_STREAM_TUNE, 0, N, s->scratch_counts, nullptr, nullptr, 0);
-            if (r != KAD_OK) return r;
-            HIPCHK(hipEventRecord(e1, st));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0.0f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            const double rate = (double)N / (ms * 1e-3);
-            s->tune_rate[i] = rate;
-            best = std::max(best, rate);
+        // pass 0: the same trial for every shape; pass 1, only when samples
+        // are short: sixteen rounds of each shape's own wave, the share of
+        // an epoch that the epoch-size rule below gives it, so that a shape
+        // with more slots is not judged on a trial dominated by its tail
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1) {
+                int fastest = 0;
+                for (int i = 1; i < 3; ++i)
+                    if (s->tune_rate[i] > s->tune_rate[fastest]) fastest = i;
+                const int sl = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(cands[fastest]));
+                if ((double)sl / s->tune_rate[fastest] > 0.010) break;
+                best = -1.0;
+            }
+            for (int i = 0; i < 3; ++i) {
+                const int b = cands[i];
+                const int sl = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(b));
+                const uint64_t trial = pass == 0 ? N : 16ull * (uint64_t)sl;
+                s->block = b;
+                s->slots = sl;
+                HIPCHK(hipMemsetAsync(s->scratch_counts, 0, 4ull * s->g->n, st));
+                HIPCHK(hipEventRecord(e0, st));
+                kad_status r = count_into(s, KAD_STREAM_TUNE, 0, trial, s->scratch_counts, nullptr, nullptr, 0);
+                if (r != KAD_OK) return r;
+                HIPCHK(hipEventRecord(e1, st));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                const double rate = (double)trial / (ms * 1e-3);
+                s->tune_rate[i] = rate;
+                best = std::max(best, rate);
+            }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);

@@ -46,11 +46,12 @@ constexpr int MEDGE = 1024;                // meet edges of one frontier chunk f
 
 // Bit filter of the vertices a sample has reached: bit (v mod its size) is
 // set whenever v is claimed.  A clear bit proves v unreached, so a probe
-// scan skips that entry without reading its record.  64 KiB for the
-// one-workgroup-per-CU shapes, 8 KiB where three workgroups share a CU.
+// scan skips that entry without reading its record.  Sized so that the
+// workgroups meant to share a CU fit its LDS: 64 KiB at 1024 threads (one
+// per CU), 32 KiB at 512 (two), 8 KiB at 256 (three).
 template <int BS>
 struct Filter {
-    static constexpr int WORDS = (BS >= 512) ? 16384 : (BS == 256 ? 2048 : 1024);
+    static constexpr int WORDS = (BS >= 1024) ? 16384 : (BS == 512 ? 8192 : (BS == 256 ? 2048 : 1024));
     static constexpr uint32_t MASK = (uint32_t)WORDS * 32u - 1u;
 };
 constexpr double BIG = 0x1p400;
@@ -1018,10 +1019,12 @@ __device__ int32_t pick_pred_layer(Smem<BS> &sm, const Ctx &c, int side, int32_t
     return pick >= 0 ? c.g.newid[pick] : pick;
 }
 
-// The 256-thread shape is held to three waves per SIMD (three workgroups
-// per CU): the high-diameter graphs depend on that many samples in flight.
+// The second bound is the minimum of waves per SIMD.  The 256-thread
+// shape is held to three (three workgroups per CU): the high-diameter
+// graphs depend on that many samples in flight; the 512-thread shape to
+// four (two workgroups per CU).
 template <int BS>
-__global__ __launch_bounds__(BS, (BS == 256 ? 3 : 1)) void k_sample(SampleLaunch a)
+__global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_sample(SampleLaunch a)
 {
     __shared__ Smem<BS> sm;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
