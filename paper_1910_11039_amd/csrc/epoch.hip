@@ -248,6 +248,63 @@ __global__ __launch_bounds__(AB) void k_alloc_update(double *lo_hi, const double
     if (red[0] <= target) lo_hi[1] = mid; else lo_hi[0] = mid;
 }
 
+// Calibration priors are counts over tau0, so the sum over vertices is a
+// sum over count values c of (vertices with count c) * exp(-mid tau0 / c).
+__global__ void k_alloc_hist(AllocArgs a, uint32_t *hist, uint32_t top)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
+        const uint32_t c = a.counts[v];
+        if (c > 0) atomicAdd(hist + min(c, top), 1u);
+    }
+}
+
+// The whole bisection in one workgroup over the count histogram: per step,
+// thread t sums bins t, t + HB, ... in turn, then a pairwise tree (a fixed
+// order).  Same interval, step rule and stopping rule as the dense form.
+constexpr int HB = 1024;
+__global__ __launch_bounds__(HB) void k_alloc_bisect_hist(AllocArgs a, const uint32_t *hist, uint32_t top,
+                                                          double target)
+{
+    __shared__ double red[HB];
+    __shared__ unsigned long long kcount;
+    const int tid = threadIdx.x;
+    if (tid == 0) kcount = 0;
+    __syncthreads();
+    unsigned long long k = 0;
+    for (uint32_t c = 1 + tid; c <= top; c += HB) k += hist[c];
+    atomicAdd(&kcount, k);
+    __syncthreads();
+    const unsigned long long K = kcount;
+    double lo = 0.0, hi = 0.0;
+    if (K > 0) {
+        hi = log((double)K / target);
+        if (hi < 0.0) hi = 0.0;
+    }
+    for (int it = 0; it < 200 && K > 0; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double sum = 0.0;
+        for (uint32_t c = 1 + tid; c <= top; c += HB) {
+            const uint32_t h = hist[c];
+            if (h) sum = sum + (double)h * exp(-mid / ((double)c / a.tau0));
+        }
+        red[tid] = sum;
+        __syncthreads();
+        for (int o = HB / 2; o > 0; o >>= 1) {
+            if (tid < o) red[tid] = red[tid] + red[tid + o];
+            __syncthreads();
+        }
+        const double tot = red[0];
+        __syncthreads();
+        if (tot <= target) hi = mid; else lo = mid;
+    }
+    if (tid == 0) {
+        a.lo_hi[0] = lo;
+        a.lo_hi[1] = hi;
+        a.lo_hi[2] = 1.0;
+    }
+}
+
 __global__ void k_alloc_delta(AllocArgs a, double C)
 {
     const double floor_d = a.beta * a.delta / (4.0 * (double)a.n);
@@ -647,6 +704,25 @@ hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host)
 {
     hipError_t e;
     const double target = 0.25 * a.delta * (1.0 - 1e-9);
+    if (a.counts) {
+        // calibration counts: histogram, then the bisection in one launch
+        const uint32_t top = (uint32_t)std::max(1.0, a.tau0);
+        uint32_t *hist = nullptr;
+        if ((e = hipMallocAsync((void **)&hist, sizeof(uint32_t) * ((size_t)top + 1), st)) != hipSuccess)
+            return e;
+        CK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * ((size_t)top + 1), st));
+        hipLaunchKernelGGL(k_alloc_hist, dim3(grid_for(a.n, 256, 2048)), dim3(256), 0, st, a, hist, top);
+        hipLaunchKernelGGL(k_alloc_bisect_hist, dim3(1), dim3(HB), 0, st, a, hist, top, target);
+        CK(hipFreeAsync(hist, st));
+        double fin[3];
+        CK(hipMemcpyAsync(fin, a.lo_hi, sizeof(fin), hipMemcpyDeviceToHost, st));
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        const double C = fin[1];
+        hipLaunchKernelGGL(k_alloc_delta, dim3(grid_for(a.n, 256)), dim3(256), 0, st, a, C);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        *C_host = C;
+        return hipSuccess;
+    }
     unsigned long long *dK = nullptr;
     if ((e = hipMallocAsync((void **)&dK, sizeof(unsigned long long), st)) != hipSuccess) return e;
     CK(hipMemsetAsync(dK, 0, sizeof(unsigned long long), st));
