@@ -89,6 +89,7 @@ struct kad_sampler {
     uint32_t *stamps;
     unsigned long long *work_ctr;
     SampleStats *stats;
+    SampleStats *cal_stats;   // the calibration's samples (they may run beside adaptive epochs)
     EpochState *es;
     void *hist;
     int32_t hist_cap;
@@ -307,7 +308,7 @@ static void free_sampler(kad_sampler *s)
     if (s->h_status) (void)hipHostFree(s->h_status);
     void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->sf[2], s->sf[3], s->cprime, s->scratch_counts, s->LL, s->LU, s->lo_hi, s->macc,
                     s->partials, s->prior, s->recs, s->queues, s->mbufs, s->stamps, s->work_ctr,
-                    s->stats, s->es, s->hist};
+                    s->stats, s->cal_stats, s->es, s->hist};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->h_es) (void)hipHostFree(s->h_es);
@@ -345,7 +346,8 @@ static kad_status reset_epochs(kad_sampler *s)
 }
 
 static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, uint64_t count,
-                             uint32_t *target, int32_t *paths, int64_t *info, int32_t max_len);
+                             uint32_t *target, int32_t *paths, int64_t *info, int32_t max_len,
+                             SampleStats *stats = nullptr);
 
 // Autotuner (workgroup shape and samples per epoch).  Workgroup size:
 // each candidate (256, 512, 1024 threads, each with one full wave of
@@ -549,7 +551,8 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
               alloc((void **)&s->mbufs, 4ull * n * s->P * s->slots) &&
               alloc((void **)&s->macc, 16ull * (size_t)s->macc_cap * s->P * s->slots) &&
               alloc((void **)&s->stamps, 4ull * s->P * s->slots) && alloc((void **)&s->work_ctr, 32) &&
-              alloc((void **)&s->stats, sizeof(SampleStats)) && alloc((void **)&s->es, sizeof(EpochState)) &&
+              alloc((void **)&s->stats, sizeof(SampleStats)) && alloc((void **)&s->cal_stats, sizeof(SampleStats)) &&
+              alloc((void **)&s->es, sizeof(EpochState)) &&
               alloc((void **)&s->hist, epoch_hist_bytes() * s->hist_cap);
     if (!ok || hipHostMalloc((void **)&s->h_es, sizeof(EpochState), 0) != hipSuccess ||
         hipHostMalloc((void **)&s->h_status, sizeof(HostStatus), hipHostMallocMapped) != hipSuccess ||
@@ -645,11 +648,13 @@ static SampleLaunch base_launch(kad_sampler *s, int pool = 0)
 
 // Non-adaptive samples [first, first+count) of `stream` counted into `target`.
 static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, uint64_t count,
-                             uint32_t *target, int32_t *paths, int64_t *info, int32_t max_len)
+                             uint32_t *target, int32_t *paths, int64_t *info, int32_t max_len,
+                             SampleStats *stats)
 {
     if (count == 0) return KAD_OK;
     hipStream_t st = s->ctx->stream;
     SampleLaunch a = base_launch(s);
+    if (stats) a.stats = stats;
     a.stream = stream;
     a.first = first;
     a.count = count;
@@ -666,10 +671,10 @@ static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, ui
     return KAD_OK;
 }
 
-static kad_status check_stats_error(kad_sampler *s)
+static kad_status check_stats_error(kad_sampler *s, const SampleStats *src = nullptr)
 {
     SampleStats h;
-    HIPCHK(hipMemcpyAsync(&h, s->stats, sizeof(h), hipMemcpyDeviceToHost, s->ctx->stream));
+    HIPCHK(hipMemcpyAsync(&h, src ? src : s->stats, sizeof(h), hipMemcpyDeviceToHost, s->ctx->stream));
     HIPCHK(hipStreamSynchronize(s->ctx->stream));
     if (h.error == 1) return fail(KAD_ENOTCONNECTED, "a sampled pair has no path: graph not connected");
     if (h.error == 2) return fail(KAD_EOVERFLOW, "a path is longer than max_len - 1");
@@ -797,7 +802,8 @@ static kad_status ensure_delta(kad_sampler *s)
         // Phase 2 (Sec. III-A): tau0 = ceil(omega / 100) non-adaptive samples on stream 1.
         s->tau0 = (uint64_t)ceil(s->omega / 100.0);
         HIPCHK(hipMemsetAsync(s->cprime, 0, 4ull * n, st));
-        kad_status r = count_into(s, KAD_STREAM_CALIB, 0, s->tau0, s->cprime, nullptr, nullptr, 0);
+        HIPCHK(hipMemsetAsync(s->cal_stats, 0, sizeof(SampleStats), st));
+        kad_status r = count_into(s, KAD_STREAM_CALIB, 0, s->tau0, s->cprime, nullptr, nullptr, 0, s->cal_stats);
         if (r != KAD_OK) return r;
         a.counts = s->cprime;
         a.tau0 = (double)s->tau0;
@@ -805,9 +811,8 @@ static kad_status ensure_delta(kad_sampler *s)
         HIPCHK(run_alloc(a, st, &C));
         HIPCHK(hipStreamSynchronize(st));
         s->C = C;
-        r = check_stats_error(s);
+        r = check_stats_error(s, s->cal_stats);
         if (r != KAD_OK) return r;
-        HIPCHK(hipMemsetAsync(s->stats, 0, sizeof(SampleStats), st));
     }
     s->res.tau0 = learned ? 0 : s->tau0;
     s->res.t_alloc_ms = now_ms() - t0;
@@ -961,12 +966,47 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
     const double t_start = now_ms();
     const bool timing = s->o.timing != 0;
     std::vector<hipEvent_t> evs;
-    kad_status r = ensure_delta(s);
+    auto timing_events = [&](hipEvent_t *e0, hipEvent_t *e1) -> kad_status {
+        *e0 = *e1 = nullptr;
+        if (!timing) return KAD_OK;
+        HIPCHK(hipEventCreate(e0));
+        HIPCHK(hipEventCreate(e1));
+        evs.push_back(*e0);
+        evs.push_back(*e1);
+        return KAD_OK;
+    };
+    // Adaptive samples do not depend on the delta allocation, only their
+    // merges do: when a plain allocation is still to come, the samplers of
+    // epochs 1 .. P-1 start first on their pools and run beside the
+    // calibration (pool 0, stream 0); epoch 0 and the merges follow it.
+    // The learned allocation is a chain of short launches that would wait
+    // for CUs behind those samplers, so it runs first on an idle GPU.
+    const unsigned long long total = (s->cap + s->E - 1) / s->E;
+    const bool graph_path = s->o.use_graphs && !timing;
+    unsigned long long pre_hi = 0;
+    kad_status r = read_state(s);   // the allocation does not touch the epoch state
     if (r != KAD_OK) return r;
+    if (!s->delta_ready && s->o.alloc_mode == KAD_ALLOC_PLAIN && !graph_path && s->P > 1 &&
+        s->next_epoch == 0 && !s->h_es->stopped) {
+        pre_hi = std::min<unsigned long long>((unsigned long long)s->P, total);
+        for (unsigned long long k = 1; k < pre_hi; ++k) {
+            hipEvent_t e0, e1;
+            kad_status rr = timing_events(&e0, &e1);
+            if (rr == KAD_OK) rr = enqueue_sampler_k(s, k, e0, e1);
+            if (rr != KAD_OK) return rr;
+        }
+    }
+    r = ensure_delta(s);
+    if (r != KAD_OK) return r;
+    if (pre_hi > 0) {
+        hipEvent_t e0, e1;
+        r = timing_events(&e0, &e1);
+        if (r == KAD_OK) r = enqueue_sampler_k(s, 0, e0, e1);
+        for (unsigned long long k = 0; r == KAD_OK && k < pre_hi; ++k) r = enqueue_merge_k(s, k);
+        if (r != KAD_OK) return r;
+        s->next_epoch = pre_hi;
+    }
     const double t_ads0 = now_ms();
-    r = read_state(s);
-    if (r != KAD_OK) return r;
-    const unsigned long long epoch_at_start = s->h_es->epoch;
     if (s->o.use_graphs && !timing && !s->have_graph) {
         r = build_graph(s);
         if (r != KAD_OK) return r;
@@ -981,17 +1021,12 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
         // Keep `inflight` epochs queued ahead of the newest verdict the host
         // has seen; the verdict of epoch k is polled from pinned memory once
         // its merge has completed.
-        const unsigned long long total = (s->cap + s->E - 1) / s->E;
-        unsigned long long known = s->next_epoch;
+        unsigned long long known = pre_hi > 0 ? 0 : s->next_epoch;
         for (;;) {
             while (s->next_epoch < total && s->next_epoch < known + (unsigned long long)s->inflight) {
-                hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (timing) {
-                    HIPCHK(hipEventCreate(&e0));
-                    HIPCHK(hipEventCreate(&e1));
-                    evs.push_back(e0);
-                    evs.push_back(e1);
-                }
+                hipEvent_t e0, e1;
+                r = timing_events(&e0, &e1);
+                if (r != KAD_OK) return r;
                 r = enqueue_epoch_k(s, s->next_epoch++, e0, e1);
                 if (r != KAD_OK) return r;
             }
@@ -1008,7 +1043,6 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
     if (timing) {
         // every launch counts, speculative ones included: the work counters
         // cover their samples too
-        (void)epoch_at_start;
         for (size_t i = 0; i + 1 < evs.size(); i += 2) {
             float ms = 0.0f;
             HIPCHK(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));

@@ -666,7 +666,10 @@ hipError_t launch_merge_stop_impl(const DevGraph &g, uint32_t *c, uint32_t *sf0,
                                   unsigned long long *work_ctr, void *hist, int32_t hist_cap,
                                   HostStatus *hs, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_merge_stop, dim3(grid_for(g.n, MB, 2048)), dim3(MB), 0, st, g.n, c, sf0, sf1,
+    // At most 256 workgroups: the merge runs while sampler workgroups hold
+    // the CUs, and each of its workgroups waits for a slot that one of them
+    // gives up; fewer, longer workgroups finish the merge sooner there.
+    hipLaunchKernelGGL(k_merge_stop, dim3(grid_for(g.n, MB, 256)), dim3(MB), 0, st, g.n, c, sf0, sf1,
                        LL, LU, omega, eps, cap, E, es, work_ctr, (EpochHist *)hist, hist_cap, hs);
     return hipGetLastError();
 }
@@ -711,14 +714,15 @@ hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host)
         if ((e = hipMallocAsync((void **)&hist, sizeof(uint32_t) * ((size_t)top + 1), st)) != hipSuccess)
             return e;
         CK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * ((size_t)top + 1), st));
-        hipLaunchKernelGGL(k_alloc_hist, dim3(grid_for(a.n, 256, 2048)), dim3(256), 0, st, a, hist, top);
+        // small grids: these run beside the adaptive samplers (see the merge)
+        hipLaunchKernelGGL(k_alloc_hist, dim3(grid_for(a.n, 256, 256)), dim3(256), 0, st, a, hist, top);
         hipLaunchKernelGGL(k_alloc_bisect_hist, dim3(1), dim3(HB), 0, st, a, hist, top, target);
         CK(hipFreeAsync(hist, st));
         double fin[3];
         CK(hipMemcpyAsync(fin, a.lo_hi, sizeof(fin), hipMemcpyDeviceToHost, st));
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
         const double C = fin[1];
-        hipLaunchKernelGGL(k_alloc_delta, dim3(grid_for(a.n, 256)), dim3(256), 0, st, a, C);
+        hipLaunchKernelGGL(k_alloc_delta, dim3(grid_for(a.n, 256, 256)), dim3(256), 0, st, a, C);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         *C_host = C;
         return hipSuccess;
