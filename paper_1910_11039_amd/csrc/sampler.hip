@@ -199,6 +199,8 @@ struct Ctx {
     Rec *R;
     int32_t *Q;
     int32_t *MB;
+    unsigned long long *gacc;   // the slot's meet accumulators: sigma_X, then sigma_Y
+    int32_t macc_cap;           // meet positions each of the two holds
     uint32_t cur;
     int fp;
 };
@@ -234,7 +236,12 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
     const uint64_t newkey = ((uint64_t)c.cur << 32) | xbit | (uint32_t)(k + 1);
     unsigned long long nd = 0;
     // sigma_X of the meet vertices, should this expansion meet: every meet
-    // edge (u, w) adds sigma(u) to w's slot once u's sigma is complete
+    // edge (u, w) adds sigma(u) to w's slot once u's sigma is complete.
+    // Slots: LDS below MCAP, the slot's global accumulators below MACC.
+    // Meet edges beyond the LDS list of a chunk spill, two words each, to
+    // the back of the meet buffer, whose front holds at most the size of
+    // Y's newest layer (the meet set lies in it).
+    const int64_t spill_cap = max<int64_t>(0, ((int64_t)n - (int64_t)(sm.hi[1 - X] - sm.lo[1 - X]) - 2) / 2);
     for (int32_t i = tid; i < MCAP; i += BS) sm.m.w[i] = 0;
     if (tid == 0) {
         sm.nme = 0;
@@ -335,6 +342,10 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
                     if (slot < MEDGE) {
                         sm.me_a[slot] = a[j];
                         sm.me_w[slot] = w[j];
+                    } else if ((int64_t)(slot - MEDGE) < spill_cap) {
+                        const int64_t q = (int64_t)n - 2 - 2 * (int64_t)(slot - MEDGE);
+                        c.MB[q + 1] = w[j];
+                        c.MB[q] = a[j];
                     }
                 }
                 const bool mj = newmeet >> j & 1;
@@ -348,7 +359,9 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
                         const int mp = pos + (int)mbcnt(mm);
                         c.MB[mp] = w[j];
                         st_sig(c.R + w[j], (uint64_t)mp);   // meet vertices are never expanded:
-                    }                                       // their sigma field holds the list position
+                                                            // their sigma field holds the list position
+                        if (mp >= MCAP && mp < c.macc_cap) c.gacc[mp] = 0;
+                    }
                 }
             }
 #pragma unroll
@@ -361,12 +374,25 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
         if (nme > 0) {
             // the chunk's sigmas are complete; meet positions were written
             // by the lanes that set the meet bits, before the barrier
-            if (nme > MEDGE && tid == 0) sm.fold_bad = 1;
-            for (int32_t i = tid; i < min(nme, MEDGE); i += BS) {
-                const uint64_t su = (k >= 1) ? (uint64_t)sm.e.acc[sm.me_a[i]] : 1ull;
-                const uint64_t mp = ld_sig(c.R + sm.me_w[i]);
-                if (mp < (uint64_t)MCAP) {
-                    const unsigned long long old = atomicAdd(&sm.m.w[mp], (unsigned long long)su);
+            if ((int64_t)nme - MEDGE > spill_cap && tid == 0) sm.fold_bad = 1;
+            const int32_t nfold = (int32_t)min<int64_t>(nme, (int64_t)MEDGE + spill_cap);
+            for (int32_t i = tid; i < nfold; i += BS) {
+                int32_t ai, wi;
+                if (i < MEDGE) {
+                    ai = sm.me_a[i];
+                    wi = sm.me_w[i];
+                } else {
+                    const int64_t q = (int64_t)n - 2 - 2 * (int64_t)(i - MEDGE);
+                    wi = c.MB[q + 1];
+                    ai = c.MB[q];
+                }
+                const uint64_t su = (k >= 1) ? (uint64_t)sm.e.acc[ai] : 1ull;
+                const uint64_t mp = ld_sig(c.R + wi);
+                unsigned long long *slotp = nullptr;
+                if (mp < (uint64_t)MCAP) slotp = &sm.m.w[mp];
+                else if (mp < (uint64_t)c.macc_cap) slotp = c.gacc + mp;
+                if (slotp) {
+                    const unsigned long long old = atomicAdd(slotp, (unsigned long long)su);
                     if (old + su < old) sm.ovf = 1;
                 } else {
                     sm.fold_bad = 1;
@@ -620,14 +646,16 @@ __device__ void meet_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t 
     }
     unsigned long long *accX = path == 0 ? sm.m.w : gacc;
     unsigned long long *accY = path == 0 ? sm.m.w2 : gacc + macc_cap;
-    // the expansion folded sigma_X of every meet vertex into sm.m.w unless
-    // the meet edges overflowed its buffer (then it is recomputed here)
-    const bool foldX = path == 0 && !sm.fold_bad;
+    // the expansion folded sigma_X of every meet vertex (positions below
+    // MCAP in sm.m.w, the rest in the slot buffer) unless the meet edges
+    // overflowed the spill space (then it is recomputed here)
+    const bool foldX = path <= 1 && !sm.fold_bad;
     uint64_t dsum = 0;
     for (int32_t i = tid; i < m; i += BS) {
         const int32_t w = c.MB[i];
         dsum += (uint64_t)(c.g.rp[w + 1] - c.g.rp[w]);
         if (!foldX) accX[i] = 0;
+        else if (path == 1 && i < MCAP) accX[i] = sm.m.w[i];
         accY[i] = 0;
         if (path == 0) sm.m.id[i] = c.g.orig[w];
     }
@@ -1044,6 +1072,8 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
     c.Q = a.queues + slot * (size_t)n;
     c.MB = a.mbufs + slot * (size_t)n;
     unsigned long long *gacc = a.macc + slot * 2 * (size_t)a.macc_cap;
+    c.gacc = gacc;
+    c.macc_cap = a.macc_cap;
     LocalStats ls{0, 0};
     unsigned long long st_edges = 0, st_exp = 0, st_path = 0, st_fp = 0, st_samples = 0, st_all = 0;
 
