@@ -202,7 +202,10 @@ def main():
                    "fell_back_to_plain": int(sum(r["tau0"] > 0 for r in lres)),
                    "plain_time_to_stop_ms": round(plain_ms, 3),
                    "plain_samples_per_run": float(np.mean([r["tau0"] + r["tau"] for r in results])),
-                   "time_ratio_learned_over_plain": round(l_ms / plain_ms, 4)}
+                   "time_ratio_learned_over_plain": round(l_ms / plain_ms, 4),
+                   "phase_ms": {k: round(float(np.mean([r[k] for r in lres])), 3)
+                                for k in ("t_omega_ms", "t_alloc_ms", "t_ads_ms")},
+                   "launch": {k: int(lres[-1][k]) for k in ("epoch_size", "slots", "block_size", "pools")}}
         print(f"# learned arm: {l_ms:.1f} ms per run vs plain {plain_ms:.1f} ms", file=sys.stderr, flush=True)
 
     cpu = None

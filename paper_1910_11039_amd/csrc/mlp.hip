@@ -28,15 +28,14 @@ constexpr int NP = 4481;        // parameters
 constexpr int PSTRIDE = NP + 1; // per-block partial: gradient then loss
 constexpr int OFF_W1 = 0, OFF_B1 = 192, OFF_W2 = 256, OFF_B2 = 4352, OFF_W3 = 4416, OFF_B3 = 4480;
 
-// Per-vertex ln(1 + deg) and deg (FP64), computed once, so that the
-// feature pass gathers one 16-byte pair per adjacency entry instead of
-// evaluating a logarithm per entry.
-__global__ void k_logdeg(DevGraph g, double2 *ld)
+// ln(1 + deg u) and deg u (FP64) of a neighbour u: the 4-byte degree is
+// gathered and the logarithm taken here.  (A precomputed 16-byte table
+// per vertex stops fitting the caches on large graphs, where the gathers
+// then dominate; the logarithm is cheap next to a missed line.)
+__device__ __forceinline__ double2 logdeg(const DevGraph &g, int32_t u)
 {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * blockDim.x) {
-        const double d = (double)g.deg[v];
-        ld[v] = make_double2(log1p(d), d);
-    }
+    const double d = (double)g.deg[u];
+    return make_double2(log1p(d), d);
 }
 
 constexpr int64_t FPIECE = 8192;   // rows longer than this are summed in pieces
@@ -52,7 +51,7 @@ constexpr int64_t FSHORT = 32;     // rows up to this long: a thread per vertex
 
 // Short rows (most vertices of a power-law graph): a thread per vertex, its
 // entries eight at a time.
-__global__ void k_features_short(DevGraph g, const double2 *ld, float *out)
+__global__ void k_features_short(DevGraph g, float *out)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t beg = g.rp[v], end = g.rp[v + 1];
@@ -65,7 +64,7 @@ __global__ void k_features_short(DevGraph g, const double2 *ld, float *out)
             for (int j = 0; j < B; ++j) u[j] = (e0 + j < end) ? g.ci[e0 + j] : -1;
             double2 p[B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? ld[u[j]] : make_double2(0.0, 0.0);
+            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? logdeg(g, u[j]) : make_double2(0.0, 0.0);
 #pragma unroll
             for (int j = 0; j < B; ++j) {
                 if (u[j] < 0) continue;
@@ -80,7 +79,7 @@ __global__ void k_features_short(DevGraph g, const double2 *ld, float *out)
 // Rows of FSHORT + 1 .. FPIECE entries: a wave per vertex.  (Vertices are
 // numbered by descending degree, so the long rows are those of vertices
 // 0 .. H-1.)
-__global__ void k_features(DevGraph g, const double2 *ld, float *out)
+__global__ void k_features(DevGraph g, float *out)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -98,7 +97,7 @@ __global__ void k_features(DevGraph g, const double2 *ld, float *out)
             for (int j = 0; j < B; ++j) u[j] = (e0 + 64 * j < end) ? g.ci[e0 + 64 * j] : -1;
             double2 p[B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? ld[u[j]] : make_double2(0.0, 0.0);
+            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? logdeg(g, u[j]) : make_double2(0.0, 0.0);
 #pragma unroll
             for (int j = 0; j < B; ++j) {
                 if (u[j] < 0) continue;
@@ -155,7 +154,7 @@ __global__ __launch_bounds__(1024) void k_feat_pieces(DevGraph g, int64_t *pref,
     if (tid == 0) pref[0] = 0;
 }
 
-__global__ void k_feat_sum(DevGraph g, const double2 *ld, const int64_t *pref, const int32_t *H_in,
+__global__ void k_feat_sum(DevGraph g, const int64_t *pref, const int32_t *H_in,
                            double2 *part)
 {
     const int lane = threadIdx.x & 63;
@@ -180,7 +179,7 @@ __global__ void k_feat_sum(DevGraph g, const double2 *ld, const int64_t *pref, c
             for (int j = 0; j < B; ++j) u[j] = (e0 + 64 * j < e) ? g.ci[e0 + 64 * j] : -1;
             double2 p[B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? ld[u[j]] : make_double2(0.0, 0.0);
+            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? logdeg(g, u[j]) : make_double2(0.0, 0.0);
 #pragma unroll
             for (int j = 0; j < B; ++j) {
                 if (u[j] < 0) continue;
@@ -424,14 +423,11 @@ size_t mlp_scratch_floats(int64_t rows) { return (size_t)blocks_for_rows(rows) *
 
 hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st)
 {
-    double2 *ld = nullptr;
-    hipError_t e = hipMallocAsync((void **)&ld, sizeof(double2) * (size_t)std::max<int32_t>(g.n, 1), st);
-    if (e != hipSuccess) return e;
+    hipError_t e;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_logdeg, dim3((unsigned)blocks), dim3(256), 0, st, g, ld);
-    hipLaunchKernelGGL(k_features_short, dim3((unsigned)blocks), dim3(256), 0, st, g, ld, out);
+    hipLaunchKernelGGL(k_features_short, dim3((unsigned)blocks), dim3(256), 0, st, g, out);
     const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(g.n, 1 << 16));
-    hipLaunchKernelGGL(k_features, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, ld, out);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, out);
     // long rows: every such row has more than FPIECE entries, so there are
     // at most nnz / FPIECE of them and at most 2 nnz / FPIECE + 1 pieces
     const int64_t hmax = g.nnz / FPIECE + 1, pmax = 2 * (g.nnz / FPIECE) + 1;
@@ -442,13 +438,12 @@ hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st)
     if ((e = hipMallocAsync((void **)&H, sizeof(int32_t), st)) != hipSuccess) return e;
     if ((e = hipMallocAsync((void **)&part, sizeof(double2) * (size_t)pmax, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_feat_pieces, dim3(1), dim3(1024), 0, st, g, pref, H);
-    hipLaunchKernelGGL(k_feat_sum, dim3(2048), dim3(256), 0, st, g, ld, pref, H, part);
+    hipLaunchKernelGGL(k_feat_sum, dim3(2048), dim3(256), 0, st, g, pref, H, part);
     hipLaunchKernelGGL(k_feat_combine, dim3(64), dim3(256), 0, st, g, pref, H, part, out);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     (void)hipFreeAsync(pref, st);
     (void)hipFreeAsync(H, st);
-    (void)hipFreeAsync(part, st);
-    return hipFreeAsync(ld, st);
+    return hipFreeAsync(part, st);
 }
 
 hipError_t launch_normalize(int32_t n, float *x, const float *norm, hipStream_t st)

@@ -263,14 +263,13 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
         const int64_t off = block_excl_scan<BS>(sm, d, total);
         sm.e.off[tid] = off;
         __syncthreads();
-        for (int64_t e0 = (int64_t)(tid >> 6) * 64 * U; e0 < total; e0 += (int64_t)BS * U) {
-            int a[U];
-            int32_t w[U];
-            uint64_t kk[U];
-            uint32_t act = 0, pred = 0, meet = 0, claim = 0;
+        // The owners and column reads of the next batch are issued before
+        // the current batch's records are probed, so their latencies overlap.
+        auto fetch = [&](int64_t eb, int *a, int32_t *w, uint32_t &act) {
+            act = 0;
 #pragma unroll
             for (int j = 0; j < U; ++j) {
-                const int64_t e = e0 + 64 * j + lane;
+                const int64_t e = eb + 64 * j + lane;
                 a[j] = 0;
                 w[j] = 0;
                 if (e < total) {
@@ -284,6 +283,18 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
                     w[j] = c.g.ci[sm.e.rs[lo_i] + (e - sm.e.off[lo_i])];
                 }
             }
+        };
+        int a[U];
+        int32_t w[U];
+        uint32_t act;
+        fetch((int64_t)(tid >> 6) * 64 * U, a, w, act);
+        for (int64_t e0 = (int64_t)(tid >> 6) * 64 * U; e0 < total; e0 += (int64_t)BS * U) {
+            int an[U];
+            int32_t wn[U];
+            uint32_t actn = 0;
+            if (e0 + (int64_t)BS * U < total) fetch(e0 + (int64_t)BS * U, an, wn, actn);
+            uint64_t kk[U];
+            uint32_t pred = 0, meet = 0, claim = 0;
             if (probe) {
 #pragma unroll
                 for (int j = 0; j < U; ++j)
@@ -367,6 +378,12 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
 #pragma unroll
             for (int j = 0; j < U; ++j) nd += (disc >> j & 1) ? (unsigned long long)c.g.deg[w[j]] : 0ull;
             ls.visited += __popc(disc);
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                a[j] = an[j];
+                w[j] = wn[j];
+            }
+            act = actn;
         }
         __syncthreads();
         if (k >= 1 && tid < cnt) st_sig(c.R + sm.e.u[tid], sm.e.acc[tid]);
