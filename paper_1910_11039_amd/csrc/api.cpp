@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <string>
 #include <vector>
@@ -356,7 +357,7 @@ static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, ui
 // samples are short, each then samples sixteen rounds of its own wave.  Fewer,
 // wider workgroups trade parallelism inside a sample for a smaller combined
 // visited-state footprint, and the balance depends on the graph.  The
-// fastest shape wins, but 1024 is kept within 5% of it.  Epoch size: see
+// widest shape within 5% of the fastest wins.  Epoch size: see
 // the end of autotune().
 static int cands_block(int i)
 {
@@ -410,13 +411,11 @@ static kad_status autotune(kad_sampler *s)
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        // the fastest shape, except that the 1024-thread one is kept when it
-        // is within 5% of the fastest: timing noise between near-equal
-        // shapes does not flip the choice from run to run
+        // the widest shape within 5% of the fastest: timing noise between
+        // near-equal shapes does not flip the choice from run to run
         int pick = 0;
-        for (int i = 1; i < 3; ++i)
-            if (s->tune_rate[i] > s->tune_rate[pick]) pick = i;
-        if (s->tune_rate[2] >= 0.95 * best) pick = 2;
+        for (int i = 0; i < 3; ++i)
+            if (s->tune_rate[i] >= 0.95 * best) pick = i;
         best_b = cands[pick];
         best_slots = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(cands[pick]));
         s->block = best_b;
@@ -550,7 +549,7 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
               alloc((void **)&s->queues, 4ull * n * s->P * s->slots) &&
               alloc((void **)&s->mbufs, 4ull * n * s->P * s->slots) &&
               alloc((void **)&s->macc, 16ull * (size_t)s->macc_cap * s->P * s->slots) &&
-              alloc((void **)&s->stamps, 4ull * s->P * s->slots) && alloc((void **)&s->work_ctr, 32) &&
+              alloc((void **)&s->stamps, 4ull * s->P * s->slots) && alloc((void **)&s->work_ctr, 64) &&
               alloc((void **)&s->stats, sizeof(SampleStats)) && alloc((void **)&s->cal_stats, sizeof(SampleStats)) &&
               alloc((void **)&s->es, sizeof(EpochState)) &&
               alloc((void **)&s->hist, epoch_hist_bytes() * s->hist_cap);
@@ -655,6 +654,7 @@ static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, ui
     hipStream_t st = s->ctx->stream;
     SampleLaunch a = base_launch(s);
     if (stats) a.stats = stats;
+    a.work_ctr = s->work_ctr + 4;   // a counter of its own: pool 0's stays at zero for its epochs
     a.stream = stream;
     a.first = first;
     a.count = count;
@@ -663,11 +663,9 @@ static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, ui
     a.paths = paths;
     a.info = info;
     a.max_len = max_len;
-    HIPCHK(hipMemsetAsync(s->work_ctr, 0, sizeof(unsigned long long), st));
+    HIPCHK(hipMemsetAsync(a.work_ctr, 0, sizeof(unsigned long long), st));
     const int slots = (int)std::min<uint64_t>(s->slots, count);
     HIPCHK(launch_sampler(a, slots, s->block, st));
-    // the epoch loop expects the sample counter at zero
-    HIPCHK(hipMemsetAsync(s->work_ctr, 0, sizeof(unsigned long long), st));
     return KAD_OK;
 }
 
@@ -770,7 +768,9 @@ static bool alloc_is_valid(kad_sampler *s)
     return finite && sum <= 0.5 * s->o.delta;
 }
 
-static kad_status ensure_delta(kad_sampler *s)
+// `after_calibration` (optional) runs once the calibration's sampler is
+// enqueued, before the host waits for the allocation.
+static kad_status ensure_delta(kad_sampler *s, const std::function<kad_status()> &after_calibration = {})
 {
     if (s->delta_ready) return KAD_OK;
     hipStream_t st = s->ctx->stream;
@@ -804,6 +804,7 @@ static kad_status ensure_delta(kad_sampler *s)
         HIPCHK(hipMemsetAsync(s->cprime, 0, 4ull * n, st));
         HIPCHK(hipMemsetAsync(s->cal_stats, 0, sizeof(SampleStats), st));
         kad_status r = count_into(s, KAD_STREAM_CALIB, 0, s->tau0, s->cprime, nullptr, nullptr, 0, s->cal_stats);
+        if (r == KAD_OK && after_calibration) r = after_calibration();
         if (r != KAD_OK) return r;
         a.counts = s->cprime;
         a.tau0 = (double)s->tau0;
@@ -977,8 +978,9 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
     };
     // Adaptive samples do not depend on the delta allocation, only their
     // merges do: when a plain allocation is still to come, the samplers of
-    // epochs 1 .. P-1 start first on their pools and run beside the
-    // calibration (pool 0, stream 0); epoch 0 and the merges follow it.
+    // epochs 1 .. P-1 start on their pools right after the calibration's
+    // (pool 0, stream 0) and fill its tail; epoch 0 and the merges follow
+    // the allocation.
     // The learned allocation is a chain of short launches that would wait
     // for CUs behind those samplers, so it runs first on an idle GPU.
     const unsigned long long total = (s->cap + s->E - 1) / s->E;
@@ -987,16 +989,19 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
     kad_status r = read_state(s);   // the allocation does not touch the epoch state
     if (r != KAD_OK) return r;
     if (!s->delta_ready && s->o.alloc_mode == KAD_ALLOC_PLAIN && !graph_path && s->P > 1 &&
-        s->next_epoch == 0 && !s->h_es->stopped) {
+        s->next_epoch == 0 && !s->h_es->stopped)
         pre_hi = std::min<unsigned long long>((unsigned long long)s->P, total);
+    // the calibration is enqueued first, so that its workgroups take the
+    // CUs before the early samplers fill in behind it
+    r = ensure_delta(s, [&]() -> kad_status {
         for (unsigned long long k = 1; k < pre_hi; ++k) {
             hipEvent_t e0, e1;
             kad_status rr = timing_events(&e0, &e1);
             if (rr == KAD_OK) rr = enqueue_sampler_k(s, k, e0, e1);
             if (rr != KAD_OK) return rr;
         }
-    }
-    r = ensure_delta(s);
+        return KAD_OK;
+    });
     if (r != KAD_OK) return r;
     if (pre_hi > 0) {
         hipEvent_t e0, e1;
