@@ -336,21 +336,42 @@ __global__ void k_argmax_degree(DevGraph g, unsigned long long *best)
     if ((threadIdx.x & 63) == 0) atomicMax(best, b);
 }
 
-__global__ void k_bfs_init(int32_t n, int32_t *dist, int32_t src, int32_t *fr, int32_t *sizes)
+// Source of the next sweep, as an internal id in *src: the caller-smallest
+// vertex of maximum degree (from k_argmax_degree's packed key) for the
+// first sweep, else the caller-smallest vertex at the previous sweep's
+// last depth (*far, a caller id, reset here for the sweep to come).  Also
+// sets the frontier state for a frontier holding the source alone.
+__global__ void k_bfs_source(DevGraph g, const unsigned long long *key, int32_t *far, int32_t *src,
+                             int32_t *sizes)
 {
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        dist[v] = (v == src) ? 0 : -1;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        fr[0] = src;
-        sizes[0] = 1;   // current frontier size
-        sizes[1] = 0;   // next frontier size
-        sizes[2] = 0;   // depth of the current frontier
-    }
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int32_t caller = key ? (int32_t)(0xFFFFFFFFull - (*key & 0xFFFFFFFFull)) : *far;
+    const int32_t v = g.newid[caller];
+    *far = 0x7fffffff;
+    *src = v;
+    const int64_t d0 = g.rp[v + 1] - g.rp[v];
+    for (int i = 0; i < 12; ++i) sizes[i] = 0;
+    sizes[0] = 1;                                  // current frontier size
+    sizes[5] = (int32_t)(uint32_t)(d0 & 0xffffffff);
+    sizes[6] = (int32_t)(d0 >> 32);                // its degree sum
+    sizes[10] = 1;                                 // listed
 }
 
-// Smallest caller id among the vertices at `depth`.
-__global__ void k_min_at_depth(int32_t n, const int32_t *dist, const int32_t *orig, int32_t depth, int32_t *out)
+__global__ void k_bfs_init(int32_t n, int32_t *dist, const int32_t *src, int32_t *fr)
 {
+    const int32_t s0 = *src;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        dist[v] = (v == s0) ? 0 : -1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) fr[0] = s0;
+}
+
+// Smallest caller id among the vertices at the sweep's last depth (sz[3],
+// which is also recorded as the sweep's eccentricity in *ecc).
+__global__ void k_min_at_depth(int32_t n, const int32_t *dist, const int32_t *orig, const int32_t *sz,
+                               int32_t *out, int32_t *ecc)
+{
+    const int32_t depth = sz[3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ecc = depth;
     int32_t b = 0x7fffffff;
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
         if (dist[v] == depth && orig[v] < b) b = orig[v];
@@ -474,8 +495,20 @@ __global__ void k_bfs_collect(int32_t n, const int32_t *dist, int32_t *buf0, int
     const int32_t fsize = sz[0], depth = sz[2];
     if (fsize == 0 || sz[10] != 0 || bfs_bottom_up(sz, lim)) return;
     int32_t *cur = (depth & 1) ? buf1 : buf0;
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        if (dist[v] == depth) cur[atomicAdd(&sz[4], 1)] = v;
+    const int lane = threadIdx.x & 63;
+    // one atomic per wave: every lane of a wave runs the same trip count
+    const int64_t span = ((int64_t)n + 63) & ~63ll;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < span; v += (int64_t)gridDim.x * blockDim.x) {
+        const bool hit = v < n && dist[v] == depth;
+        const uint64_t m = __ballot(hit);
+        if (m == 0) continue;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&sz[4], __popcll(m));
+        base = __shfl(base, leader);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (hit) cur[base + (int)below] = (int32_t)v;
+    }
 }
 
 // One top-down level: a wave per frontier vertex; rows longer than HEAVY
@@ -604,12 +637,18 @@ __global__ void k_bfs_bu(DevGraph g, int32_t *dist, uint64_t *bits0, uint64_t *b
         bool found = false;
         if (v < g.n && dist[v] == -1) {
             const int64_t b = g.rp[v], e1 = g.rp[v + 1];
-            for (int64_t e = b; e < e1; ++e) {
-                const int32_t u = g.ci[e];
-                if ((cur[u >> 6] >> (u & 63)) & 1ull) {
-                    found = true;
-                    break;
-                }
+            // eight probes in flight, then the first hit among them
+            constexpr int B = 8;
+            for (int64_t e0 = b; e0 < e1 && !found; e0 += B) {
+                int32_t u[B];
+#pragma unroll
+                for (int j = 0; j < B; ++j) u[j] = (e0 + j < e1) ? g.ci[e0 + j] : -1;
+                uint64_t wd[B];
+#pragma unroll
+                for (int j = 0; j < B; ++j) wd[j] = u[j] >= 0 ? cur[u[j] >> 6] : 0ull;
+#pragma unroll
+                for (int j = 0; j < B; ++j)
+                    if (u[j] >= 0 && ((wd[j] >> (u[j] & 63)) & 1ull)) found = true;
             }
             if (found) {
                 dist[v] = depth + 1;
@@ -843,37 +882,32 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
     if ((e = hipMallocAsync((void **)&bits1, sizeof(uint64_t) * nwords, st)) != hipSuccess) return e;
     if ((e = hipMallocAsync((void **)&sizes, sizeof(int32_t) * 12, st)) != hipSuccess) return e;
     if ((e = hipMallocAsync((void **)&best, sizeof(unsigned long long), st)) != hipSuccess) return e;
+    int32_t *pick = nullptr;   // {source (internal id), far vertex (caller id), ecc x 3}
+    if ((e = hipMallocAsync((void **)&pick, sizeof(int32_t) * 5, st)) != hipSuccess) return e;
     CK(hipMemsetAsync(best, 0, sizeof(unsigned long long), st));
     hipLaunchKernelGGL(k_argmax_degree, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, g, best);
-    unsigned long long hb = 0;
-    CK(hipMemcpyAsync(&hb, best, sizeof(hb), hipMemcpyDeviceToHost, st));
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    int32_t r = 0;     // internal id of the caller-smallest vertex of maximum degree
-    {
-        const int32_t r_caller = (int32_t)(0xFFFFFFFFull - (hb & 0xFFFFFFFFull));
-        CK(hipMemcpyAsync(&r, g.newid + r_caller, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    }
 
-    // Direction-optimising BFS enqueued in batches of steps; the host only
-    // looks at the frontier size between batches.
+    // Three sweeps of a direction-optimising BFS, each enqueued in batches
+    // of steps; the next sweep's source is picked on the device, and the
+    // host only looks at the frontier size between batches.
     BfsLim lim;
     lim.big_v = std::max<int32_t>(n / 16, 1 << 14);
     lim.big_e = std::max<int64_t>(g.nnz / 16, (int64_t)1 << 20);
-    auto bfs = [&](int32_t src, int32_t *ecc, int32_t *far) -> hipError_t {
-        hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, 256)), dim3(256), 0, st, n, dist, src, fa, sizes);
-        int64_t rp2[2];
-        CK(hipMemcpyAsync(rp2, g.rp + src, sizeof(rp2), hipMemcpyDeviceToHost, st));
-        CK(hipStreamSynchronize(st));
-        const int64_t d0 = rp2[1] - rp2[0];
-        int32_t hs[12] = {0};
-        hs[0] = 1;
-        hs[5] = (int32_t)(uint32_t)(d0 & 0xffffffff);
-        hs[6] = (int32_t)(d0 >> 32);
-        hs[10] = 1;
-        CK(hipMemcpyAsync(sizes, hs, sizeof(hs), hipMemcpyHostToDevice, st));
-        for (int64_t steps = 0; steps <= (int64_t)n + 1; steps += 8) {
-            for (int k = 0; k < 8; ++k) {
+    int32_t er_first = 0;
+    for (int sweep = 0; sweep < 3; ++sweep) {
+        hipLaunchKernelGGL(k_bfs_source, dim3(1), dim3(1), 0, st, g, sweep == 0 ? best : nullptr, pick + 1,
+                           pick, sizes);
+        hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, 256)), dim3(256), 0, st, n, dist, pick, fa);
+        // Batch sizes: the first sweep takes 8 steps, then 4 at a time; a
+        // later sweep starts from a vertex at the first sweep's last depth,
+        // so its eccentricity is at least that depth (er): min(er + 2, 16)
+        // steps first (a step may run many small levels), then 2 at a
+        // time.  A step past the last level does nothing but still costs
+        // its launches.
+        int32_t hs[4] = {1, 0, 0, 0};
+        int32_t batch = sweep == 0 ? 8 : std::min<int32_t>(std::max<int32_t>(er_first + 2, 2), 16);
+        for (int64_t steps = 0; steps <= (int64_t)n + 1; steps += batch, batch = sweep == 0 ? 4 : 2) {
+            for (int k = 0; k < batch; ++k) {
                 hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(1024), 0, st, g, dist, fa, fb, sizes);
                 hipLaunchKernelGGL(k_bfs_collect, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, dist, fa, fb,
                                    sizes, lim);
@@ -890,21 +924,14 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
             if (hs[0] == 0) break;
         }
         if (hs[0] != 0) return hipErrorUnknown;   // more levels than vertices: cannot happen
-        *ecc = hs[3];
-        int32_t init = 0x7fffffff;
-        CK(hipMemcpyAsync(sizes + 4, &init, sizeof(int32_t), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_min_at_depth, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, dist, g.orig, *ecc,
-                           sizes + 4);
-        int32_t far_caller = 0;
-        CK(hipMemcpyAsync(&far_caller, sizes + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        CK(hipStreamSynchronize(st));
-        CK(hipMemcpyAsync(far, g.newid + far_caller, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        return hipStreamSynchronize(st);
-    };
-    int32_t er, ea, eb, a, b, cfar;
-    if ((e = bfs(r, &er, &a)) != hipSuccess) return e;
-    if ((e = bfs(a, &ea, &b)) != hipSuccess) return e;
-    if ((e = bfs(b, &eb, &cfar)) != hipSuccess) return e;
+        if (sweep == 0) er_first = hs[3];
+        hipLaunchKernelGGL(k_min_at_depth, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, dist, g.orig, sizes,
+                           pick + 1, pick + 2 + sweep);
+    }
+    int32_t hp[5];
+    CK(hipMemcpyAsync(hp, pick, sizeof(hp), hipMemcpyDeviceToHost, st));
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    const int32_t er = hp[2], ea = hp[3], eb = hp[4];
     const int32_t lb = ea > eb ? ea : eb;
     int32_t mn = er < ea ? er : ea;
     mn = eb < mn ? eb : mn;
@@ -918,6 +945,7 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
     CK(hipFreeAsync(bits1, st));
     CK(hipFreeAsync(sizes, st));
     CK(hipFreeAsync(best, st));
+    CK(hipFreeAsync(pick, st));
     return hipGetLastError();
 }
 
