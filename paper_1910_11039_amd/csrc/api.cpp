@@ -75,8 +75,10 @@ struct kad_sampler {
     // stream k mod P, so that later epochs sample while epoch k finishes
     // its tail
     int P;
+    int cal_pool;   // pool index of the calibration's slots: P when memory holds a pool of its own, else 0
     hipStream_t sts[4];          // sts[0] is the context's stream
     hipEvent_t ev_merge[4];
+    hipEvent_t ev_cal = nullptr;   // the allocation done on the calibration's stream
     std::vector<hipEvent_t> ev_ring;   // one per epoch in flight: its merge is done
     HostStatus *h_status, *d_status;   // pinned verdict mirror
     unsigned long long next_epoch;     // epochs enqueued since the reset
@@ -305,6 +307,7 @@ static void free_sampler(kad_sampler *s)
         (void)hipStreamDestroy(s->aux);
     }
     if (s->ev_aux) (void)hipEventDestroy(s->ev_aux);
+    if (s->ev_cal) (void)hipEventDestroy(s->ev_cal);
     if (s->yhat) (void)hipFree(s->yhat);
     if (s->h_status) (void)hipHostFree(s->h_status);
     void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->sf[2], s->sf[3], s->cprime, s->scratch_counts, s->LL, s->LU, s->lo_hi, s->macc,
@@ -348,7 +351,7 @@ static kad_status reset_epochs(kad_sampler *s)
 
 static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, uint64_t count,
                              uint32_t *target, int32_t *paths, int64_t *info, int32_t max_len,
-                             SampleStats *stats = nullptr);
+                             SampleStats *stats = nullptr, hipStream_t on = nullptr);
 
 // Autotuner (workgroup shape and samples per epoch).  Workgroup size:
 // each candidate (256, 512, 1024 threads, each with one full wave of
@@ -530,6 +533,11 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
         delete s;
         return fail(KAD_ENOMEM, "requested slots exceed the visited-state budget");
     }
+    // the calibration (and the other non-adaptive launches) get a pool of
+    // their own when memory holds one, so that all P first epochs can run
+    // beside the calibration
+    s->cal_pool = ((size_t)(s->P + 1) * (size_t)s->slots <= fit) ? s->P : 0;
+    const size_t pools_alloc = (size_t)s->P + (s->cal_pool ? 1 : 0);
     s->E = o->epoch_size;
     s->inflight = o->epochs_in_flight > 0 ? o->epochs_in_flight : 4;
     s->macc_cap = (int32_t)std::min<int64_t>(n, 1 << 16);   // larger meet sets take the slow path
@@ -545,11 +553,11 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
               alloc((void **)&s->scratch_counts, 4ull * n) && alloc((void **)&s->LL, 8ull * n) &&
               alloc((void **)&s->LU, 8ull * n) && alloc((void **)&s->lo_hi, 64) &&
               alloc((void **)&s->partials, 8 * alloc_partials(n)) && alloc((void **)&s->prior, 8ull * n) &&
-              alloc((void **)&s->recs, sizeof(Rec) * (size_t)n * s->P * s->slots) &&
-              alloc((void **)&s->queues, 4ull * n * s->P * s->slots) &&
-              alloc((void **)&s->mbufs, 4ull * n * s->P * s->slots) &&
-              alloc((void **)&s->macc, 16ull * (size_t)s->macc_cap * s->P * s->slots) &&
-              alloc((void **)&s->stamps, 4ull * s->P * s->slots) && alloc((void **)&s->work_ctr, 64) &&
+              alloc((void **)&s->recs, sizeof(Rec) * (size_t)n * pools_alloc * s->slots) &&
+              alloc((void **)&s->queues, 4ull * n * pools_alloc * s->slots) &&
+              alloc((void **)&s->mbufs, 4ull * n * pools_alloc * s->slots) &&
+              alloc((void **)&s->macc, 16ull * (size_t)s->macc_cap * pools_alloc * s->slots) &&
+              alloc((void **)&s->stamps, 4ull * pools_alloc * s->slots) && alloc((void **)&s->work_ctr, 64) &&
               alloc((void **)&s->stats, sizeof(SampleStats)) && alloc((void **)&s->cal_stats, sizeof(SampleStats)) &&
               alloc((void **)&s->es, sizeof(EpochState)) &&
               alloc((void **)&s->hist, epoch_hist_bytes() * s->hist_cap);
@@ -567,10 +575,11 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     }
     s->ev_ring.resize(std::max(s->inflight, s->P) + 1);
     for (auto &e : s->ev_ring) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&s->ev_cal, hipEventDisableTiming));
     HIPCHK(hipStreamCreate(&s->aux));
     HIPCHK(hipEventCreateWithFlags(&s->ev_aux, hipEventDisableTiming));
-    HIPCHK(hipMemsetAsync(s->recs, 0, sizeof(Rec) * (size_t)n * s->P * s->slots, st));
-    HIPCHK(hipMemsetAsync(s->stamps, 0, 4ull * s->P * s->slots, st));
+    HIPCHK(hipMemsetAsync(s->recs, 0, sizeof(Rec) * (size_t)n * pools_alloc * s->slots, st));
+    HIPCHK(hipMemsetAsync(s->stamps, 0, 4ull * pools_alloc * s->slots, st));
     kad_status rs = autotune(s);
     if (rs != KAD_OK) { free_sampler(s); return rs; }
     rs = reset_epochs(s);
@@ -648,11 +657,11 @@ static SampleLaunch base_launch(kad_sampler *s, int pool = 0)
 // Non-adaptive samples [first, first+count) of `stream` counted into `target`.
 static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, uint64_t count,
                              uint32_t *target, int32_t *paths, int64_t *info, int32_t max_len,
-                             SampleStats *stats)
+                             SampleStats *stats, hipStream_t on)
 {
     if (count == 0) return KAD_OK;
-    hipStream_t st = s->ctx->stream;
-    SampleLaunch a = base_launch(s);
+    hipStream_t st = on ? on : s->ctx->stream;
+    SampleLaunch a = base_launch(s, s->cal_pool);
     if (stats) a.stats = stats;
     a.work_ctr = s->work_ctr + 4;   // a counter of its own: pool 0's stays at zero for its epochs
     a.stream = stream;
@@ -669,11 +678,12 @@ static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, ui
     return KAD_OK;
 }
 
-static kad_status check_stats_error(kad_sampler *s, const SampleStats *src = nullptr)
+static kad_status check_stats_error(kad_sampler *s, const SampleStats *src = nullptr, hipStream_t on = nullptr)
 {
     SampleStats h;
-    HIPCHK(hipMemcpyAsync(&h, src ? src : s->stats, sizeof(h), hipMemcpyDeviceToHost, s->ctx->stream));
-    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    hipStream_t st = on ? on : s->ctx->stream;
+    HIPCHK(hipMemcpyAsync(&h, src ? src : s->stats, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     if (h.error == 1) return fail(KAD_ENOTCONNECTED, "a sampled pair has no path: graph not connected");
     if (h.error == 2) return fail(KAD_EOVERFLOW, "a path is longer than max_len - 1");
     if (h.error == 3) return fail(KAD_EDEVICE, "internal error: a path choice found no candidate");
@@ -769,8 +779,10 @@ static bool alloc_is_valid(kad_sampler *s)
 }
 
 // `after_calibration` (optional) runs once the calibration's sampler is
-// enqueued, before the host waits for the allocation.
-static kad_status ensure_delta(kad_sampler *s, const std::function<kad_status()> &after_calibration = {})
+// enqueued, before the host waits for the allocation; `cal_stream`
+// (optional) carries the calibration and the plain allocation.
+static kad_status ensure_delta(kad_sampler *s, const std::function<kad_status()> &after_calibration = {},
+                               hipStream_t cal_stream = nullptr)
 {
     if (s->delta_ready) return KAD_OK;
     hipStream_t st = s->ctx->stream;
@@ -801,18 +813,19 @@ static kad_status ensure_delta(kad_sampler *s, const std::function<kad_status()>
     if (!learned) {
         // Phase 2 (Sec. III-A): tau0 = ceil(omega / 100) non-adaptive samples on stream 1.
         s->tau0 = (uint64_t)ceil(s->omega / 100.0);
-        HIPCHK(hipMemsetAsync(s->cprime, 0, 4ull * n, st));
-        HIPCHK(hipMemsetAsync(s->cal_stats, 0, sizeof(SampleStats), st));
-        kad_status r = count_into(s, KAD_STREAM_CALIB, 0, s->tau0, s->cprime, nullptr, nullptr, 0, s->cal_stats);
+        hipStream_t cst = cal_stream ? cal_stream : st;
+        HIPCHK(hipMemsetAsync(s->cprime, 0, 4ull * n, cst));
+        HIPCHK(hipMemsetAsync(s->cal_stats, 0, sizeof(SampleStats), cst));
+        kad_status r = count_into(s, KAD_STREAM_CALIB, 0, s->tau0, s->cprime, nullptr, nullptr, 0, s->cal_stats, cst);
         if (r == KAD_OK && after_calibration) r = after_calibration();
         if (r != KAD_OK) return r;
         a.counts = s->cprime;
         a.tau0 = (double)s->tau0;
         double C = 0.0;
-        HIPCHK(run_alloc(a, st, &C));
-        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(run_alloc(a, cst, &C));
+        HIPCHK(hipStreamSynchronize(cst));
         s->C = C;
-        r = check_stats_error(s, s->cal_stats);
+        r = check_stats_error(s, s->cal_stats, cst);
         if (r != KAD_OK) return r;
     }
     s->res.tau0 = learned ? 0 : s->tau0;
@@ -991,22 +1004,34 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
     if (!s->delta_ready && s->o.alloc_mode == KAD_ALLOC_PLAIN && !graph_path && s->P > 1 &&
         s->next_epoch == 0 && !s->h_es->stopped)
         pre_hi = std::min<unsigned long long>((unsigned long long)s->P, total);
-    // the calibration is enqueued first, so that its workgroups take the
-    // CUs before the early samplers fill in behind it
+    // The calibration is enqueued first, so that its workgroups take the
+    // CUs before the early samplers fill in behind it.  With slots of its
+    // own it runs on the last pool's stream and only that pool's epoch
+    // waits for the allocation; otherwise it uses pool 0 and epoch 0 waits.
+    const bool own_cal = pre_hi > 0 && s->cal_pool != 0 && s->P > 1;
+    const unsigned long long late = own_cal ? (unsigned long long)(s->P - 1) : 0;
+    hipStream_t cst = own_cal ? s->sts[s->P - 1] : nullptr;
     r = ensure_delta(s, [&]() -> kad_status {
-        for (unsigned long long k = 1; k < pre_hi; ++k) {
+        for (unsigned long long k = 0; k < pre_hi; ++k) {
+            if (k == late) continue;
             hipEvent_t e0, e1;
             kad_status rr = timing_events(&e0, &e1);
             if (rr == KAD_OK) rr = enqueue_sampler_k(s, k, e0, e1);
             if (rr != KAD_OK) return rr;
         }
         return KAD_OK;
-    });
+    }, cst);
     if (r != KAD_OK) return r;
     if (pre_hi > 0) {
-        hipEvent_t e0, e1;
-        r = timing_events(&e0, &e1);
-        if (r == KAD_OK) r = enqueue_sampler_k(s, 0, e0, e1);
+        if (own_cal) {   // the merges see the delta arrays written on that stream
+            HIPCHK(hipEventRecord(s->ev_cal, cst));
+            HIPCHK(hipStreamWaitEvent(s->sts[0], s->ev_cal, 0));
+        }
+        if (late < pre_hi) {
+            hipEvent_t e0, e1;
+            r = timing_events(&e0, &e1);
+            if (r == KAD_OK) r = enqueue_sampler_k(s, late, e0, e1);
+        }
         for (unsigned long long k = 0; r == KAD_OK && k < pre_hi; ++k) r = enqueue_merge_k(s, k);
         if (r != KAD_OK) return r;
         s->next_epoch = pre_hi;

@@ -132,6 +132,20 @@ def test_launch_shapes_give_identical_counts(ctx, oracle, block, slots):
     assert np.array_equal(c, want)
 
 
+@pytest.mark.parametrize("block", [64, 128])
+def test_reached_filter_aliasing_gives_identical_counts(ctx, oracle, block):
+    """More vertices than the small shapes' LDS filter has bits (32 768), so
+    distinct vertices share bits and probe scans must fall back to reading
+    their records."""
+    g = gg.rmat(16, 16, 21)
+    assert g.n > 32768
+    G = upload(ctx, g)
+    S, _ = explicit_sampler(G, g, oracle, block_size=block)
+    c = S.count_samples(0, 0, 1500)
+    want, _ = oracle.count(g, 1, 0, 0, 1500)
+    assert np.array_equal(c, want)
+
+
 def _run_and_compare(S, g, oracle, omega, eps, epoch, seed=1):
     r = S.run_to_stop()
     c, tau = S.counts()
