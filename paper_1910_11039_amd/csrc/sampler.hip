@@ -29,11 +29,15 @@
 //
 // Expansion (integer mode) is edge-parallel and load-balanced: a chunk of
 // up to BS frontier vertices is staged in LDS with the exclusive scan of
-// their degrees, every lane takes one adjacency entry, finds its owner by
-// binary search in LDS, and sigma contributions go to per-owner LDS
-// accumulators.  New frontier entries are compacted with a wave ballot and
-// mbcnt prefix, one LDS atomic per wave.  FP mode is vertex-parallel so that
-// every sum runs in CSR order in one lane.
+// their degrees, every lane takes four adjacency entries at a time, finds
+// their owners by binary search in LDS, and sigma contributions go to
+// per-owner LDS accumulators.  New frontier entries are compacted with a
+// wave ballot and mbcnt prefix, one LDS atomic per wave.  A step likely to
+// meet is first scanned without claiming (the new layer of a step that
+// meets is never used), and an LDS bit filter of the vertices the sample
+// has reached lets that scan skip most entries without reading their
+// records.  FP mode is vertex-parallel so that every sum runs in CSR order
+// in one lane.
 #include "kad_internal.h"
 #include "philox.h"
 
