@@ -116,8 +116,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "epoch aggregation is not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); aggregating "
+              "epochs across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_probe:

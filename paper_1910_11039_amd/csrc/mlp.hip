@@ -51,11 +51,14 @@ constexpr int64_t FSHORT = 32;     // rows up to this long: a thread per vertex
 
 // Short rows (most vertices of a power-law graph): a thread per vertex, its
 // entries eight at a time.
-__global__ void k_features_short(DevGraph g, float *out)
+// (Vertices are numbered by descending degree: the short rows are those of
+// vertices bnd[1] .. n-1.)
+__global__ void k_features_short(DevGraph g, const int32_t *bnd, float *out)
 {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t first = bnd[1];
+    for (int64_t v = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t beg = g.rp[v], end = g.rp[v + 1];
-        if (end - beg > FSHORT) continue;
         double acc = 0.0, sd = 0.0;
         constexpr int B = 8;
         for (int64_t e0 = beg; e0 < end; e0 += B) {
@@ -76,17 +79,16 @@ __global__ void k_features_short(DevGraph g, float *out)
     }
 }
 
-// Rows of FSHORT + 1 .. FPIECE entries: a wave per vertex.  (Vertices are
-// numbered by descending degree, so the long rows are those of vertices
-// 0 .. H-1.)
-__global__ void k_features(DevGraph g, float *out)
+// Rows of FSHORT + 1 .. FPIECE entries: a wave per vertex, vertices
+// bnd[0] .. bnd[1]-1 (the longer rows, vertices 0 .. bnd[0]-1, go in pieces).
+__global__ void k_features(DevGraph g, const int32_t *bnd, float *out)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t v = wave; v < g.n; v += waves) {
+    const int64_t lo = bnd[0], hi = bnd[1];
+    for (int64_t v = lo + wave; v < hi; v += waves) {
         const int64_t beg = g.rp[v], end = g.rp[v + 1];
-        if (end - beg > FPIECE || end - beg <= FSHORT) continue;
         double acc = 0.0, sd = 0.0;
         // eight entries per lane in flight: a hub's row is a long serial
         // loop for its one wave, and the loads dominate it
@@ -131,7 +133,13 @@ __global__ __launch_bounds__(1024) void k_feat_pieces(DevGraph g, int64_t *pref,
         }
         sH = lo;
         s_run = 0;
-        *H_out = lo;
+        H_out[0] = lo;
+        hi = g.n;                      // first vertex with at most FSHORT entries
+        while (lo < hi) {
+            const int32_t mid = lo + ((hi - lo) >> 1);
+            if ((int64_t)g.deg[mid] > FSHORT) lo = mid + 1; else hi = mid;
+        }
+        H_out[1] = lo;
     }
     __syncthreads();
     const int32_t H = sH;
@@ -424,20 +432,20 @@ size_t mlp_scratch_floats(int64_t rows) { return (size_t)blocks_for_rows(rows) *
 hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st)
 {
     hipError_t e;
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_features_short, dim3((unsigned)blocks), dim3(256), 0, st, g, out);
-    const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(g.n, 1 << 16));
-    hipLaunchKernelGGL(k_features, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, out);
     // long rows: every such row has more than FPIECE entries, so there are
     // at most nnz / FPIECE of them and at most 2 nnz / FPIECE + 1 pieces
     const int64_t hmax = g.nnz / FPIECE + 1, pmax = 2 * (g.nnz / FPIECE) + 1;
     int64_t *pref = nullptr;
-    int32_t *H = nullptr;
+    int32_t *H = nullptr;      // {first vertex of at most FPIECE entries, of at most FSHORT}
     double2 *part = nullptr;
     if ((e = hipMallocAsync((void **)&pref, sizeof(int64_t) * (size_t)(hmax + 1), st)) != hipSuccess) return e;
-    if ((e = hipMallocAsync((void **)&H, sizeof(int32_t), st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&H, sizeof(int32_t) * 2, st)) != hipSuccess) return e;
     if ((e = hipMallocAsync((void **)&part, sizeof(double2) * (size_t)pmax, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_feat_pieces, dim3(1), dim3(1024), 0, st, g, pref, H);
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_features_short, dim3((unsigned)blocks), dim3(256), 0, st, g, H, out);
+    const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(g.n, 1 << 16));
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, H, out);
     hipLaunchKernelGGL(k_feat_sum, dim3(2048), dim3(256), 0, st, g, pref, H, part);
     hipLaunchKernelGGL(k_feat_combine, dim3(64), dim3(256), 0, st, g, pref, H, part, out);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -1,4 +1,4 @@
-"""Pins of the exact betweenness judge and of the (eps, delta) guarantee.
+"""Pins of the exact betweenness reference (Brandes) and of the (eps, delta) guarantee.
 
 Betweenness here is the paper's normalisation (Sec. I): ordered pairs,
 divided by n(n-1).  networkx normalises undirected graphs by
