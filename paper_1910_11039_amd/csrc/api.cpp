@@ -857,7 +857,8 @@ static kad_status enqueue_epoch(kad_sampler *s, hipEvent_t ev0, hipEvent_t ev1)
 // merge of epoch k - 1, so c~ grows and the rule is checked in epoch order
 // on exactly samples [0, tau).  A sampler whose epoch turns out to follow
 // the stop quits at its next sample; its frame is never merged.
-static kad_status enqueue_sampler_k(kad_sampler *s, unsigned long long k, hipEvent_t ev0, hipEvent_t ev1)
+static kad_status enqueue_sampler_k(kad_sampler *s, unsigned long long k, hipEvent_t ev0, hipEvent_t ev1,
+                                    int width = 0)
 {
     const int p = (int)(k % (unsigned long long)s->P);
     hipStream_t st = s->sts[p];
@@ -871,7 +872,8 @@ static kad_status enqueue_sampler_k(kad_sampler *s, unsigned long long k, hipEve
     // the pool's sample counter is zero here: set by the reset, then cleared
     // by the merge of this stream's previous epoch
     if (ev0) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_sampler(a, (int)std::min<unsigned long long>(s->slots, count), s->block, st));
+    const int w = width > 0 ? std::min(width, s->slots) : s->slots;
+    HIPCHK(launch_sampler(a, (int)std::min<unsigned long long>((unsigned long long)w, count), s->block, st));
     if (ev1) HIPCHK(hipEventRecord(ev1, st));
     return KAD_OK;
 }
@@ -1011,12 +1013,18 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
     const bool own_cal = pre_hi > 0 && s->cal_pool != 0 && s->P > 1;
     const unsigned long long late = own_cal ? (unsigned long long)(s->P - 1) : 0;
     hipStream_t cst = own_cal ? s->sts[s->P - 1] : nullptr;
+    // The early epochs share the slots between them and leave 16 free
+    // (eight CUs' worth at two workgroups per CU), so that the allocation's
+    // launches and the first merges find room instead of waiting for a
+    // whole epoch launch to drain.
+    const unsigned long long npre = pre_hi - (late < pre_hi ? 1 : 0);
+    const int pre_width = npre > 0 ? std::max(1, (int)((s->slots - std::min(16, s->slots / 4)) / (int)npre)) : 0;
     r = ensure_delta(s, [&]() -> kad_status {
         for (unsigned long long k = 0; k < pre_hi; ++k) {
             if (k == late) continue;
             hipEvent_t e0, e1;
             kad_status rr = timing_events(&e0, &e1);
-            if (rr == KAD_OK) rr = enqueue_sampler_k(s, k, e0, e1);
+            if (rr == KAD_OK) rr = enqueue_sampler_k(s, k, e0, e1, pre_width);
             if (rr != KAD_OK) return rr;
         }
         return KAD_OK;

@@ -261,7 +261,7 @@ __global__ void k_alloc_hist(AllocArgs a, uint32_t *hist, uint32_t top)
 // The whole bisection in one workgroup over the count histogram: per step,
 // thread t sums bins t, t + HB, ... in turn, then a pairwise tree (a fixed
 // order).  Same interval, step rule and stopping rule as the dense form.
-constexpr int HB = 1024;
+constexpr int HB = 256;   // a workgroup small enough to find room beside the samplers
 __global__ __launch_bounds__(HB) void k_alloc_bisect_hist(AllocArgs a, const uint32_t *hist, uint32_t top,
                                                           double target)
 {
@@ -488,6 +488,47 @@ __global__ __launch_bounds__(1024) void k_bfs_small(DevGraph g, int32_t *dist, i
     }
 }
 
+// Position for a lane's append to a shared list: one atomic per wave (every
+// lane of the wave must call; -1 for lanes that append nothing).
+__device__ __forceinline__ int32_t wave_append(int32_t *ctr, bool pred)
+{
+    const uint64_t m = __ballot(pred);
+    if (m == 0) return -1;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(ctr, (int32_t)__popcll(m));
+    base = __shfl(base, leader);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    return pred ? base + (int32_t)below : -1;
+}
+
+// Adds each thread's (count, degree sum) into sz[1] and sz[8..9] with one
+// atomic pair per workgroup (every thread of the workgroup must call).
+__device__ __forceinline__ void block_add_level(int32_t *sz, int cnt, unsigned long long dsum)
+{
+    __shared__ int s_cnt;
+    __shared__ unsigned long long s_dsum;
+    if (threadIdx.x == 0) {
+        s_cnt = 0;
+        s_dsum = 0;
+    }
+    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+        cnt += __shfl_xor(cnt, o);
+        dsum += __shfl_xor(dsum, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (cnt) atomicAdd(&s_cnt, cnt);
+        if (dsum) atomicAdd(&s_dsum, dsum);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_cnt) atomicAdd(&sz[1], s_cnt);
+        if (s_dsum) atomicAdd((unsigned long long *)&sz[8], s_dsum);
+    }
+}
+
 // List the frontier from dist when the previous level was bottom-up.
 __global__ void k_bfs_collect(int32_t n, const int32_t *dist, int32_t *buf0, int32_t *buf1, int32_t *sz,
                               BfsLim lim)
@@ -530,16 +571,22 @@ __global__ void k_bfs_td(DevGraph g, int32_t *dist, int32_t *buf0, int32_t *buf1
             if (lane == 0) heavy[atomicAdd(&sz[7], 1)] = u;
             continue;
         }
-        for (int64_t e = b + lane; e < e1; e += 64) {
-            const int32_t w = g.ci[e];
-            if (atomicCAS(&dist[w], -1, depth + 1) == -1) {
-                nxt[atomicAdd(&sz[1], 1)] = w;
+        for (int64_t e0 = b; e0 < e1; e0 += 64) {   // wave-uniform trip count
+            const int64_t e = e0 + lane;
+            int32_t w = 0;
+            bool claimed = false;
+            if (e < e1) {
+                w = g.ci[e];
+                claimed = atomicCAS(&dist[w], -1, depth + 1) == -1;
+            }
+            const int32_t pos = wave_append(&sz[1], claimed);
+            if (claimed) {
+                nxt[pos] = w;
                 dsum += (unsigned long long)g.deg[w];
             }
         }
     }
-    for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o);
-    if (lane == 0 && dsum) atomicAdd((unsigned long long *)&sz[8], dsum);
+    block_add_level(sz, 0, dsum);
 }
 
 // The heavy rows of a top-down level, cut into pieces of PIECE entries that
@@ -588,18 +635,24 @@ __global__ __launch_bounds__(256) void k_bfs_heavy(DevGraph g, int32_t *dist, co
             }
             const int64_t pb = s_beg[lo_i] + (gp - s_pre[lo_i]) * PIECE;
             const int64_t pe = min(pb + PIECE, s_end[lo_i]);
-            for (int64_t e = pb + tid; e < pe; e += 256) {
-                const int32_t w = g.ci[e];
-                if (atomicCAS(&dist[w], -1, depth + 1) == -1) {
-                    nxt[atomicAdd(&sz[1], 1)] = w;
+            for (int64_t e0 = pb; e0 < pe; e0 += 256) {   // uniform trip count
+                const int64_t e = e0 + tid;
+                int32_t w = 0;
+                bool claimed = false;
+                if (e < pe) {
+                    w = g.ci[e];
+                    claimed = atomicCAS(&dist[w], -1, depth + 1) == -1;
+                }
+                const int32_t pos = wave_append(&sz[1], claimed);
+                if (claimed) {
+                    nxt[pos] = w;
                     dsum += (unsigned long long)g.deg[w];
                 }
             }
         }
         __syncthreads();
     }
-    for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o);
-    if (lane == 0 && dsum) atomicAdd((unsigned long long *)&sz[8], dsum);
+    block_add_level(sz, 0, dsum);
 }
 
 // Frontier bitmap of the current depth from dist (before a bottom-up level
@@ -659,14 +712,7 @@ __global__ void k_bfs_bu(DevGraph g, int32_t *dist, uint64_t *bits0, uint64_t *b
         const uint64_t m = __ballot(found);
         if ((threadIdx.x & 63) == 0) nxt[v >> 6] = m;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        cnt += __shfl_xor(cnt, o);
-        dsum += __shfl_xor(dsum, o);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (cnt) atomicAdd(&sz[1], cnt);
-        if (dsum) atomicAdd((unsigned long long *)&sz[8], dsum);
-    }
+    block_add_level(sz, cnt, dsum);
 }
 
 // Close a level: the next frontier becomes the current one.
