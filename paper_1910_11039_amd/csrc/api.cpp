@@ -359,8 +359,9 @@ static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, ui
 // the tuning stream (counts discarded), timed with HIP events; when
 // samples are short, each then samples sixteen rounds of its own wave.  Fewer,
 // wider workgroups trade parallelism inside a sample for a smaller combined
-// visited-state footprint, and the balance depends on the graph.  The
-// widest shape within 5% of the fastest wins.  Epoch size: see
+// visited-state footprint, and the balance depends on the graph.  With
+// short samples the widest shape within 5% of the fastest wins; with long
+// ones the fastest, but 1024 is kept within 5% of it.  Epoch size: see
 // the end of autotune().
 static int cands_block(int i)
 {
@@ -384,6 +385,7 @@ static kad_status autotune(kad_sampler *s)
         // are short: sixteen rounds of each shape's own wave, the share of
         // an epoch that the epoch-size rule below gives it, so that a shape
         // with more slots is not judged on a trial dominated by its tail
+        bool short_samples = false;
         for (int pass = 0; pass < 2; ++pass) {
             if (pass == 1) {
                 int fastest = 0;
@@ -391,6 +393,7 @@ static kad_status autotune(kad_sampler *s)
                     if (s->tune_rate[i] > s->tune_rate[fastest]) fastest = i;
                 const int sl = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(cands[fastest]));
                 if ((double)sl / s->tune_rate[fastest] > 0.010) break;
+                short_samples = true;
                 best = -1.0;
             }
             for (int i = 0; i < 3; ++i) {
@@ -414,11 +417,19 @@ static kad_status autotune(kad_sampler *s)
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        // the widest shape within 5% of the fastest: timing noise between
-        // near-equal shapes does not flip the choice from run to run
+        // short samples: the widest shape within 5% of the fastest, so that
+        // timing noise between near-equal shapes does not flip the choice
+        // from run to run; long samples (one trial of few rounds): the
+        // fastest, but the 1024-thread shape within 5% of it
         int pick = 0;
-        for (int i = 0; i < 3; ++i)
-            if (s->tune_rate[i] >= 0.95 * best) pick = i;
+        if (short_samples) {
+            for (int i = 0; i < 3; ++i)
+                if (s->tune_rate[i] >= 0.95 * best) pick = i;
+        } else {
+            for (int i = 1; i < 3; ++i)
+                if (s->tune_rate[i] > s->tune_rate[pick]) pick = i;
+            if (s->tune_rate[2] >= 0.95 * best) pick = 2;
+        }
         best_b = cands[pick];
         best_slots = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(cands[pick]));
         s->block = best_b;

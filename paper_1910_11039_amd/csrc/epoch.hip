@@ -333,7 +333,12 @@ __global__ void k_argmax_degree(DevGraph g, unsigned long long *best)
         const unsigned long long y = __shfl_xor(b, o);
         b = y > b ? y : b;
     }
-    if ((threadIdx.x & 63) == 0) atomicMax(best, b);
+    __shared__ unsigned long long s_b;   // one global atomic per workgroup
+    if (threadIdx.x == 0) s_b = 0;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) atomicMax(&s_b, b);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_b) atomicMax(best, s_b);
 }
 
 // Source of the next sweep, as an internal id in *src: the caller-smallest
@@ -530,25 +535,37 @@ __device__ __forceinline__ void block_add_level(int32_t *sz, int cnt, unsigned l
 }
 
 // List the frontier from dist when the previous level was bottom-up.
-__global__ void k_bfs_collect(int32_t n, const int32_t *dist, int32_t *buf0, int32_t *buf1, int32_t *sz,
+__global__ __launch_bounds__(1024) void k_bfs_collect(int32_t n, const int32_t *dist, int32_t *buf0, int32_t *buf1, int32_t *sz,
                               BfsLim lim)
 {
     const int32_t fsize = sz[0], depth = sz[2];
     if (fsize == 0 || sz[10] != 0 || bfs_bottom_up(sz, lim)) return;
     int32_t *cur = (depth & 1) ? buf1 : buf0;
-    const int lane = threadIdx.x & 63;
-    // one atomic per wave: every lane of a wave runs the same trip count
-    const int64_t span = ((int64_t)n + 63) & ~63ll;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < span; v += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // one global atomic per workgroup and sweep of the grid: waves take
+    // their offsets in LDS, thread 0 reserves the workgroup's range (every
+    // thread runs the same trip count)
+    __shared__ int32_t s_wcnt[16], s_base;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    const int64_t span = ((int64_t)n + step - 1) / step * step;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < span; v += step) {
         const bool hit = v < n && dist[v] == depth;
         const uint64_t m = __ballot(hit);
-        if (m == 0) continue;
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&sz[4], __popcll(m));
-        base = __shfl(base, leader);
+        if (lane == 0) s_wcnt[wid] = __popcll(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t tot = 0;
+            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+                const int32_t c = s_wcnt[i];
+                s_wcnt[i] = tot;
+                tot += c;
+            }
+            s_base = tot ? atomicAdd(&sz[4], tot) : 0;
+        }
+        __syncthreads();
         const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if (hit) cur[base + (int)below] = (int32_t)v;
+        if (hit) cur[s_base + s_wcnt[wid] + (int)below] = (int32_t)v;
+        __syncthreads();
     }
 }
 
@@ -955,7 +972,7 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
         for (int64_t steps = 0; steps <= (int64_t)n + 1; steps += batch, batch = sweep == 0 ? 4 : 2) {
             for (int k = 0; k < batch; ++k) {
                 hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(1024), 0, st, g, dist, fa, fb, sizes);
-                hipLaunchKernelGGL(k_bfs_collect, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, dist, fa, fb,
+                hipLaunchKernelGGL(k_bfs_collect, dim3(grid_for(n, 1024, 1024)), dim3(1024), 0, st, n, dist, fa, fb,
                                    sizes, lim);
                 hipLaunchKernelGGL(k_bfs_td, dim3(2048), dim3(256), 0, st, g, dist, fa, fb, heavy, sizes, lim);
                 hipLaunchKernelGGL(k_bfs_heavy, dim3(1024), dim3(256), 0, st, g, dist, heavy, fa, fb, sizes, lim);
