@@ -93,6 +93,8 @@ struct kad_sampler {
     unsigned long long *work_ctr;
     SampleStats *stats;
     SampleStats *cal_stats;   // the calibration's samples (they may run beside adaptive epochs)
+    uint32_t *cal_hist = nullptr;   // histogram of the calibration counts, kept by its sampler
+    uint32_t cal_hist_top = 0;      // its last bin: tau0
     EpochState *es;
     void *hist;
     int32_t hist_cap;
@@ -308,6 +310,7 @@ static void free_sampler(kad_sampler *s)
     }
     if (s->ev_aux) (void)hipEventDestroy(s->ev_aux);
     if (s->ev_cal) (void)hipEventDestroy(s->ev_cal);
+    if (s->cal_hist) (void)hipFree(s->cal_hist);
     if (s->yhat) (void)hipFree(s->yhat);
     if (s->h_status) (void)hipHostFree(s->h_status);
     void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->sf[2], s->sf[3], s->cprime, s->scratch_counts, s->LL, s->LU, s->lo_hi, s->macc,
@@ -351,7 +354,8 @@ static kad_status reset_epochs(kad_sampler *s)
 
 static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, uint64_t count,
                              uint32_t *target, int32_t *paths, int64_t *info, int32_t max_len,
-                             SampleStats *stats = nullptr, hipStream_t on = nullptr);
+                             SampleStats *stats = nullptr, hipStream_t on = nullptr,
+                             uint32_t *hist = nullptr, uint32_t hist_top = 0);
 
 // Autotuner (workgroup shape and samples per epoch).  Workgroup size:
 // each candidate (256, 512, 1024 threads, each with one full wave of
@@ -668,7 +672,7 @@ static SampleLaunch base_launch(kad_sampler *s, int pool = 0)
 // Non-adaptive samples [first, first+count) of `stream` counted into `target`.
 static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, uint64_t count,
                              uint32_t *target, int32_t *paths, int64_t *info, int32_t max_len,
-                             SampleStats *stats, hipStream_t on)
+                             SampleStats *stats, hipStream_t on, uint32_t *hist, uint32_t hist_top)
 {
     if (count == 0) return KAD_OK;
     hipStream_t st = on ? on : s->ctx->stream;
@@ -683,6 +687,8 @@ static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, ui
     a.paths = paths;
     a.info = info;
     a.max_len = max_len;
+    a.hist = hist;
+    a.hist_top = hist_top;
     HIPCHK(hipMemsetAsync(a.work_ctr, 0, sizeof(unsigned long long), st));
     const int slots = (int)std::min<uint64_t>(s->slots, count);
     HIPCHK(launch_sampler(a, slots, s->block, st));
@@ -825,13 +831,28 @@ static kad_status ensure_delta(kad_sampler *s, const std::function<kad_status()>
         // Phase 2 (Sec. III-A): tau0 = ceil(omega / 100) non-adaptive samples on stream 1.
         s->tau0 = (uint64_t)ceil(s->omega / 100.0);
         hipStream_t cst = cal_stream ? cal_stream : st;
+        const uint32_t top = (uint32_t)std::max<uint64_t>(1, s->tau0);
+        if (s->cal_hist && s->cal_hist_top != top) {
+            (void)hipFree(s->cal_hist);
+            s->cal_hist = nullptr;
+        }
+        if (!s->cal_hist) {
+            if (hipMalloc((void **)&s->cal_hist, sizeof(uint32_t) * ((size_t)top + 1)) != hipSuccess) {
+                s->cal_hist = nullptr;
+                return fail(KAD_ENOMEM, "calibration histogram allocation failed");
+            }
+            s->cal_hist_top = top;
+        }
         HIPCHK(hipMemsetAsync(s->cprime, 0, 4ull * n, cst));
         HIPCHK(hipMemsetAsync(s->cal_stats, 0, sizeof(SampleStats), cst));
-        kad_status r = count_into(s, KAD_STREAM_CALIB, 0, s->tau0, s->cprime, nullptr, nullptr, 0, s->cal_stats, cst);
+        HIPCHK(hipMemsetAsync(s->cal_hist, 0, sizeof(uint32_t) * ((size_t)top + 1), cst));
+        kad_status r = count_into(s, KAD_STREAM_CALIB, 0, s->tau0, s->cprime, nullptr, nullptr, 0, s->cal_stats, cst,
+                                  s->cal_hist, top);
         if (r == KAD_OK && after_calibration) r = after_calibration();
         if (r != KAD_OK) return r;
         a.counts = s->cprime;
         a.tau0 = (double)s->tau0;
+        a.hist = s->cal_hist;
         double C = 0.0;
         HIPCHK(run_alloc(a, cst, &C));
         HIPCHK(hipStreamSynchronize(cst));

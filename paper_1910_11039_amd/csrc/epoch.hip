@@ -810,16 +810,19 @@ hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host)
     hipError_t e;
     const double target = 0.25 * a.delta * (1.0 - 1e-9);
     if (a.counts) {
-        // calibration counts: histogram, then the bisection in one launch
+        // calibration counts: histogram (unless the sampler kept it), then
+        // the bisection in one launch
         const uint32_t top = (uint32_t)std::max(1.0, a.tau0);
-        uint32_t *hist = nullptr;
-        if ((e = hipMallocAsync((void **)&hist, sizeof(uint32_t) * ((size_t)top + 1), st)) != hipSuccess)
-            return e;
-        CK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * ((size_t)top + 1), st));
-        // small grids: these run beside the adaptive samplers (see the merge)
-        hipLaunchKernelGGL(k_alloc_hist, dim3(grid_for(a.n, 256, 256)), dim3(256), 0, st, a, hist, top);
+        uint32_t *hist = a.hist;
+        if (!hist) {
+            if ((e = hipMallocAsync((void **)&hist, sizeof(uint32_t) * ((size_t)top + 1), st)) != hipSuccess)
+                return e;
+            CK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * ((size_t)top + 1), st));
+            // small grids: these run beside the adaptive samplers (see the merge)
+            hipLaunchKernelGGL(k_alloc_hist, dim3(grid_for(a.n, 256, 256)), dim3(256), 0, st, a, hist, top);
+        }
         hipLaunchKernelGGL(k_alloc_bisect_hist, dim3(1), dim3(HB), 0, st, a, hist, top, target);
-        CK(hipFreeAsync(hist, st));
+        if (!a.hist) CK(hipFreeAsync(hist, st));
         double fin[3];
         CK(hipMemcpyAsync(fin, a.lo_hi, sizeof(fin), hipMemcpyDeviceToHost, st));
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;

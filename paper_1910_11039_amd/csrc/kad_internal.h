@@ -103,6 +103,8 @@ struct SampleLaunch {
     int32_t *paths;                 // optional per-sample paths [count][max_len]
     int64_t *info;                  // optional per-sample info  [count][KAD_INFO_WIDTH]
     int32_t max_len;
+    uint32_t *hist;                 // optional: histogram of the counters' values 1..hist_top,
+    uint32_t hist_top;              // kept as they are counted (the calibration's)
 };
 
 hipError_t launch_sampler(const SampleLaunch &a, int slots, int block, hipStream_t st);
@@ -155,6 +157,7 @@ struct AllocArgs {
     double *lo_hi;       // device: {lo, hi, done}
     double *partials;    // device scratch, one per block
     double *LL, *LU;     // out
+    uint32_t *hist;      // optional: histogram of the counts already built (bins 1..tau0)
 };
 hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host);
 // Sum over v of delta_L(v) + delta_U(v) = e^-LL + e^-LU on the device

@@ -1068,6 +1068,18 @@ __device__ int32_t pick_pred_layer(Smem<BS> &sm, const Ctx &c, int side, int32_t
     return pick >= 0 ? c.g.newid[pick] : pick;
 }
 
+// One count for an interior vertex.  With a histogram (the calibration),
+// its bins follow the counter: the value moves from bin c to bin c + 1
+// (a vertex is counted at most once per sample, so c < samples <= top).
+__device__ __forceinline__ void count_vertex(const SampleLaunch &a, uint32_t *sf, int32_t v)
+{
+    const uint32_t old = atomicAdd(sf + v, 1u);
+    if (a.hist) {
+        if (old >= 1) atomicSub(a.hist + min(old, a.hist_top), 1u);
+        atomicAdd(a.hist + min(old + 1, a.hist_top), 1u);
+    }
+}
+
 // The second bound is the minimum of waves per SIMD.  The 256-thread
 // shape is held to three (three workgroups per CU): the high-diameter
 // graphs depend on that many samples in flight; the 512-thread shape to
@@ -1284,7 +1296,7 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                     prow[dep[0]] = a.g.orig[w];
                 }
                 if (w != s && w != t) {
-                    if (lane == 0) atomicAdd(sf + w, 1u);
+                    if (lane == 0) count_vertex(a, sf, w);
                     cnt += 1;
                 }
             }
@@ -1310,7 +1322,7 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                         break;
                     }
                     if (lane == 0) {
-                        atomicAdd(sf + p, 1u);
+                        count_vertex(a, sf, p);
                         if (prow) prow[side == 0 ? (l - 1) : (d - (l - 1))] = a.g.orig[p];
                     }
                     cnt += 1;
