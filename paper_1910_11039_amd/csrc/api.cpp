@@ -1024,12 +1024,11 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
         return KAD_OK;
     };
     // Adaptive samples do not depend on the delta allocation, only their
-    // merges do: when a plain allocation is still to come, the samplers of
-    // epochs 1 .. P-1 start on their pools right after the calibration's
-    // (pool 0, stream 0) and fill its tail; epoch 0 and the merges follow
-    // the allocation.
-    // The learned allocation is a chain of short launches that would wait
-    // for CUs behind those samplers, so it runs first on an idle GPU.
+    // merges do: when a plain allocation is still to come, the first
+    // epochs' samplers start on their pools right after the calibration's
+    // sampler and fill its tail; the merges follow the allocation.  The
+    // learned allocation is a chain of short launches that would wait for
+    // CUs behind those samplers, so it runs first on an idle GPU.
     const unsigned long long total = (s->cap + s->E - 1) / s->E;
     const bool graph_path = s->o.use_graphs && !timing;
     unsigned long long pre_hi = 0;

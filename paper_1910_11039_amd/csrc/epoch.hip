@@ -250,14 +250,6 @@ __global__ __launch_bounds__(AB) void k_alloc_update(double *lo_hi, const double
 
 // Calibration priors are counts over tau0, so the sum over vertices is a
 // sum over count values c of (vertices with count c) * exp(-mid tau0 / c).
-__global__ void k_alloc_hist(AllocArgs a, uint32_t *hist, uint32_t top)
-{
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
-        const uint32_t c = a.counts[v];
-        if (c > 0) atomicAdd(hist + min(c, top), 1u);
-    }
-}
-
 // The whole bisection in one workgroup over the count histogram: per step,
 // thread t sums bins t, t + HB, ... in turn, then a pairwise tree (a fixed
 // order).  Same interval, step rule and stopping rule as the dense form.
@@ -810,19 +802,11 @@ hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host)
     hipError_t e;
     const double target = 0.25 * a.delta * (1.0 - 1e-9);
     if (a.counts) {
-        // calibration counts: histogram (unless the sampler kept it), then
-        // the bisection in one launch
+        // calibration counts: the bisection in one launch over the histogram
+        // of the counts that the calibration's sampler kept
+        if (!a.hist) return hipErrorInvalidValue;
         const uint32_t top = (uint32_t)std::max(1.0, a.tau0);
-        uint32_t *hist = a.hist;
-        if (!hist) {
-            if ((e = hipMallocAsync((void **)&hist, sizeof(uint32_t) * ((size_t)top + 1), st)) != hipSuccess)
-                return e;
-            CK(hipMemsetAsync(hist, 0, sizeof(uint32_t) * ((size_t)top + 1), st));
-            // small grids: these run beside the adaptive samplers (see the merge)
-            hipLaunchKernelGGL(k_alloc_hist, dim3(grid_for(a.n, 256, 256)), dim3(256), 0, st, a, hist, top);
-        }
-        hipLaunchKernelGGL(k_alloc_bisect_hist, dim3(1), dim3(HB), 0, st, a, hist, top, target);
-        if (!a.hist) CK(hipFreeAsync(hist, st));
+        hipLaunchKernelGGL(k_alloc_bisect_hist, dim3(1), dim3(HB), 0, st, a, a.hist, top, target);
         double fin[3];
         CK(hipMemcpyAsync(fin, a.lo_hi, sizeof(fin), hipMemcpyDeviceToHost, st));
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
