@@ -4,11 +4,17 @@ One step = one whole run of the sampling path on a graph already resident
 in HBM: the vertex-diameter bracket and omega, the delta allocation
 (calibration samples for the plain arm; features + MLP inference for the
 learned arm), then epochs of sampling with the merge + FP64 stop check
-until the rule holds.  Default workload: R-MAT scale 20, edge factor 16
-(Graph500 parameters), largest component, eps = 0.005, delta = 0.1.
+until the rule holds.
 
-Prints one JSON line.  value = samples per second over the timed steps
-(calibration plus adaptive samples, divided by the steps' wall time).
+Default workload: R-MAT scale 26, edge factor 16 (Graph500 parameters),
+largest component, eps = 0.01, delta = 0.1, the plain allocation and the
+learned one on the same graph and seeds, both timed on the same host clock
+around each step.  Secondary lines: R-MAT 22 (the learned prior's held-out
+graph, eps 0.01, both arms) and R-MAT 20 at eps 0.005 (plain).
+
+Prints one JSON line.  value = samples per second of the plain arm over
+its timed steps (calibration plus adaptive samples, divided by the steps'
+wall time).
 """
 from __future__ import annotations
 
@@ -31,15 +37,19 @@ FIXED_EPOCH = {"er2048": 1024}
 
 WORKLOADS = {
     # name: (graphgen workload, eps, description)
-    "rmat20": ("rmat20", 0.005, "R-MAT scale 20, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), "
-                                "symmetrised, deduplicated, largest component"),
+    "rmat26": ("rmat26", 0.01, "R-MAT scale 26, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), "
+                               "symmetrised, deduplicated, largest component"),
+    "rmat22": ("rmat22", 0.01, "R-MAT scale 22, edge factor 16, Graph500 parameters, largest component "
+                               "(held out from the learned prior's training graphs)"),
+    "rmat20": ("rmat20", 0.005, "R-MAT scale 20, edge factor 16, Graph500 parameters, largest component"),
     "er2048": ("er2048", 0.01, "Erdos-Renyi G(2048, 16384), largest component"),
     "grid2048": ("grid2048", 0.01, "2048x2048 grid, 5% edges removed, 0.1% shortcuts of offset <= 8, "
                                    "largest component"),
-    "rmat22": ("rmat22", 0.01, "R-MAT scale 22, edge factor 16, Graph500 parameters, largest component "
-                               "(held out from the learned prior's training graphs)"),
-    "rmat26": ("rmat26", 0.01, "R-MAT scale 26, edge factor 16, Graph500 parameters, largest component"),
 }
+
+
+def log(msg: str):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 def algorithmic_bytes(r) -> int:
@@ -53,6 +63,10 @@ def algorithmic_bytes(r) -> int:
     return int(16 * r["vertices_expanded"] + 8 * r["edges_scanned"] + 8 * r["pred_edges"]
                + 20 * r["vertices_visited"] + 8 * (r["path_vertices"] + 2 * samples)
                + 4 * r["path_vertices"])
+
+
+WORK_KEYS = ("edges_scanned", "vertices_expanded", "vertices_visited", "pred_edges", "path_vertices",
+             "t_sample_kernel_ms", "sample_launches", "tau", "tau0", "samples_run", "t_ads_ms")
 
 
 def csrc_sha256() -> str:
@@ -69,7 +83,7 @@ def csrc_sha256() -> str:
 
 def counter_traffic(workload: str, epoch_size: int, block: int):
     """HBM bytes per sampler dispatch from the committed rocprofv3 counter
-    profile (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or None when
+    profile (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
     the native sources have changed since the counters were taken, or the
     launch configuration differs."""
     path = os.path.join(ROOT, "profiles", f"k_sample_{workload}_traffic.json")
@@ -82,20 +96,165 @@ def counter_traffic(workload: str, epoch_size: int, block: int):
     return float(prof["traffic_bytes_per_dispatch"])
 
 
-def cpu_baseline(g, seed: int, target_s: float = 12.0):
-    """The oracle, as it stands, on the host: first samples of the adaptive
-    stream, single thread, grown until about target_s seconds."""
+def run_arm(K, G, eps, steps, warmup, seed_base=1, **opts):
+    """Warm-up runs, then `steps` timed runs; each step = reset (bracket and
+    omega) + run to stop, timed on the host clock around the two calls."""
+    S = K.Sampler(G, seed=seed_base, epsilon=eps, delta=0.1, **opts)
+    return S, arm_steps(S, steps, warmup, seed_base)
+
+
+def arm_steps(S, steps, warmup, seed_base=1):
+    for i in range(warmup):
+        S.reset(1000 + i)
+        S.run_to_stop()
+    res, walls = [], []
+    for i in range(steps):
+        t0 = time.perf_counter()
+        S.reset(seed_base + i)
+        r = S.run_to_stop().as_dict()
+        walls.append(time.perf_counter() - t0)
+        res.append(r)
+    return res, walls
+
+
+def summarize(res, walls):
+    samples = sum(r["tau0"] + r["tau"] for r in res)
+    return {"time_to_stop_ms": round(1e3 * float(np.mean(walls)), 3),
+            "time_to_stop_ms_min_max": [round(1e3 * min(walls), 3), round(1e3 * max(walls), 3)],
+            "samples_per_s": round(samples / sum(walls), 1),
+            "samples_per_run": float(np.mean([r["tau0"] + r["tau"] for r in res])),
+            "adaptive_samples_per_run": float(np.mean([r["tau"] for r in res])),
+            "calibration_samples_per_run": float(np.mean([r["tau0"] for r in res])),
+            "epochs_per_run": float(np.mean([r["epochs"] for r in res])),
+            "phase_ms": {k: round(float(np.mean([r[k] for r in res])), 3)
+                         for k in ("t_omega_ms", "t_alloc_ms", "t_ads_ms")},
+            "launch": {k: int(res[-1][k]) for k in ("epoch_size", "slots", "block_size", "pools")}}
+
+
+def learned_vs_plain(K, G, eps, steps, warmup, args):
+    """Both arms on the same graph, seeds and clock."""
+    from paper_1910_11039_amd import learned as LRN
+    shape = dict(epoch_size=args.epoch_size, slots=args.slots, block_size=args.block,
+                 use_graphs=args.use_graphs, timing=1)
+    S, (pres, pwalls) = run_arm(K, G, eps, steps, warmup, **shape)
+    S.close()   # frees the plain arm's visited state before the learned arm sizes its own
+    params, norm = LRN.load()
+    SL = K.Sampler(G, seed=1, epsilon=eps, delta=0.1, alloc_mode=K.KAD_ALLOC_LEARNED, **shape)
+    SL.set_mlp_weights(params, norm)
+    lres, lwalls = arm_steps(SL, steps, warmup)
+    SL.close()
+    plain, learned = summarize(pres, pwalls), summarize(lres, lwalls)
+    learned["fell_back_to_plain"] = int(sum(r["tau0"] > 0 for r in lres))
+    out = {"plain": plain, "learned": learned,
+           "time_ratio_learned_over_plain": round(learned["time_to_stop_ms"] / plain["time_to_stop_ms"], 4),
+           "sample_ratio_learned_over_plain": round(learned["samples_per_run"] / plain["samples_per_run"], 4),
+           "certified_max_f_g_at_stop": {
+               "plain": float(max(max(r["max_f"], r["max_g"]) for r in pres)),
+               "learned": float(max(max(r["max_f"], r["max_g"]) for r in lres))}}
+    return out, pres, pwalls
+
+
+def roofline_leg(K, G, eps, workload, steps=3):
+    """The sampler's roofline with one slot pool, so that a launch's
+    duration is the kernel's own time (with several pools, launches of
+    neighbouring epochs share the GPU).  achieved = algorithmic bytes per
+    launch / average launch duration (HIP events on the launch stream)."""
+    S = K.Sampler(G, seed=1, epsilon=eps, delta=0.1, timing=1, pools=1)
+    res, _ = arm_steps(S, steps, 1)
+    S.close()
+    agg = {k: sum(r[k] for r in res) for k in WORK_KEYS}
+    agg["samples"] = agg["samples_run"]
+    launches = agg["sample_launches"]
+    per_launch_bytes = algorithmic_bytes(agg) / launches
+    per_launch_s = agg["t_sample_kernel_ms"] / 1e3 / launches
+    achieved = per_launch_bytes / per_launch_s / 1e9
+    traffic = counter_traffic(workload, res[0]["epoch_size"], res[0]["block_size"])
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": None if traffic is None else round(traffic),
+            "kernel": "k_sample (one slot pool: launch time is the kernel's own)",
+            "launch_ms": round(per_launch_s * 1e3, 4), "launches": int(launches),
+            "bytes_per_launch": int(per_launch_bytes),
+            "launch_shape": {k: int(res[0][k]) for k in ("epoch_size", "slots", "block_size", "pools")}}
+
+
+def aggregate_rate(res, walls):
+    """Algorithmic bytes of all sampler work over the adaptive phases' wall
+    time (every pool overlapped, as the timed runs launch it)."""
+    agg = {k: sum(r[k] for r in res) for k in WORK_KEYS}
+    agg["samples"] = agg["samples_run"]
+    ads_s = agg["t_ads_ms"] / 1e3
+    gbs = algorithmic_bytes(agg) / ads_s / 1e9
+    return {"algorithmic_GBps": round(gbs, 2), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 5),
+            "edges_scanned_per_s": round(agg["edges_scanned"] / sum(walls), 1),
+            "edges_scanned_per_s_adaptive_phase": round(agg["edges_scanned"] / ads_s, 1)}
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10):
+    """A plain device-to-device copy of known size (hipMemcpy's copy kernel),
+    timed with HIP events: read + write bytes per second."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    src, dst = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(src), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMalloc(ctypes.byref(dst), ctypes.c_size_t(nbytes)) == 0
+    hip.hipMemset(src, 1, ctypes.c_size_t(nbytes))
+    e0, e1 = ctypes.c_void_p(), ctypes.c_void_p()
+    hip.hipEventCreate(ctypes.byref(e0))
+    hip.hipEventCreate(ctypes.byref(e1))
+    hip.hipMemcpy(dst, src, ctypes.c_size_t(nbytes), 3)
+    hip.hipEventRecord(e0, None)
+    for _ in range(reps):
+        hip.hipMemcpyAsync(dst, src, ctypes.c_size_t(nbytes), 3, None)
+    hip.hipEventRecord(e1, None)
+    hip.hipEventSynchronize(e1)
+    ms = ctypes.c_float()
+    hip.hipEventElapsedTime(ctypes.byref(ms), e0, e1)
+    hip.hipEventDestroy(e0)
+    hip.hipEventDestroy(e1)
+    hip.hipFree(src)
+    hip.hipFree(dst)
+    return round(2.0 * nbytes * reps / (ms.value * 1e-3) / 1e9, 1)
+
+
+def cpu_baseline(g, eps, omega, epoch, epochs_gpu, target_s: float = 20.0):
+    """The oracle as it stands, on the host: its threaded runner on every
+    core this process may use (plain calibration, then the first epochs of
+    the adaptive phase with the GPU run's epoch size, extrapolated to the
+    GPU run's epoch count), and one thread over the first samples."""
     from oracle import oracle as O
-    G = O.Graph(g)
-    n_s, t = 256, 0.0
+    og = O.Graph(g)
+    T = O.host_threads()
+    t0 = time.perf_counter()
+    cal = O.calibrate(og, seed=1, omega_=omega, threads=T)
+    t_cal = time.perf_counter() - t0
+    ep = 1
+    t_ep = 0.0
     while True:
         t0 = time.perf_counter()
-        O.count(G, seed, 0, 0, n_s)
-        t = time.perf_counter() - t0
-        if t >= target_s or n_s >= 1 << 22:
+        O.run(og, seed=1, eps=eps, omega_=omega, epoch=epoch, LL=cal["LL"], LU=cal["LU"],
+              stop_after_epochs=ep, threads=T)
+        t_ep = time.perf_counter() - t0
+        if t_ep >= 0.4 * target_s or ep >= epochs_gpu:
             break
-        n_s = int(n_s * min(8.0, max(1.5, 1.2 * target_s / max(t, 1e-3))))
-    return n_s, t
+        ep = min(epochs_gpu, max(ep + 1, int(ep * 0.4 * target_s / max(t_ep, 1e-3))))
+    rate_T = ep * epoch / t_ep
+    n1, t1 = 64, 0.0
+    while True:
+        t0 = time.perf_counter()
+        O.count(og, 1, 0, 0, n1)
+        t1 = time.perf_counter() - t0
+        if t1 >= 0.2 * target_s or n1 >= 1 << 22:
+            break
+        n1 = int(n1 * min(8.0, max(1.5, 0.24 * target_s / max(t1, 1e-3))))
+    tts = t_cal + t_ep * epochs_gpu / ep
+    return {"value": round(rate_T, 2), "unit": "samples/s", "cores": T, "kind": "oracle",
+            "sample": (f"threaded oracle on {T} host threads: plain calibration ({cal['tau0']} samples, "
+                       f"{t_cal:.1f} s), then the first {ep} epochs of {epoch} adaptive samples "
+                       f"({t_ep:.1f} s); extrapolated to the GPU run's {epochs_gpu} epochs"),
+            "time_to_stop_ms_extrapolated": round(1e3 * tts, 1),
+            "one_thread": {"value": round(n1 / t1, 2), "unit": "samples/s", "cores": 1,
+                           "sample": f"first {n1} samples of the adaptive stream, {t1:.1f} s"}}
 
 
 def main():
@@ -103,14 +262,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat26", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-secondary", action="store_true", help="skip the R-MAT 22 and R-MAT 20 lines")
     ap.add_argument("--use-graphs", type=int, default=0)
     ap.add_argument("--epoch-size", type=int, default=0)
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--pools", type=int, default=0)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-allocation arm")
+    ap.add_argument("--profile-leg", action="store_true",
+                    help="only the one-pool roofline leg (the command the committed profiles run)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain device copy of known size (counter calibration) and exit")
     args = ap.parse_args()
@@ -121,99 +284,71 @@ def main():
         sys.exit(2)
 
     if args.copy_probe:
-        copy_probe()
+        print(json.dumps({"copy_GBps": copy_bandwidth()}), flush=True)
         return
 
     import graphgen as gg
     from paper_1910_11039_amd import kadabra as K
 
     wname, eps, desc = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
     g = gg.workload(wname)
+    gn, gm = g.n, g.m
+    log(f"workload {wname}: n={gn} m={gm} built in {time.perf_counter() - t0:.1f} s")
     ctx = K.Context(0)
     G = K.Graph(ctx, g)
+    log("graph resident in HBM")
     if args.epoch_size == 0:
         args.epoch_size = FIXED_EPOCH.get(args.workload, 0)
-    S = K.Sampler(G, seed=1, epsilon=eps, delta=0.1, timing=0 if args.use_graphs else 1,
-                  use_graphs=args.use_graphs, epoch_size=args.epoch_size, slots=args.slots,
-                  block_size=args.block)
-    print(f"# workload {wname}: n={g.n} m={g.m}; warmup {args.warmup}, steps {args.steps}",
-          file=sys.stderr, flush=True)
 
-    def step(seed):
-        S.reset(seed)
-        return S.run_to_stop().as_dict()
+    if args.profile_leg:
+        roof = roofline_leg(K, G, eps, wname, steps=args.steps)
+        print(json.dumps({"roofline": roof}), flush=True)
+        return
 
-    for i in range(args.warmup):
-        step(1000 + i)
-    results = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        results.append(step(1 + i))
-        print(f"# step {i}: tau0={results[-1]['tau0']} tau={results[-1]['tau']} "
-              f"epochs={results[-1]['epochs']} total_ms={results[-1]['t_total_ms']:.1f}",
-              file=sys.stderr, flush=True)
-    wall = time.perf_counter() - t0
-
-    samples = sum(r["tau0"] + r["tau"] for r in results)
+    shape = dict(epoch_size=args.epoch_size, slots=args.slots, block_size=args.block,
+                 use_graphs=args.use_graphs, timing=1, pools=args.pools)
+    if args.no_learned:
+        S, (pres, pwalls) = run_arm(K, G, eps, args.steps, args.warmup, **shape)
+        S.close()
+        arms = None
+    else:
+        arms, pres, pwalls = learned_vs_plain(K, G, eps, args.steps, args.warmup, args)
+        log(f"plain {arms['plain']['time_to_stop_ms']:.1f} ms, learned {arms['learned']['time_to_stop_ms']:.1f} ms")
+    wall = sum(pwalls)
+    samples = sum(r["tau0"] + r["tau"] for r in pres)
     value = samples / wall
-    agg = {k: sum(r[k] for r in results) for k in
-           ("edges_scanned", "vertices_expanded", "vertices_visited", "pred_edges", "path_vertices",
-            "t_sample_kernel_ms", "sample_launches", "tau", "samples_run")}
-    agg["samples"] = agg["samples_run"]
-    roof = None
-    if agg["sample_launches"] > 0 and agg["t_sample_kernel_ms"] > 0:
-        per_launch_bytes = algorithmic_bytes(agg) / agg["sample_launches"]
-        per_launch_s = agg["t_sample_kernel_ms"] / 1e3 / agg["sample_launches"]
-        achieved = per_launch_bytes / per_launch_s / 1e9
-        traffic = counter_traffic(args.workload, results[0]["epoch_size"], results[0]["block_size"])
-        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": None if traffic is None else round(traffic),
-                "kernel": "k_sample (adaptive-phase launches)",
-                "launch_ms": round(per_launch_s * 1e3, 4),
-                "bytes_per_launch": int(per_launch_bytes)}
-
-    r0 = results[0]
-    S.close()          # frees the plain arm's visited state before the learned arm sizes its own
-    learned = None
-    if not args.no_learned:
-        # the same runs with the learned delta allocation (committed network)
-        from paper_1910_11039_amd import learned as LRN
-        params, norm = LRN.load()
-        SL = K.Sampler(G, seed=1, epsilon=eps, delta=0.1, alloc_mode=K.KAD_ALLOC_LEARNED,
-                       timing=0 if args.use_graphs else 1, use_graphs=args.use_graphs,
-                       epoch_size=args.epoch_size, slots=args.slots, block_size=args.block)
-        SL.set_mlp_weights(params, norm)
-        for i in range(args.warmup):
-            SL.reset(1000 + i)
-            SL.run_to_stop()
-        lres = []
-        tl0 = time.perf_counter()
-        for i in range(args.steps):
-            SL.reset(1 + i)
-            lres.append(SL.run_to_stop().as_dict())
-        lwall = time.perf_counter() - tl0
-        SL.close()
-        plain_ms = wall * 1e3 / args.steps
-        l_ms = lwall * 1e3 / args.steps
-        learned = {"time_to_stop_ms": round(l_ms, 3),
-                   "samples_per_run": float(np.mean([r["tau0"] + r["tau"] for r in lres])),
-                   "alloc_ms": round(float(np.mean([r["t_alloc_ms"] for r in lres])), 3),
-                   "fell_back_to_plain": int(sum(r["tau0"] > 0 for r in lres)),
-                   "plain_time_to_stop_ms": round(plain_ms, 3),
-                   "plain_samples_per_run": float(np.mean([r["tau0"] + r["tau"] for r in results])),
-                   "time_ratio_learned_over_plain": round(l_ms / plain_ms, 4),
-                   "phase_ms": {k: round(float(np.mean([r[k] for r in lres])), 3)
-                                for k in ("t_omega_ms", "t_alloc_ms", "t_ads_ms")},
-                   "launch": {k: int(lres[-1][k]) for k in ("epoch_size", "slots", "block_size", "pools")}}
-        print(f"# learned arm: {l_ms:.1f} ms per run vs plain {plain_ms:.1f} ms", file=sys.stderr, flush=True)
+    r0 = pres[0]
+    roof = roofline_leg(K, G, eps, wname)
+    roof["aggregate"] = aggregate_rate(pres, pwalls)
+    roof["copy_kernel_GBps_measured"] = copy_bandwidth()
+    log(f"roofline leg: {roof['achieved']} GB/s per launch; copy {roof['copy_kernel_GBps_measured']} GB/s")
+    G.close()
 
     cpu = None
     if not args.no_cpu_baseline:
-        n_s, t = cpu_baseline(g, 1, args.cpu_seconds)
-        cpu = {"value": round(n_s / t, 2), "unit": "samples/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {n_s} samples of the adaptive stream (seed 1) on the same graph, "
-                         f"oracle sample loop, one host thread, {t:.1f} s"}
+        cpu = cpu_baseline(g, eps, r0["omega"], r0["epoch_size"], int(round(np.mean([r["epochs"] for r in pres]))),
+                           args.cpu_seconds)
+        log(f"cpu baseline: {cpu['value']} samples/s on {cpu['cores']} threads")
+    del g
+
+    secondary = {}
+    if not args.no_secondary and args.workload == "rmat26":
+        for sname in ("rmat22", "rmat20"):
+            swl, seps, sdesc = WORKLOADS[sname]
+            sg = gg.workload(swl)
+            SG = K.Graph(ctx, sg)
+            if sname == "rmat22":
+                out, _, _ = learned_vs_plain(K, SG, seps, args.steps, args.warmup,
+                                             argparse.Namespace(epoch_size=0, slots=0, block=0, use_graphs=0))
+            else:
+                S2, (res2, walls2) = run_arm(K, SG, seps, args.steps, args.warmup, timing=1)
+                S2.close()
+                out = {"plain": summarize(res2, walls2)}
+            out["workload"] = f"{sname}: {sdesc}, n={sg.n}, m={sg.m}, eps={seps}, delta=0.1"
+            secondary[sname] = out
+            SG.close()
+            log(f"secondary {sname} done")
 
     out = {
         "metric": METRIC,
@@ -228,40 +363,24 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"{wname}: {desc}, n={g.n}, m={g.m}", "epsilon": eps, "delta": 0.1,
-                   "delta_alloc": "plain (calibration samples)", "epoch_size": r0["epoch_size"],
-                   "slots": r0["slots"], "block_size": r0["block_size"], "pools": r0["pools"],
-                   "omega": r0["omega"], "vd_bracket": [r0["vd_lo"], r0["vd_hi"]]},
-        "time_to_stop_ms": round(float(np.mean([r["t_total_ms"] for r in results])), 3),
-        "adaptive_samples_per_run": float(np.mean([r["tau"] for r in results])),
-        "calibration_samples_per_run": float(np.mean([r["tau0"] for r in results])),
-        "edges_scanned_per_s": round(agg["edges_scanned"] / wall, 1),
-        "phase_ms": {k: round(float(np.mean([r[k] for r in results])), 3)
+        "config": {"workload": f"{wname}: {desc}, n={gn}, m={gm}, eps={eps}, delta=0.1",
+                   "epsilon": eps, "delta": 0.1,
+                   "value_arm": "plain (calibration samples)",
+                   "epoch_size": r0["epoch_size"], "slots": r0["slots"], "block_size": r0["block_size"],
+                   "pools": r0["pools"], "omega": r0["omega"], "vd_bracket": [r0["vd_lo"], r0["vd_hi"]]},
+        "time_to_stop_ms": round(1e3 * float(np.mean(pwalls)), 3),
+        "adaptive_samples_per_run": float(np.mean([r["tau"] for r in pres])),
+        "calibration_samples_per_run": float(np.mean([r["tau0"] for r in pres])),
+        "edges_scanned_per_s": roof["aggregate"]["edges_scanned_per_s"],
+        "phase_ms": {k: round(float(np.mean([r[k] for r in pres])), 3)
                      for k in ("t_omega_ms", "t_alloc_ms", "t_ads_ms")},
-        "learned_alloc": learned,
+        "learned_vs_plain": arms,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "secondary": secondary or None,
     }
     print(json.dumps(out), flush=True)
-    G.close()
     ctx.close()
-
-
-def copy_probe(nbytes: int = 1 << 30, reps: int = 5):
-    """A plain device-to-device copy of known size (hipMemcpy's blit kernel)
-    to scale the HBM byte counters of the profiler."""
-    import ctypes
-    hip = ctypes.CDLL("libamdhip64.so")
-    src, dst = ctypes.c_void_p(), ctypes.c_void_p()
-    assert hip.hipMalloc(ctypes.byref(src), ctypes.c_size_t(nbytes)) == 0
-    assert hip.hipMalloc(ctypes.byref(dst), ctypes.c_size_t(nbytes)) == 0
-    hip.hipMemset(src, 1, ctypes.c_size_t(nbytes))
-    for _ in range(reps):
-        assert hip.hipMemcpy(dst, src, ctypes.c_size_t(nbytes), 3) == 0   # device to device
-    hip.hipDeviceSynchronize()
-    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
-    hip.hipFree(src)
-    hip.hipFree(dst)
 
 
 if __name__ == "__main__":

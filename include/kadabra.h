@@ -163,7 +163,8 @@ kad_status kad_sampler_reset(kad_sampler *s, uint64_t seed);
  * the sum over vertices of delta_L + delta_U must stay below delta / 2
  * (the other half of delta is spent on omega); checked, EINVAL otherwise.
  * Any such split is a valid allocation (Sec. III-A, footnote on delta_L,
- * delta_U). */
+ * delta_U).  The stop rule's L = ln(1/delta) is computed here, once per
+ * vertex, on the host in FP64 with the C library's log. */
 kad_status kad_set_delta(kad_sampler *s, const double *h_delta_L, const double *h_delta_U);
 
 /* kad_set_mlp_weights: LEARNED allocation; h_params float32[4481] in the

@@ -39,6 +39,7 @@
  * scaled to the total.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -655,13 +656,17 @@ void orc_alloc_delta(int32_t n, const double *prior, double C, double delta, dou
     }
 }
 
-int orc_calibrate(const orc_graph *g, uint64_t seed, double omega, double delta, int sigma_mode,
-                  uint32_t *cprime, double *C_out, double *LL, double *LU)
+int orc_count_mt(const orc_graph *g, uint64_t seed, uint64_t stream, uint64_t first, uint64_t count,
+                 int sigma_mode, uint32_t *c, int64_t *edges_out, int nthreads);
+
+int orc_calibrate_mt(const orc_graph *g, uint64_t seed, double omega, double delta, int sigma_mode,
+                     uint32_t *cprime, double *C_out, double *LL, double *LU, int nthreads)
 {
     const int32_t n = g->n;
     uint64_t tau0 = (uint64_t)ceil(omega / 100.0);
     memset(cprime, 0, sizeof(uint32_t) * (size_t)n);
-    int rc = orc_count(g, seed, ORC_STREAM_CALIB, 0, tau0, sigma_mode, cprime, NULL);
+    int rc = nthreads > 1 ? orc_count_mt(g, seed, ORC_STREAM_CALIB, 0, tau0, sigma_mode, cprime, NULL, nthreads)
+                          : orc_count(g, seed, ORC_STREAM_CALIB, 0, tau0, sigma_mode, cprime, NULL);
     if (rc != ORC_OK) return rc;
     double *prior = (double *)malloc(sizeof(double) * (size_t)n);
     for (int32_t v = 0; v < n; ++v) prior[v] = (double)cprime[v] / (double)tau0;
@@ -670,6 +675,12 @@ int orc_calibrate(const orc_graph *g, uint64_t seed, double omega, double delta,
     free(prior);
     *C_out = C;
     return ORC_OK;
+}
+
+int orc_calibrate(const orc_graph *g, uint64_t seed, double omega, double delta, int sigma_mode,
+                  uint32_t *cprime, double *C_out, double *LL, double *LU)
+{
+    return orc_calibrate_mt(g, seed, omega, delta, sigma_mode, cprime, C_out, LL, LU, 1);
 }
 
 /* ------------------------------------------------------------------ */
@@ -886,4 +897,236 @@ void orc_adam_step(double *p, const double *grad, double *m, double *v, int64_t 
         double mh = m[i] / c1, vh = v[i] / c2;
         p[i] -= lr * mh / (sqrt(vh) + eps);
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* -ln(delta) per vertex: the stop rule takes L = ln(1/delta_L) and      */
+/* ln(1/delta_U) (Sec. III-A); the oracle computes them itself from the  */
+/* delta arrays a run is given.                                          */
+/* ------------------------------------------------------------------ */
+
+void orc_neglog(int32_t n, const double *delta, double *L)
+{
+    for (int32_t v = 0; v < n; ++v) L[v] = -log(delta[v]);
+}
+
+/* ------------------------------------------------------------------ */
+/* Threaded runner.  The shared-memory layout of the sampling phase      */
+/* (Sec. IV-A): every thread samples into a state frame of its own, and  */
+/* the frames are summed into the counters at each epoch boundary (the   */
+/* aggregation of Alg. 1 / Alg. 2, here without MPI).  The samples of an */
+/* epoch are split into contiguous index slices, one per thread.  The    */
+/* counters are integer sums, so the result is the single-threaded       */
+/* run's, bit for bit; the check's maxima, minimum and AND do not depend */
+/* on the order either.                                                  */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    const orc_graph *g;
+    uint64_t seed, stream;
+    int sigma_mode;
+    uint64_t lo, hi;          /* sample indices [lo, hi) of this thread     */
+    uint32_t *frame;          /* thread-local state frame, n counters       */
+    orc_ws *ws;
+    int32_t *path;
+    int64_t edges;
+    int rc;
+    /* frame sum and check over vertices [v0, v1) */
+    int32_t v0, v1;
+    uint32_t *const *frames;
+    int nframes;
+    uint32_t *c;
+    uint64_t tau;
+    double omega, eps;
+    const double *LL, *LU;
+    int all;
+    orc_check_info ci;
+} mt_job;
+
+static void *mt_sample(void *arg)
+{
+    mt_job *j = (mt_job *)arg;
+    j->rc = ORC_OK;
+    for (uint64_t i = j->lo; i < j->hi; ++i) {
+        orc_sample_info info;
+        int rc = orc_sample_path(j->g, j->ws, j->seed, j->stream, i, j->sigma_mode, j->path, &info);
+        if (rc != ORC_OK) { j->rc = rc; return NULL; }
+        for (int32_t q = 1; q < info.d; ++q) j->frame[j->path[q]] += 1;
+        j->edges += info.edges;
+    }
+    return NULL;
+}
+
+/* c[v] += sum of the frames at v, frames cleared; then the stop rule on
+ * the slice's vertices when LL is set. */
+static void *mt_merge_check(void *arg)
+{
+    mt_job *j = (mt_job *)arg;
+    for (int f = 0; f < j->nframes; ++f) {
+        uint32_t *fr = j->frames[f];
+        for (int32_t v = j->v0; v < j->v1; ++v) {
+            j->c[v] += fr[v];
+            fr[v] = 0;
+        }
+    }
+    if (j->LL) {
+        j->all = orc_check(j->v1 - j->v0, j->c + j->v0, j->tau, j->omega, j->eps, j->LL + j->v0,
+                           j->LU + j->v0, &j->ci);
+    }
+    return NULL;
+}
+
+static int mt_for(int nthreads, mt_job *jobs, void *(*fn)(void *))
+{
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    int started = 0;
+    for (int i = 1; i < nthreads; ++i) {
+        if (pthread_create(&th[i], NULL, fn, &jobs[i]) != 0) break;
+        started = i;
+    }
+    /* thread 0's share runs here; shares whose thread did not start too */
+    fn(&jobs[0]);
+    for (int i = started + 1; i < nthreads; ++i) fn(&jobs[i]);
+    for (int i = 1; i <= started; ++i) pthread_join(th[i], NULL);
+    free(th);
+    return ORC_OK;
+}
+
+typedef struct {
+    int nthreads;
+    mt_job *jobs;
+    uint32_t **frames;
+} mt_pool;
+
+static void mt_pool_init(mt_pool *p, const orc_graph *g, uint64_t seed, uint64_t stream, int sigma_mode,
+                         int nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    p->nthreads = nthreads;
+    p->jobs = (mt_job *)calloc((size_t)nthreads, sizeof(mt_job));
+    p->frames = (uint32_t **)malloc(sizeof(uint32_t *) * (size_t)nthreads);
+    for (int i = 0; i < nthreads; ++i) {
+        mt_job *j = &p->jobs[i];
+        j->g = g;
+        j->seed = seed;
+        j->stream = stream;
+        j->sigma_mode = sigma_mode;
+        j->frame = (uint32_t *)calloc((size_t)g->n, sizeof(uint32_t));
+        j->ws = orc_ws_create(g->n);
+        j->path = (int32_t *)malloc(sizeof(int32_t) * ((size_t)g->n + 1));
+        p->frames[i] = j->frame;
+    }
+}
+
+static void mt_pool_free(mt_pool *p)
+{
+    for (int i = 0; i < p->nthreads; ++i) {
+        free(p->jobs[i].frame);
+        orc_ws_free(p->jobs[i].ws);
+        free(p->jobs[i].path);
+    }
+    free(p->jobs);
+    free(p->frames);
+}
+
+/* Samples [lo, hi) on the pool's threads, frames summed into c; when LL is
+ * set, the stop rule at tau is evaluated (returns 1 when it holds). */
+static int mt_epoch(mt_pool *p, uint64_t lo, uint64_t hi, uint32_t *c, int64_t *edges, uint64_t tau,
+                    double omega, double eps, const double *LL, const double *LU, orc_check_info *ci,
+                    int *rc_out)
+{
+    const int T = p->nthreads;
+    const int32_t n = p->jobs[0].g->n;
+    const uint64_t cnt = hi - lo;
+    for (int i = 0; i < T; ++i) {
+        mt_job *j = &p->jobs[i];
+        j->lo = lo + cnt * (uint64_t)i / (uint64_t)T;
+        j->hi = lo + cnt * (uint64_t)(i + 1) / (uint64_t)T;
+        j->edges = 0;
+    }
+    mt_for(T, p->jobs, mt_sample);
+    *rc_out = ORC_OK;
+    for (int i = 0; i < T; ++i) {
+        if (p->jobs[i].rc != ORC_OK) *rc_out = p->jobs[i].rc;
+        *edges += p->jobs[i].edges;
+    }
+    for (int i = 0; i < T; ++i) {
+        mt_job *j = &p->jobs[i];
+        j->v0 = (int32_t)((int64_t)n * i / T);
+        j->v1 = (int32_t)((int64_t)n * (i + 1) / T);
+        j->frames = p->frames;
+        j->nframes = T;
+        j->c = c;
+        j->tau = tau;
+        j->omega = omega;
+        j->eps = eps;
+        j->LL = LL;
+        j->LU = LU;
+    }
+    mt_for(T, p->jobs, mt_merge_check);
+    if (!LL) return 0;
+    int all = 1;
+    double mf = 0.0, mg = 0.0, mm = INFINITY;
+    for (int i = 0; i < T; ++i) {
+        const mt_job *j = &p->jobs[i];
+        if (j->v1 <= j->v0) continue;
+        if (!j->all) all = 0;
+        if (j->ci.max_f > mf) mf = j->ci.max_f;
+        if (j->ci.max_g > mg) mg = j->ci.max_g;
+        if (j->ci.min_abs_margin < mm) mm = j->ci.min_abs_margin;
+    }
+    if (ci) { ci->max_f = mf; ci->max_g = mg; ci->min_abs_margin = mm; }
+    return all;
+}
+
+int orc_count_mt(const orc_graph *g, uint64_t seed, uint64_t stream, uint64_t first, uint64_t count,
+                 int sigma_mode, uint32_t *c, int64_t *edges_out, int nthreads)
+{
+    mt_pool p;
+    mt_pool_init(&p, g, seed, stream, sigma_mode, nthreads);
+    int64_t edges = 0;
+    int rc = ORC_OK;
+    mt_epoch(&p, first, first + count, c, &edges, 0, 0.0, 0.0, NULL, NULL, NULL, &rc);
+    mt_pool_free(&p);
+    if (edges_out) *edges_out = edges;
+    return rc;
+}
+
+/* orc_run with every epoch's samples split over nthreads threads. */
+int orc_run_mt(const orc_graph *g, const orc_run_opts *o, const double *LL, const double *LU,
+               uint32_t *c, orc_run_result *res, orc_check_info *per_epoch, int32_t max_epochs,
+               int nthreads)
+{
+    const int32_t n = g->n;
+    uint64_t cap = (uint64_t)ceil(o->omega);
+    mt_pool p;
+    mt_pool_init(&p, g, o->seed, o->stream, o->sigma_mode, nthreads);
+    int32_t k = o->start_epoch;
+    if (k == 0) memset(c, 0, sizeof(uint32_t) * (size_t)n);
+    int64_t edges = 0;
+    uint64_t tau = 0;
+    int reason = 0;
+    for (;; ++k) {
+        uint64_t lo = (uint64_t)k * o->epoch;
+        uint64_t hi = lo + o->epoch;
+        if (hi > cap) hi = cap;
+        orc_check_info ci;
+        int rc = ORC_OK;
+        int ok = mt_epoch(&p, lo, hi, c, &edges, hi, o->omega, o->eps, LL, LU, &ci, &rc);
+        if (rc != ORC_OK) { mt_pool_free(&p); return rc; }
+        tau = hi;
+        if (per_epoch && k < max_epochs) per_epoch[k] = ci;
+        if (ok) { reason = ORC_STOP_COND; break; }
+        if (tau >= cap) { reason = ORC_STOP_OMEGA; break; }
+        if (o->stop_after_epochs > 0 && k + 1 >= o->start_epoch + o->stop_after_epochs) {
+            reason = ORC_STOP_PAUSED;
+            break;
+        }
+    }
+    res->tau = tau;
+    res->epochs = k + 1;
+    res->reason = reason;
+    res->edges = edges;
+    mt_pool_free(&p);
+    return ORC_OK;
 }

@@ -87,11 +87,23 @@ int orc_run(const orc_graph *g, const orc_run_opts *o, const double *LL, const d
 int orc_count(const orc_graph *g, uint64_t seed, uint64_t stream, uint64_t first, uint64_t count,
               int sigma_mode, uint32_t *c, int64_t *edges_out);
 
+/* Threaded runner: every epoch's samples split over nthreads threads, each
+ * with a state frame of its own, summed at the epoch boundary; results
+ * equal orc_run / orc_count exactly. */
+int orc_run_mt(const orc_graph *g, const orc_run_opts *o, const double *LL, const double *LU,
+               uint32_t *c, orc_run_result *res, orc_check_info *per_epoch, int32_t max_epochs,
+               int nthreads);
+int orc_count_mt(const orc_graph *g, uint64_t seed, uint64_t stream, uint64_t first, uint64_t count,
+                 int sigma_mode, uint32_t *c, int64_t *edges_out, int nthreads);
+void orc_neglog(int32_t n, const double *delta, double *L);
+
 double orc_alloc_constant(int32_t n, const double *prior, double delta);
 void orc_alloc_delta(int32_t n, const double *prior, double C, double delta, double beta,
                      double *LL, double *LU);
 int orc_calibrate(const orc_graph *g, uint64_t seed, double omega, double delta, int sigma_mode,
                   uint32_t *cprime, double *C_out, double *LL, double *LU);
+int orc_calibrate_mt(const orc_graph *g, uint64_t seed, double omega, double delta, int sigma_mode,
+                     uint32_t *cprime, double *C_out, double *LL, double *LU, int nthreads);
 
 void orc_brandes(const orc_graph *g, double *bc);
 

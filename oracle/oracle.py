@@ -27,7 +27,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + f".tmp{os.getpid()}"
         subprocess.check_call([
-            "gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math",
+            "gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-pthread",
             "-shared", "-fPIC", "-o", tmp, os.path.join(HERE, "oracle.c"), "-lm",
         ])
         os.replace(tmp, LIB_PATH)
@@ -98,6 +98,13 @@ def lib():
         L.orc_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32]
         L.orc_count.restype = C.c_int
         L.orc_count.argtypes = [vp, u64, u64, u64, u64, C.c_int, vp, vp]
+        L.orc_run_mt.restype = C.c_int
+        L.orc_run_mt.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, C.c_int]
+        L.orc_count_mt.restype = C.c_int
+        L.orc_count_mt.argtypes = [vp, u64, u64, u64, u64, C.c_int, vp, vp, C.c_int]
+        L.orc_calibrate_mt.restype = C.c_int
+        L.orc_calibrate_mt.argtypes = [vp, u64, dbl, dbl, C.c_int, vp, vp, vp, vp, C.c_int]
+        L.orc_neglog.argtypes = [i32, vp, vp]
         L.orc_alloc_constant.restype = dbl
         L.orc_alloc_constant.argtypes = [i32, vp, dbl]
         L.orc_alloc_delta.argtypes = [i32, vp, dbl, dbl, dbl, vp, vp]
@@ -192,11 +199,25 @@ class Sampler:
         return self.buf[: info.d + 1].copy(), info
 
 
-def count(g, seed: int, stream: int, first: int, cnt: int, sigma_mode: int = SIGMA_AUTO):
+def host_threads() -> int:
+    """Threads the host lets this process run at once: its CPU affinity,
+    capped by OMP_NUM_THREADS when that is set."""
+    n = len(os.sched_getaffinity(0))
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    if cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def count(g, seed: int, stream: int, first: int, cnt: int, sigma_mode: int = SIGMA_AUTO,
+          threads: int = 1):
     g = as_graph(g)
     c = np.zeros(g.n, dtype=np.uint32)
     edges = C.c_int64()
-    rc = lib().orc_count(g.ref, seed, stream, first, cnt, sigma_mode, _p(c), C.byref(edges))
+    if threads > 1:
+        rc = lib().orc_count_mt(g.ref, seed, stream, first, cnt, sigma_mode, _p(c), C.byref(edges), threads)
+    else:
+        rc = lib().orc_count(g.ref, seed, stream, first, cnt, sigma_mode, _p(c), C.byref(edges))
     if rc != 0:
         raise RuntimeError(f"oracle count failed: {rc}")
     return c, edges.value
@@ -248,8 +269,11 @@ def check(c: np.ndarray, tau: int, omega_: float, eps: float, LL, LU):
 
 
 def run(g, *, seed=1, eps=0.01, omega_: float, epoch=1024, LL, LU, sigma_mode=SIGMA_AUTO,
-        stream=STREAM_ADS, start_epoch=0, stop_after_epochs=0, c_init=None, max_epochs=4096):
-    """Epoch loop to the stop rule.  Returns dict with counters and per-epoch info."""
+        stream=STREAM_ADS, start_epoch=0, stop_after_epochs=0, c_init=None, max_epochs=4096,
+        threads=1):
+    """Epoch loop to the stop rule.  Returns dict with counters and per-epoch
+    info.  threads > 1: every epoch's samples split over that many threads
+    (same result)."""
     g = as_graph(g)
     LL = np.ascontiguousarray(LL, dtype=np.float64)
     LU = np.ascontiguousarray(LU, dtype=np.float64)
@@ -257,7 +281,11 @@ def run(g, *, seed=1, eps=0.01, omega_: float, epoch=1024, LL, LU, sigma_mode=SI
     opts = RunOpts(seed, stream, eps, omega_, epoch, sigma_mode, start_epoch, stop_after_epochs)
     res = RunResult()
     per = (CheckInfo * max_epochs)()
-    rc = lib().orc_run(g.ref, C.byref(opts), _p(LL), _p(LU), _p(c), C.byref(res), per, max_epochs)
+    if threads > 1:
+        rc = lib().orc_run_mt(g.ref, C.byref(opts), _p(LL), _p(LU), _p(c), C.byref(res), per, max_epochs,
+                              threads)
+    else:
+        rc = lib().orc_run(g.ref, C.byref(opts), _p(LL), _p(LU), _p(c), C.byref(res), per, max_epochs)
     if rc != 0:
         raise RuntimeError(f"oracle run failed: {rc}")
     k = min(res.epochs, max_epochs)
@@ -283,16 +311,25 @@ def alloc_delta(prior: np.ndarray, Cc: float, delta: float, beta: float = 1e-3):
     return LL, LU
 
 
-def calibrate(g, *, seed=1, omega_: float, delta=0.1, sigma_mode=SIGMA_AUTO):
+def calibrate(g, *, seed=1, omega_: float, delta=0.1, sigma_mode=SIGMA_AUTO, threads=1):
     g = as_graph(g)
     cp = np.zeros(g.n, dtype=np.uint32)
     LL = np.zeros(g.n)
     LU = np.zeros(g.n)
     Cc = C.c_double()
-    rc = lib().orc_calibrate(g.ref, seed, omega_, delta, sigma_mode, _p(cp), C.byref(Cc), _p(LL), _p(LU))
+    rc = lib().orc_calibrate_mt(g.ref, seed, omega_, delta, sigma_mode, _p(cp), C.byref(Cc), _p(LL), _p(LU),
+                                threads)
     if rc != 0:
         raise RuntimeError(f"oracle calibration failed: {rc}")
     return dict(cprime=cp, C=Cc.value, LL=LL, LU=LU, tau0=int(np.ceil(omega_ / 100.0)))
+
+
+def neglog(delta: np.ndarray) -> np.ndarray:
+    """L = -ln(delta) per vertex, computed by the oracle (libm log in FP64)."""
+    d = np.ascontiguousarray(delta, dtype=np.float64)
+    L = np.zeros(len(d))
+    lib().orc_neglog(len(d), _p(d), _p(L))
+    return L
 
 
 def uniform_delta(n: int, delta: float):

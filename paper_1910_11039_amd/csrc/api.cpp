@@ -719,16 +719,20 @@ extern "C" kad_status kad_set_delta(kad_sampler *s, const double *h_delta_L, con
     }
     if (!(sum < 0.5L * (long double)s->o.delta))
         return fail(KAD_EINVAL, "sum of delta_L + delta_U must stay below delta / 2");
+    // L = ln(1/delta) is taken once per vertex on the host in FP64 (the
+    // C library's log), in the caller's numbering, then mapped in
+    std::vector<double> Lh((size_t)n);
     HIPCHK(hipSetDevice(s->ctx->device));
     hipStream_t st = s->ctx->stream;
     double *t = nullptr;
     HIPCHK(hipMallocAsync((void **)&t, 8ull * n, st));
-    HIPCHK(hipMemcpyAsync(t, h_delta_L, 8ull * n, hipMemcpyHostToDevice, st));
-    HIPCHK(launch_from_caller_f64(n, s->g->d_orig, t, s->prior, st));
-    HIPCHK(launch_neglog(n, s->prior, s->LL, st));
-    HIPCHK(hipMemcpyAsync(t, h_delta_U, 8ull * n, hipMemcpyHostToDevice, st));
-    HIPCHK(launch_from_caller_f64(n, s->g->d_orig, t, s->prior, st));
-    HIPCHK(launch_neglog(n, s->prior, s->LU, st));
+    for (int side = 0; side < 2; ++side) {
+        const double *d = side ? h_delta_U : h_delta_L;
+        for (int32_t v = 0; v < n; ++v) Lh[(size_t)v] = -log(d[v]);
+        HIPCHK(hipMemcpyAsync(t, Lh.data(), 8ull * n, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_from_caller_f64(n, s->g->d_orig, t, side ? s->LU : s->LL, st));
+        HIPCHK(hipStreamSynchronize(st));   // Lh is refilled for the other side
+    }
     HIPCHK(hipFreeAsync(t, st));
     HIPCHK(hipStreamSynchronize(st));
     s->delta_ready = true;

@@ -162,12 +162,6 @@ __global__ void k_btilde(int32_t n, const uint32_t *c, double tau, double *b)
         b[v] = (double)c[v] / tau;
 }
 
-__global__ void k_neglog(int32_t n, const double *in, double *out)
-{
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        out[v] = -log(in[v]);
-}
-
 __global__ void k_philox(uint64_t seed, uint64_t stream, uint64_t first, uint32_t count, uint32_t nwords,
                          uint64_t *out)
 {
@@ -780,12 +774,6 @@ hipError_t launch_fg(int32_t n, const uint32_t *c, double tau, const double *LL,
 hipError_t launch_btilde(int32_t n, const uint32_t *c, double tau, double *b, hipStream_t st)
 {
     hipLaunchKernelGGL(k_btilde, dim3(grid_for(n, 256)), dim3(256), 0, st, n, c, tau, b);
-    return hipGetLastError();
-}
-
-hipError_t launch_neglog(int32_t n, const double *in, double *out, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_neglog, dim3(grid_for(n, 256)), dim3(256), 0, st, n, in, out);
     return hipGetLastError();
 }
 

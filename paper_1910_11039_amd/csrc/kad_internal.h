@@ -142,7 +142,6 @@ size_t alloc_partials(int32_t n);
 hipError_t launch_fg(int32_t n, const uint32_t *c, double tau, const double *LL, const double *LU,
                      double omega, double *f, double *g, hipStream_t st);
 hipError_t launch_btilde(int32_t n, const uint32_t *c, double tau, double *b, hipStream_t st);
-hipError_t launch_neglog(int32_t n, const double *in, double *out, hipStream_t st);
 hipError_t launch_philox(uint64_t seed, uint64_t stream, uint64_t first, uint32_t count,
                          uint32_t nwords, uint64_t *out, hipStream_t st);
 
