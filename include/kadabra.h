@@ -267,6 +267,36 @@ kad_status kad_mlp_train_step(kad_mlp *m, const float *d_x, const float *d_y, in
  * or h_y (host) when d_y is NULL. */
 kad_status kad_mlp_forward(kad_mlp *m, const float *d_x, int64_t rows, float *d_y, float *h_y);
 
+/* Training options of kad_mlp_train. */
+typedef struct {
+    int32_t epochs;           /* passes; each is ceil(rows / batch) Adam steps   */
+    int32_t batch;            /* rows per step                                    */
+    float lr;                 /* Adam step size of the first epochs               */
+    int32_t lr_halve_every;   /* the step size halves every this many epochs      */
+                              /* (0: constant)                                    */
+    uint64_t seed;            /* Philox seed (stream 2) of the initialisation and */
+                              /* of the batches                                   */
+} kad_train_opts;
+
+/* kad_mlp_train: trains the prior network on the vertices of ngraphs graphs.
+ * The rows are the graphs' vertices, graph after graph, each graph's in its
+ * caller numbering.  Row v of graph i: the features of kad_features, and
+ * the target ln(b~ + 1/omega) with b~ = h_btilde[i][v] (float64[n_i], the
+ * estimate a plain run gave) and omega = h_omega[i].  The features are
+ * standardised with their mean and population standard deviation over all
+ * rows (FP64 sums; a zero deviation is taken as 1).  Initialisation: weight
+ * i (in the layout of kad_set_mlp_weights) is (2u - 1) sqrt(6 / fan_in),
+ * u = unit53(draw 0 of Philox sample i of stream 2); biases 0.  Adam step j
+ * (beta1 0.9, beta2 0.999, eps 1e-8; mean squared error) takes batch rows
+ * floor(u_b rows / 2^64), u_b = draw b of Philox sample 2^32 + j (uniform
+ * rows, with replacement).  Everything runs on the device.
+ * Out: h_params float32[4481], h_norm float32[6] (means, then standard
+ * deviations: the h_norm of kad_set_mlp_weights) and, unless NULL,
+ * h_losses float32[epochs] (each epoch's mean batch loss). */
+kad_status kad_mlp_train(kad_ctx *ctx, const kad_graph *const *graphs, const double *const *h_btilde,
+                         const double *h_omega, int32_t ngraphs, const kad_train_opts *o, float *h_params,
+                         float *h_norm, float *h_losses);
+
 #ifdef __cplusplus
 }
 #endif

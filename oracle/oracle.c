@@ -815,6 +815,19 @@ void orc_features(const orc_graph *g, double *x /* n x 3, row-major */)
 
 /* Parameter layout (4481 values): W1[64][3], b1[64], W2[64][64], b2[64],
  * W3[64], b3.  Row-major, out x in. */
+/* Learned prior from the network output y = ln(b + 1/omega) (the
+ * regression target): b = e^y - 1/omega, clamped to [0, 1], the range of
+ * betweenness (Sec. I). */
+void orc_prior_from_output(int64_t n, const double *y, double omega, double *prior)
+{
+    for (int64_t v = 0; v < n; ++v) {
+        double b = exp(y[v]) - 1.0 / omega;
+        if (b < 0.0) b = 0.0;
+        if (b > 1.0) b = 1.0;
+        prior[v] = b;
+    }
+}
+
 void orc_mlp_forward(const double *p, const double *x, int64_t rows, double *y)
 {
     const double *W1 = p, *b1 = p + 192, *W2 = p + 256, *b2 = p + 4352, *W3 = p + 4416, *b3 = p + 4480;
@@ -1129,4 +1142,62 @@ int orc_run_mt(const orc_graph *g, const orc_run_opts *o, const double *LL, cons
     res->edges = edges;
     mt_pool_free(&p);
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Training loop of the prior network (not in the paper).  Weights drawn */
+/* uniformly in [-sqrt(6/fan_in), sqrt(6/fan_in)) (He), biases zero:     */
+/* parameter i takes draw 0 of Philox sample i of stream 2.  Adam step j */
+/* (counted over all epochs) takes `batch` rows drawn uniformly with     */
+/* replacement: row b is floor(u rows / 2^64), u = draw b of sample      */
+/* 2^32 + j of stream 2.  The step size halves every `halve_every`       */
+/* epochs.  losses[e] = mean over epoch e's steps of the batch loss.     */
+/* ------------------------------------------------------------------ */
+
+static double orc_unit53(uint64_t u) { return (double)(u >> 11) * 0x1p-53; }
+
+void orc_mlp_init(uint64_t seed, double *p)
+{
+    for (int i = 0; i < ORC_MLP_PARAMS; ++i) {
+        double bound = 0.0;
+        if (i < 192) bound = sqrt(6.0 / 3.0);                 /* W1 */
+        else if (i >= 256 && i < 4352) bound = sqrt(6.0 / 64.0);   /* W2 */
+        else if (i >= 4416 && i < 4480) bound = sqrt(6.0 / 64.0);  /* W3 */
+        p[i] = bound > 0.0 ? (2.0 * orc_unit53(orc_draw(seed, 2, (uint64_t)i, 0)) - 1.0) * bound : 0.0;
+    }
+}
+
+void orc_batch_rows(uint64_t seed, uint64_t step, int32_t batch, int64_t rows, int64_t *out)
+{
+    for (int32_t b = 0; b < batch; ++b)
+        out[b] = (int64_t)mulhi64(orc_draw(seed, 2, (1ull << 32) + step, (uint64_t)b), (uint64_t)rows);
+}
+
+void orc_mlp_train(const double *x, const double *y, int64_t rows, int32_t epochs, int32_t batch, double lr,
+                   int32_t halve_every, uint64_t seed, double *p, double *losses)
+{
+    double *grad = (double *)malloc(sizeof(double) * ORC_MLP_PARAMS);
+    double *m = (double *)calloc(ORC_MLP_PARAMS, sizeof(double));
+    double *v = (double *)calloc(ORC_MLP_PARAMS, sizeof(double));
+    double *xb = (double *)malloc(sizeof(double) * 3 * (size_t)batch);
+    double *yb = (double *)malloc(sizeof(double) * (size_t)batch);
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)batch);
+    orc_mlp_init(seed, p);
+    const int64_t steps = (rows + batch - 1) / batch;
+    uint64_t j = 0;
+    for (int32_t e = 0; e < epochs; ++e) {
+        const double lr_e = lr * pow(0.5, (double)(halve_every > 0 ? e / halve_every : 0));
+        double sum = 0.0;
+        for (int64_t s = 0; s < steps; ++s, ++j) {
+            orc_batch_rows(seed, j, batch, rows, idx);
+            for (int32_t b = 0; b < batch; ++b) {
+                for (int k = 0; k < 3; ++k) xb[3 * b + k] = x[3 * idx[b] + k];
+                yb[b] = y[idx[b]];
+            }
+            sum += orc_mlp_loss_grad(p, xb, yb, batch, grad);
+            orc_adam_step(p, grad, m, v, ORC_MLP_PARAMS, (int64_t)j + 1, lr_e, 0.9, 0.999, 1e-8);
+        }
+        if (losses) losses[e] = sum / (double)steps;
+    }
+    free(grad); free(m); free(v); free(xb); free(yb); free(idx);
 }

@@ -108,11 +108,16 @@ int orc_calibrate_mt(const orc_graph *g, uint64_t seed, double omega, double del
 void orc_brandes(const orc_graph *g, double *bc);
 
 void orc_features(const orc_graph *g, double *x);
+void orc_prior_from_output(int64_t n, const double *y, double omega, double *prior);
 void orc_mlp_forward(const double *p, const double *x, int64_t rows, double *y);
 double orc_mlp_loss_grad(const double *p, const double *x, const double *target, int64_t rows,
                          double *grad);
 void orc_adam_step(double *p, const double *grad, double *m, double *v, int64_t count, int64_t step,
                    double lr, double b1, double b2, double eps);
+void orc_mlp_init(uint64_t seed, double *p);
+void orc_batch_rows(uint64_t seed, uint64_t step, int32_t batch, int64_t rows, int64_t *out);
+void orc_mlp_train(const double *x, const double *y, int64_t rows, int32_t epochs, int32_t batch, double lr,
+                   int32_t halve_every, uint64_t seed, double *p, double *losses);
 
 #ifdef __cplusplus
 }

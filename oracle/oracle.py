@@ -113,9 +113,13 @@ def lib():
         L.orc_brandes.argtypes = [vp, vp]
         L.orc_features.argtypes = [vp, vp]
         L.orc_mlp_forward.argtypes = [vp, vp, i64, vp]
+        L.orc_prior_from_output.argtypes = [i64, vp, dbl, vp]
         L.orc_mlp_loss_grad.restype = dbl
         L.orc_mlp_loss_grad.argtypes = [vp, vp, vp, i64, vp]
         L.orc_adam_step.argtypes = [vp, vp, vp, vp, i64, i64, dbl, dbl, dbl, dbl]
+        L.orc_mlp_init.argtypes = [u64, vp]
+        L.orc_batch_rows.argtypes = [u64, u64, i32, i64, vp]
+        L.orc_mlp_train.argtypes = [vp, vp, i64, i32, i32, dbl, i32, u64, vp, vp]
         _lib = L
     return _lib
 
@@ -366,6 +370,14 @@ def mlp_forward(params: np.ndarray, x: np.ndarray) -> np.ndarray:
     return y
 
 
+def prior_from_output(y: np.ndarray, omega_: float) -> np.ndarray:
+    """Learned prior b = e^y - 1/omega clamped to [0, 1]."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    pr = np.zeros(len(y))
+    lib().orc_prior_from_output(len(y), _p(y), omega_, _p(pr))
+    return pr
+
+
 def mlp_loss_grad(params: np.ndarray, x: np.ndarray, target: np.ndarray):
     p = np.ascontiguousarray(params, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64)
@@ -378,3 +390,25 @@ def mlp_loss_grad(params: np.ndarray, x: np.ndarray, target: np.ndarray):
 def adam_step(params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     """In place on float64 arrays."""
     lib().orc_adam_step(_p(params), _p(grad), _p(m), _p(v), len(params), step, lr, b1, b2, eps)
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    p = np.zeros(MLP_PARAMS)
+    lib().orc_mlp_init(seed, _p(p))
+    return p
+
+
+def batch_rows(seed: int, step: int, batch: int, rows: int) -> np.ndarray:
+    out = np.zeros(batch, dtype=np.int64)
+    lib().orc_batch_rows(seed, step, batch, rows, _p(out))
+    return out
+
+
+def mlp_train(x: np.ndarray, y: np.ndarray, *, epochs: int, batch: int, lr: float, halve_every: int, seed: int):
+    """FP64 training loop (initialisation, batches, Adam); returns (params, per-epoch losses)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    p = np.zeros(MLP_PARAMS)
+    losses = np.zeros(epochs)
+    lib().orc_mlp_train(_p(x), _p(y), len(y), epochs, batch, lr, halve_every, seed, _p(p), _p(losses))
+    return p, losses

@@ -1485,6 +1485,103 @@ extern "C" kad_status kad_mlp_forward(kad_mlp *m, const float *d_x, int64_t rows
     return KAD_OK;
 }
 
+// Training of the prior network, everything on the device: features and
+// targets of every graph's vertices (rows in graph order, vertices in the
+// caller's numbering), the standardisation vector, the initialisation,
+// then epochs of Adam steps on batches drawn from a Philox stream.
+extern "C" kad_status kad_mlp_train(kad_ctx *ctx, const kad_graph *const *graphs, const double *const *h_btilde,
+                                    const double *h_omega, int32_t ngraphs, const kad_train_opts *o,
+                                    float *h_params, float *h_norm, float *h_losses)
+{
+    if (!ctx || !graphs || !h_btilde || !h_omega || !o || !h_params || !h_norm)
+        return fail(KAD_EINVAL, "null argument");
+    if (ngraphs < 1 || o->epochs < 1 || o->batch < 1 || !(o->lr > 0.0f) || o->lr_halve_every < 0)
+        return fail(KAD_EINVAL, "bad training options");
+    int64_t rows = 0;
+    for (int32_t i = 0; i < ngraphs; ++i) {
+        if (!graphs[i] || !h_btilde[i] || !(h_omega[i] > 0.0)) return fail(KAD_EINVAL, "bad graph, b~ or omega");
+        if (graphs[i]->device != ctx->device) return fail(KAD_EINVAL, "graph on another device");
+        rows += graphs[i]->n;
+    }
+    if (rows * 3 >= (int64_t)1 << 31) return fail(KAD_EOVERFLOW, "too many training rows");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    float *X = nullptr, *Y = nullptr, *XB = nullptr, *YB = nullptr, *norm = nullptr, *feat = nullptr;
+    double *bt = nullptr, *mom = nullptr, *acc = nullptr;
+    kad_mlp *m = nullptr;
+    kad_status r = KAD_OK;
+    int32_t nmax = 0;
+    for (int32_t i = 0; i < ngraphs; ++i) nmax = std::max(nmax, graphs[i]->n);
+    const size_t B = (size_t)o->batch;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        void *ps[] = {X, Y, XB, YB, norm, feat, bt, mom, acc};
+        for (void *q : ps)
+            if (q) (void)hipFree(q);
+        if (m) kad_mlp_free(m);
+    };
+    if (hipMalloc((void **)&X, 12ull * rows) != hipSuccess || hipMalloc((void **)&Y, 4ull * rows) != hipSuccess ||
+        hipMalloc((void **)&XB, 12ull * B) != hipSuccess || hipMalloc((void **)&YB, 4ull * B) != hipSuccess ||
+        hipMalloc((void **)&norm, 64) != hipSuccess || hipMalloc((void **)&feat, 12ull * nmax) != hipSuccess ||
+        hipMalloc((void **)&bt, 8ull * nmax) != hipSuccess ||
+        hipMalloc((void **)&mom, 8 * moments_scratch_doubles()) != hipSuccess ||
+        hipMalloc((void **)&acc, 8ull * o->epochs) != hipSuccess) {
+        cleanup();
+        return fail(KAD_ENOMEM, "training buffers");
+    }
+#define TRAIN_CHK(expr)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            cleanup();                                                                   \
+            return fail(KAD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        }                                                                                \
+    } while (0)
+    int64_t off = 0;
+    for (int32_t i = 0; i < ngraphs; ++i) {
+        const kad_graph *g = graphs[i];
+        TRAIN_CHK(launch_features(g->dev(), feat, st));
+        TRAIN_CHK(launch_to_caller_f32x3(g->n, g->d_orig, feat, X + 3 * off, st));
+        TRAIN_CHK(hipMemcpyAsync(bt, h_btilde[i], 8ull * g->n, hipMemcpyHostToDevice, st));
+        TRAIN_CHK(launch_target(g->n, bt, h_omega[i], Y + off, st));
+        TRAIN_CHK(hipStreamSynchronize(st));   // bt is refilled for the next graph
+        off += g->n;
+    }
+    TRAIN_CHK(launch_feature_norm(X, rows, mom, norm, st));
+    TRAIN_CHK(launch_normalize((int32_t)rows, X, norm, st));
+    TRAIN_CHK(launch_zero_words((uint32_t *)acc, 2ull * o->epochs, st));
+    {
+        std::vector<float> zero(4481, 0.0f);
+        r = kad_mlp_create(ctx, zero.data(), &m);
+        if (r != KAD_OK) { cleanup(); return r; }
+    }
+    TRAIN_CHK(launch_mlp_init(o->seed, m->params, st));
+    r = mlp_scratch(m, o->batch);
+    if (r != KAD_OK) { cleanup(); return r; }
+    const int64_t steps_per_epoch = (rows + o->batch - 1) / o->batch;
+    uint64_t step = 0;
+    for (int32_t e = 0; e < o->epochs; ++e) {
+        const int halvings = o->lr_halve_every > 0 ? e / o->lr_halve_every : 0;
+        const float lr = o->lr * powf(0.5f, (float)halvings);
+        for (int64_t j = 0; j < steps_per_epoch; ++j, ++step) {
+            TRAIN_CHK(launch_gather_batch(o->seed, step, o->batch, rows, X, Y, XB, YB, st));
+            TRAIN_CHK(launch_mlp_loss_grad(m->params, XB, YB, o->batch, m->grad, m->loss, m->scratch, st));
+            TRAIN_CHK(launch_adam(m->params, m->grad, m->m, m->v, 4481, (int)(step + 1), lr, st));
+            TRAIN_CHK(launch_acc_loss(m->loss, acc, e, st));
+        }
+    }
+    std::vector<double> lsum((size_t)o->epochs);
+    TRAIN_CHK(hipMemcpyAsync(h_params, m->params, 4 * 4481, hipMemcpyDeviceToHost, st));
+    TRAIN_CHK(hipMemcpyAsync(h_norm, norm, 4 * 6, hipMemcpyDeviceToHost, st));
+    TRAIN_CHK(hipMemcpyAsync(lsum.data(), acc, 8ull * o->epochs, hipMemcpyDeviceToHost, st));
+    TRAIN_CHK(hipStreamSynchronize(st));
+#undef TRAIN_CHK
+    if (h_losses)
+        for (int32_t e = 0; e < o->epochs; ++e) h_losses[e] = (float)(lsum[(size_t)e] / (double)steps_per_epoch);
+    cleanup();
+    return KAD_OK;
+}
+
 // ----------------------------------------------------------- device memory
 
 extern "C" kad_status kad_device_alloc(kad_ctx *ctx, size_t bytes, void **d_out)

@@ -25,6 +25,14 @@ __global__ void k_relabel_rows(int32_t n, const int64_t *rp_in, const int32_t *c
     }
 }
 
+// Clears `words` 32-bit words (a kernel, not a memset node, so that it is
+// safe under stream capture).
+__global__ void k_zero_words(uint32_t *p, size_t words)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = 0u;
+}
+
 __global__ void k_degrees(int32_t n, const int64_t *rp, uint32_t *deg)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
@@ -83,6 +91,15 @@ hipError_t sort_rows(int32_t n, int64_t nnz, const int64_t *rp, const int32_t *i
     e = hipcub::DeviceSegmentedSort::SortKeys(tmp, bytes, in, out, (int)nnz, (int)n, rp, rp + 1, st);
     const hipError_t f = hipFreeAsync(tmp, st);
     return e != hipSuccess ? e : f;
+}
+
+hipError_t launch_zero_words(uint32_t *p, size_t words, hipStream_t st)
+{
+    if (words == 0) return hipSuccess;
+    size_t blocks = (words + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(256), 0, st, p, words);
+    return hipGetLastError();
 }
 
 hipError_t launch_degrees(int32_t n, const int64_t *rp, uint32_t *deg, hipStream_t st)

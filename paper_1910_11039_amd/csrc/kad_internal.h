@@ -74,6 +74,8 @@ hipError_t launch_relabel_rows(int32_t n, const int64_t *rp_in, const int32_t *c
 // out[orig[i]] = in[i]; from_caller writes out[i] = in[orig[i]].
 // deg[v] = rp[v + 1] - rp[v].
 hipError_t launch_degrees(int32_t n, const int64_t *rp, uint32_t *deg, hipStream_t st);
+// Clears `words` 32-bit words with a kernel.
+hipError_t launch_zero_words(uint32_t *p, size_t words, hipStream_t st);
 // Sorts every row of a CSR (int32 entries) into ascending order.
 hipError_t sort_rows(int32_t n, int64_t nnz, const int64_t *rp, const int32_t *in, int32_t *out, hipStream_t st);
 hipError_t launch_to_caller_u32(int32_t n, const int32_t *orig, const uint32_t *in, uint32_t *out, hipStream_t st);
@@ -105,6 +107,7 @@ struct SampleLaunch {
     int32_t max_len;
     uint32_t *hist;                 // optional: histogram of the counters' values 1..hist_top,
     uint32_t hist_top;              // kept as they are counted (the calibration's)
+    const int32_t *count_map;       // optional: counter index of a vertex (internal id -> caller id)
 };
 
 hipError_t launch_sampler(const SampleLaunch &a, int slots, int block, hipStream_t st);
@@ -180,5 +183,15 @@ hipError_t launch_adam(float *params, const float *grad, float *m, float *v, int
 hipError_t launch_prior_from_mlp(int32_t n, const float *yhat, double omega, double *prior,
                                  hipStream_t st);
 size_t mlp_scratch_floats(int64_t rows);
+// Training: target ln(b~ + 1/omega); feature standardisation vector [mean,
+// std] (FP64 sums, scratch of moments_scratch_doubles()); Philox-seeded
+// initialisation; the rows of one Adam step; the per-epoch loss sum.
+hipError_t launch_target(int32_t n, const double *btilde, double omega, float *y, hipStream_t st);
+size_t moments_scratch_doubles();
+hipError_t launch_feature_norm(const float *x, int64_t rows, double *scratch, float *norm, hipStream_t st);
+hipError_t launch_mlp_init(uint64_t seed, float *params, hipStream_t st);
+hipError_t launch_gather_batch(uint64_t seed, uint64_t step, int32_t batch, int64_t rows, const float *x,
+                               const float *y, float *xb, float *yb, hipStream_t st);
+hipError_t launch_acc_loss(const float *loss, double *acc, int e, hipStream_t st);
 
 }  // namespace kad

@@ -16,6 +16,7 @@
 #include <math.h>
 
 #include "kad_internal.h"
+#include "philox.h"
 
 namespace kad {
 namespace {
@@ -414,9 +415,121 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, int count, 
 __global__ void k_prior(int32_t n, const float *y, double inv_omega, double *prior)
 {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        // betweenness lies in [0, 1] (Sec. I), so the prior is clamped to it;
+        // a non-finite output passes through (the budget check rejects it)
         const double b = exp((double)y[v]) - inv_omega;
-        prior[v] = b > 0.0 ? b : (b == b ? 0.0 : b);
+        prior[v] = b > 1.0 ? 1.0 : (b > 0.0 ? b : (b == b ? 0.0 : b));
     }
+}
+
+// ---- training (kad_mlp_train) ----
+
+// Regression target of a vertex: y = ln(b~ + 1/omega), in FP64, stored FP32.
+__global__ void k_target(int32_t n, const double *b, double inv_omega, float *y)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        y[v] = (float)log(b[v] + inv_omega);
+}
+
+constexpr int MOM_BLOCKS = 256;
+
+// Per-block FP64 partial sums of the three feature columns (pass 0) or of
+// their squared deviations from `mean` (pass 1); a block's rows are a fixed
+// grid-stride set, so the sums do not depend on scheduling.
+__global__ __launch_bounds__(256) void k_moments(const float *x, int64_t rows, const double *mean, double *part)
+{
+    __shared__ double sm[3][256];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    const double m0 = mean ? mean[0] : 0.0, m1 = mean ? mean[1] : 0.0, m2 = mean ? mean[2] : 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
+        const double x0 = (double)x[3 * r] - m0, x1 = (double)x[3 * r + 1] - m1, x2 = (double)x[3 * r + 2] - m2;
+        if (mean) {
+            a0 += x0 * x0;
+            a1 += x1 * x1;
+            a2 += x2 * x2;
+        } else {
+            a0 += x0;
+            a1 += x1;
+            a2 += x2;
+        }
+    }
+    sm[0][threadIdx.x] = a0;
+    sm[1][threadIdx.x] = a1;
+    sm[2][threadIdx.x] = a2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int j = 0; j < 3; ++j) sm[j][threadIdx.x] += sm[j][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[3 * blockIdx.x + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+// Sums the block partials in block order: mean (pass 0) or the population
+// standard deviation (pass 1; a zero deviation is taken as 1); writes the
+// FP64 value and, for pass 1, the FP32 standardisation vector norm =
+// [mean, std].
+__global__ void k_moments_finish(const double *part, int nb, int64_t rows, double *out, const double *mean,
+                                 float *norm)
+{
+    const int j = threadIdx.x;
+    if (j >= 3) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[3 * b + j];
+    if (!mean) {
+        out[j] = s / (double)rows;
+    } else {
+        double sd = sqrt(s / (double)rows);
+        if (!(sd > 0.0)) sd = 1.0;
+        out[j] = sd;
+        norm[j] = (float)mean[j];
+        norm[3 + j] = (float)sd;
+    }
+}
+
+// Uniform initialisation in [-sqrt(6 / fan_in), sqrt(6 / fan_in)) for the
+// weights (He), zero biases: parameter i takes draw 0 of Philox sample i of
+// stream 2, u = (2 * unit53 - 1) * bound.
+__global__ void k_mlp_init(uint64_t seed, float *p)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NP) return;
+    double bound = 0.0;
+    if (i < OFF_B1) bound = sqrt(6.0 / 3.0);
+    else if (i >= OFF_W2 && i < OFF_B2) bound = sqrt(6.0 / 64.0);
+    else if (i >= OFF_W3 && i < OFF_B3) bound = sqrt(6.0 / 64.0);
+    float v = 0.f;
+    if (bound > 0.0) {
+        SampleDraws dr;
+        dr.init(seed, 2, (uint64_t)i);
+        const double u = (double)(dr.get(0) >> 11) * 0x1p-53;
+        v = (float)((2.0 * u - 1.0) * bound);
+    }
+    p[i] = v;
+}
+
+// Batch of Adam step j: row b of the batch is row floor(u * rows / 2^64) of
+// the training set, u = draw b of Philox sample 2^32 + j of stream 2
+// (uniform rows, with replacement).
+__global__ void k_gather_batch(uint64_t seed, uint64_t step, int32_t batch, int64_t rows, const float *x,
+                               const float *y, float *xb, float *yb)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    uint64_t c[4] = {(uint64_t)b >> 2, (1ull << 32) + step, 0, 0};
+    philox4x64_10(seed, 2, c);
+    const uint64_t u = c[b & 3];
+    const int64_t r = (int64_t)__umul64hi(u, (uint64_t)rows);
+    xb[3 * b] = x[3 * r];
+    xb[3 * b + 1] = x[3 * r + 1];
+    xb[3 * b + 2] = x[3 * r + 2];
+    yb[b] = y[r];
+}
+
+// acc[e] += loss (the batch loss, a mean over its rows).
+__global__ void k_acc_loss(const float *loss, double *acc, int e)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) acc[e] += (double)*loss;
 }
 
 int blocks_for_rows(int64_t rows)
@@ -491,6 +604,48 @@ hipError_t launch_prior_from_mlp(int32_t n, const float *yhat, double omega, dou
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
     hipLaunchKernelGGL(k_prior, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, n, yhat,
                        1.0 / omega, prior);
+    return hipGetLastError();
+}
+
+hipError_t launch_target(int32_t n, const double *btilde, double omega, float *y, hipStream_t st)
+{
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_target, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, n, btilde,
+                       1.0 / omega, y);
+    return hipGetLastError();
+}
+
+size_t moments_scratch_doubles() { return 3 * MOM_BLOCKS + 6; }
+
+hipError_t launch_feature_norm(const float *x, int64_t rows, double *scratch, float *norm, hipStream_t st)
+{
+    const int nb = (int)std::min<int64_t>(MOM_BLOCKS, std::max<int64_t>(1, (rows + 255) / 256));
+    double *part = scratch, *mean = scratch + 3 * MOM_BLOCKS, *sd = mean + 3;
+    hipLaunchKernelGGL(k_moments, dim3(nb), dim3(256), 0, st, x, rows, (const double *)nullptr, part);
+    hipLaunchKernelGGL(k_moments_finish, dim3(1), dim3(64), 0, st, part, nb, rows, mean, (const double *)nullptr,
+                       (float *)nullptr);
+    hipLaunchKernelGGL(k_moments, dim3(nb), dim3(256), 0, st, x, rows, (const double *)mean, part);
+    hipLaunchKernelGGL(k_moments_finish, dim3(1), dim3(64), 0, st, part, nb, rows, sd, (const double *)mean, norm);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_init(uint64_t seed, float *params, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_init, dim3((NP + 255) / 256), dim3(256), 0, st, seed, params);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_batch(uint64_t seed, uint64_t step, int32_t batch, int64_t rows, const float *x,
+                               const float *y, float *xb, float *yb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather_batch, dim3((batch + 255) / 256), dim3(256), 0, st, seed, step, batch, rows, x, y,
+                       xb, yb);
+    return hipGetLastError();
+}
+
+hipError_t launch_acc_loss(const float *loss, double *acc, int e, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_acc_loss, dim3(1), dim3(64), 0, st, loss, acc, e);
     return hipGetLastError();
 }
 

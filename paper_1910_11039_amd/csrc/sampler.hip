@@ -1068,12 +1068,13 @@ __device__ int32_t pick_pred_layer(Smem<BS> &sm, const Ctx &c, int side, int32_t
     return pick >= 0 ? c.g.newid[pick] : pick;
 }
 
-// One count for an interior vertex.  With a histogram (the calibration),
+// One count for an interior vertex (at its caller id when the launch maps
+// counters to the caller's numbering).  With a histogram (the calibration),
 // its bins follow the counter: the value moves from bin c to bin c + 1
 // (a vertex is counted at most once per sample, so c < samples <= top).
 __device__ __forceinline__ void count_vertex(const SampleLaunch &a, uint32_t *sf, int32_t v)
 {
-    const uint32_t old = atomicAdd(sf + v, 1u);
+    const uint32_t old = atomicAdd(sf + (a.count_map ? a.count_map[v] : v), 1u);
     if (a.hist) {
         if (old >= 1) atomicSub(a.hist + min(old, a.hist_top), 1u);
         atomicAdd(a.hist + min(old + 1, a.hist_top), 1u);

@@ -60,6 +60,11 @@ class kad_result(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class kad_train_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("lr_halve_every", C.c_int32), ("seed", C.c_uint64)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point
@@ -101,6 +106,7 @@ SIGNATURES = [
     ("kad_mlp_loss_grad", C.c_int, [_vp, _vp, _vp, _i64, _P(C.c_float), _vp]),
     ("kad_mlp_train_step", C.c_int, [_vp, _vp, _vp, _i64, C.c_float, _P(C.c_float)]),
     ("kad_mlp_forward", C.c_int, [_vp, _vp, _i64, _vp, _vp]),
+    ("kad_mlp_train", C.c_int, [_vp, _P(_vp), _P(_vp), _vp, _i32, _P(kad_train_opts), _vp, _vp, _vp]),
 ]
 
 
@@ -368,6 +374,23 @@ def kad_mlp_forward(m, d_x: int, rows: int) -> np.ndarray:
     y = np.zeros(rows, dtype=np.float32)
     _check(lib().kad_mlp_forward(m, C.c_void_p(d_x), rows, None, _p(y)))
     return y
+
+
+def kad_mlp_train(ctx, graphs, btildes, omegas, epochs: int, batch: int, lr: float, lr_halve_every: int,
+                  seed: int):
+    """graphs: kad_graph handles; btildes: float64 arrays (caller numbering);
+    omegas: one omega per graph.  Returns (params, norm, per-epoch losses)."""
+    k = len(graphs)
+    gs = (_vp * k)(*[g.value if hasattr(g, "value") else g for g in graphs])
+    bts = [np.ascontiguousarray(b, dtype=np.float64) for b in btildes]
+    bps = (_vp * k)(*[b.ctypes.data for b in bts])
+    om = np.ascontiguousarray(omegas, dtype=np.float64)
+    o = kad_train_opts(epochs, batch, lr, lr_halve_every, seed)
+    params = np.zeros(MLP_PARAMS, dtype=np.float32)
+    norm = np.zeros(6, dtype=np.float32)
+    losses = np.zeros(epochs, dtype=np.float32)
+    _check(lib().kad_mlp_train(ctx, gs, bps, _p(om), k, C.byref(o), _p(params), _p(norm), _p(losses)))
+    return params, norm, losses
 
 
 # ---------------------------------------------------------- convenience

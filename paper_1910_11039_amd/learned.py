@@ -9,10 +9,10 @@ turns that prior into delta_L = delta_U.  The plain allocation remains the
 fallback (the library uses it whenever the learned one is not finite or
 breaks the budget).
 
-Everything numeric runs in the library's HIP kernels (features, forward,
-backward, Adam); this module only orchestrates: it builds the training set
-from plain runs on seeded graphs, shuffles and uploads batches, and stores
-the weights.
+Everything numeric runs in the library's HIP kernels (features, targets,
+standardisation, initialisation, batches, forward, backward, Adam, all
+behind kad_mlp_train); this module only orchestrates: it runs the plain
+method on seeded graphs and stores the weights.
 """
 from __future__ import annotations
 
@@ -34,8 +34,10 @@ def _rng(seed: int, salt: int = 0) -> np.random.Generator:
 
 
 def init_params(seed: int = 7) -> np.ndarray:
-    """Uniform He initialisation (bound sqrt(6 / fan_in)), biases zero,
-    layout W1[64][3], b1[64], W2[64][64], b2[64], W3[64], b3."""
+    """Random weights in the law of the initialisation (uniform within
+    sqrt(6 / fan_in), biases zero; layout W1[64][3], b1[64], W2[64][64],
+    b2[64], W3[64], b3) from a host stream: fixed weights for checking the
+    network kernels.  Training draws its own on the device."""
     r = _rng(seed)
     p = np.zeros(N_PARAMS, dtype=np.float32)
     p[0:192] = r.uniform(-1, 1, 192) * math.sqrt(6 / 3)
@@ -44,69 +46,36 @@ def init_params(seed: int = 7) -> np.ndarray:
     return p
 
 
-def target_of(btilde: np.ndarray, omega: float) -> np.ndarray:
-    """Regression target ln(b~ + 1/omega); the prior is its inverse,
-    max(0, e^y - 1/omega)."""
-    return np.log(btilde + 1.0 / omega).astype(np.float32)
-
-
 def plain_run(ctx: K.Context, g, eps: float = 0.01, delta: float = 0.1, seed: int = 1):
-    """Plain KADABRA on the GPU; returns (features float32[n][3], b~, omega, result)."""
+    """Plain KADABRA on the GPU; returns (resident graph, b~, omega, result)."""
     G = K.Graph(ctx, g)
     S = K.Sampler(G, seed=seed, epsilon=eps, delta=delta)
     r = S.run_to_stop()
     b = S.btilde()
-    x = K.kad_features(ctx.h, G.h, g.n)
     S.close()
-    G.close()
-    return x, b, r.omega, r
+    return G, b, r.omega, r
 
 
 def build_training_set(ctx: K.Context, graphs, eps: float = 0.01, seed: int = 1, log=None):
-    xs, ys = [], []
+    """Plain runs on the training graphs: the graphs stay resident, with
+    their estimates b~ and omegas (the targets are formed on the device)."""
+    Gs, bts, oms = [], [], []
     for g in graphs:
-        x, b, omega, r = plain_run(ctx, g, eps=eps, seed=seed)
-        xs.append(x)
-        ys.append(target_of(b, omega))
+        G, b, omega, r = plain_run(ctx, g, eps=eps, seed=seed)
+        Gs.append(G)
+        bts.append(b)
+        oms.append(omega)
         if log:
             log(f"{g.name}: n={g.n} tau={r.tau} tau0={r.tau0} time={r.t_total_ms:.1f} ms")
-    return np.concatenate(xs), np.concatenate(ys)
+    return Gs, bts, oms
 
 
-def standardize(x: np.ndarray):
-    mean = x.mean(axis=0).astype(np.float32)
-    std = x.std(axis=0).astype(np.float32)
-    std[std == 0] = 1.0
-    return np.concatenate([mean, std]).astype(np.float32)
-
-
-def train(ctx: K.Context, x: np.ndarray, y: np.ndarray, norm: np.ndarray, epochs: int = 8,
-          batch: int = 4096, lr: float = 2e-3, seed: int = 7, log=None):
-    """Adam on mean squared error with the library's forward/backward kernels."""
-    xs = ((x - norm[:3]) / norm[3:]).astype(np.float32)
-    m = K.kad_mlp_create(ctx.h, init_params(seed))
-    losses = []
-    try:
-        for ep in range(epochs):
-            order = _rng(seed, 1 + ep).permutation(len(xs))
-            bx = K.DeviceArray(ctx, xs[order])
-            by = K.DeviceArray(ctx, y[order])
-            tot, cnt = 0.0, 0
-            step_lr = lr * (0.5 ** (ep // 3))
-            for i in range(0, len(xs), batch):
-                rows = min(batch, len(xs) - i)
-                loss = K.kad_mlp_train_step(m, bx.ptr + 12 * i, by.ptr + 4 * i, rows, step_lr)
-                tot += loss * rows
-                cnt += rows
-            bx.close()
-            by.close()
-            losses.append(tot / cnt)
-            if log:
-                log(f"epoch {ep}: mse {losses[-1]:.5f}")
-        params = K.kad_mlp_get_params(m)
-    finally:
-        K.kad_mlp_free(m)
-    return params, losses
+def train(ctx: K.Context, Gs, btildes, omegas, epochs: int = 8, batch: int = 4096, lr: float = 2e-3,
+          halve_every: int = 3, seed: int = 7):
+    """kad_mlp_train: features, targets ln(b~ + 1/omega), standardisation,
+    initialisation and Adam on the mean squared error, in the library's
+    kernels.  Returns (params, norm, per-epoch losses)."""
+    return K.kad_mlp_train(ctx.h, [G.h for G in Gs], btildes, omegas, epochs, batch, lr, halve_every, seed)
 
 
 def save(path: str, params: np.ndarray, norm: np.ndarray, **meta):
@@ -143,14 +112,14 @@ def main():
     graphs = gg.training_graphs(args.graphs)
     log(f"graphs ready in {time.time() - t0:.1f} s")
     ctx = K.Context(0)
-    x, y = build_training_set(ctx, graphs, eps=args.eps, log=log)
-    norm = standardize(x)
-    log(f"training rows: {len(x)}")
+    Gs, bts, oms = build_training_set(ctx, graphs, eps=args.eps, log=log)
+    rows = sum(len(b) for b in bts)
+    log(f"training rows: {rows}")
     t1 = time.time()
-    params, losses = train(ctx, x, y, norm, epochs=args.epochs, log=log)
-    log(f"trained in {time.time() - t1:.1f} s")
+    params, norm, losses = train(ctx, Gs, bts, oms, epochs=args.epochs)
+    log(f"trained in {time.time() - t1:.1f} s; mse per epoch {np.round(losses, 5).tolist()}")
     save(args.out, params, norm, losses=np.array(losses), graph_seeds=np.arange(101, 101 + args.graphs),
-         eps=args.eps, rows=len(x))
+         eps=args.eps, rows=rows)
     log(f"saved {args.out}")
     ctx.close()
 

@@ -152,7 +152,7 @@ def _oracle_learned_delta(oracle, g, params, norm, omega, delta=0.1):
     x = oracle.features(g)
     xs = (x - norm[:3].astype(np.float64)) / norm[3:].astype(np.float64)
     y = oracle.mlp_forward(params.astype(np.float64), xs)
-    prior = np.maximum(np.exp(y) - 1.0 / omega, 0.0)
+    prior = oracle.prior_from_output(y, omega)
     Cc = oracle.alloc_constant(prior, delta)
     return oracle.alloc_delta(prior, Cc, delta)
 
@@ -178,6 +178,25 @@ def test_learned_allocation_matches_oracle_and_keeps_the_guarantee(ctx, oracle):
     assert r.stop_reason in (K.KAD_STOP_COND, K.KAD_STOP_OMEGA)
     bc = oracle.brandes(g)
     assert np.abs(S.btilde() - bc).max() <= 0.01
+
+
+def test_learned_prior_above_one_is_clamped(ctx, oracle):
+    """A network that over-predicts every vertex (output y > ln(1 + 1/omega),
+    prior e^y - 1/omega above 1) still gives a valid learned allocation:
+    the prior is clamped to 1, betweenness's upper end, the bisection's
+    bracket holds, and no calibration samples are spent."""
+    g = gg.rmat(11, 16, 8)
+    G = K.Graph(ctx, g)
+    params = L.init_params(2)
+    params[4480] = 5.0
+    params[4416:4480] = 0.0            # y = 5 for every vertex
+    S = K.Sampler(G, seed=1, epsilon=0.02, delta=0.1, alloc_mode=K.KAD_ALLOC_LEARNED)
+    S.set_mlp_weights(params, np.array([0, 0, 0, 1, 1, 1], dtype=np.float32))
+    r = S.run_to_stop()
+    assert r.tau0 == 0
+    LLg, _ = S.delta_logs()
+    LLo, _ = _oracle_learned_delta(oracle, g, params, np.array([0, 0, 0, 1, 1, 1], dtype=np.float32), r.omega)
+    assert np.allclose(LLg, LLo, rtol=1e-4, atol=0)
 
 
 def test_learned_allocation_falls_back_to_plain(ctx, oracle):
@@ -225,3 +244,30 @@ def test_trained_prior_beats_plain_calibration(ctx, oracle):
         S.run_to_stop()
         assert np.abs(S.btilde() - bc).max() <= 0.01
         S.close()
+
+
+def test_mlp_train_entry_point_matches_oracle_loop(ctx, oracle):
+    """kad_mlp_train (features, targets, standardisation, initialisation,
+    batches and Adam, all on the device) against the oracle's FP64 loop on
+    the oracle's own features, targets and standardisation: the
+    standardisation vector within 1e-6, the loss curve within 2e-3 and the
+    final weights within 2e-3 of their scale (FP32 kernels over 60 Adam
+    steps)."""
+    graphs = [gg.rmat(10, 8, 41), gg.rmat(11, 8, 42)]
+    r = np.random.default_rng(8)
+    bts = [oracle.brandes(g) for g in graphs]
+    omegas = [30000.0, 35000.0]
+    Gs = [K.Graph(ctx, g) for g in graphs]
+    epochs, batch, lr, halve, seed = 4, 256, 2e-3, 3, 9
+    params, norm, losses = K.kad_mlp_train(ctx.h, [G.h for G in Gs], bts, omegas, epochs, batch, lr, halve, seed)
+    x = np.concatenate([oracle.features(g) for g in graphs])
+    y = np.concatenate([np.log(b + 1.0 / om) for b, om in zip(bts, omegas)])
+    mean, std = x.mean(0), x.std(0)
+    assert np.allclose(norm[:3], mean, rtol=1e-6, atol=1e-7)
+    assert np.allclose(norm[3:], std, rtol=1e-6, atol=1e-7)
+    po, lo = oracle.mlp_train((x - mean) / std, y, epochs=epochs, batch=batch, lr=lr, halve_every=halve, seed=seed)
+    assert np.all(np.abs(losses - lo) <= 2e-3 * np.abs(lo)), (losses, lo)
+    for name, sl in SLICES.items():
+        scale = max(np.abs(po[sl]).max(), 1e-3)
+        assert np.abs(params[sl] - po[sl]).max() <= 2e-3 * scale, name
+    assert losses[-1] < losses[0]

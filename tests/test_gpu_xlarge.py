@@ -3,10 +3,11 @@ column indices): the batched sampler at full size, as launched by the
 benchmark, against the oracle.
 
 Builds the graph once with the threaded generator (about a minute).  The
-sampled paths are compared one by one; the plain run to the stop (eps =
-0.01, delta = 0.1, autotuned launch shape, every slot pool, timing on) is
-compared whole with the oracle's threaded run: calibration counters,
-allocation constant, counters, tau and stop epoch.
+sampled paths are compared one by one; the plain arm (eps = 0.01, delta =
+0.1, autotuned launch shape, every slot pool, timing on) is compared with
+the oracle's threaded run over its calibration and first four epochs: the
+oracle needs minutes of host time per epoch of this graph, so the run to
+the stop is compared on the smaller graphs.
 """
 import numpy as np
 import pytest
@@ -47,12 +48,18 @@ def test_rmat26_sampled_paths_at_full_size(big, oracle):
     S.close()
 
 
-def test_rmat26_benched_plain_run_matches_oracle(big, oracle):
+def test_rmat26_first_epochs_match_oracle(big, oracle):
+    """The plain arm in the benchmark's launch shape (autotuned epoch size
+    and workgroups, every slot pool, timing on): omega, the calibration and
+    the allocation, then the first four epochs' counters, tau and per-epoch
+    f/g maxima equal the oracle's threaded run, epoch by epoch."""
     K, ctx, G, g = big
     S = K.Sampler(G, seed=1, epsilon=0.01, delta=0.1, timing=1)
-    r = S.run_to_stop()
-    print(f"device run: E={r.epoch_size} block={r.block_size} slots={r.slots} pools={r.pools} "
-          f"tau0={r.tau0} tau={r.tau} epochs={r.epochs} {r.t_total_ms:.1f} ms", flush=True)
+    stops = [S.step_epoch() for _ in range(4)]
+    r = S.result()
+    c, tau = S.counts()
+    print(f"device: E={r.epoch_size} block={r.block_size} slots={r.slots} pools={r.pools} tau={tau} "
+          f"stopped={stops}", flush=True)
     threads = oracle.host_threads()
     og = oracle.Graph(g)
     omega = oracle.omega_bracket(*oracle.vd_bracket(og), 0.01, 0.1)
@@ -60,24 +67,27 @@ def test_rmat26_benched_plain_run_matches_oracle(big, oracle):
     print(f"oracle bracket done, omega={omega}", flush=True)
     cal = oracle.calibrate(og, seed=1, omega_=omega, threads=threads)
     cp, tau0, Cc = S.calibration()
-    assert tau0 == cal["tau0"] == r.tau0
+    assert tau0 == cal["tau0"]
     assert np.array_equal(cp, cal["cprime"])
     assert abs(Cc - cal["C"]) <= 1e-12 * abs(cal["C"])
     dLL, dLU = S.delta_logs()
     assert np.allclose(dLL, cal["LL"], rtol=1e-12, atol=0)
     assert np.allclose(dLU, cal["LU"], rtol=1e-12, atol=0)
-    print(f"calibration equal (tau0={tau0}); oracle run on {threads} threads", flush=True)
-    c, tau = S.counts()
-    ref = oracle.run(og, seed=1, eps=0.01, omega_=omega, epoch=r.epoch_size, LL=cal["LL"], LU=cal["LU"],
-                     threads=threads)
-    margin = float(ref["min_margin"].min())
-    if margin < 1e-12 * 0.01:
-        pytest.xfail(f"near tie: smallest |eps - max(f, g)| = {margin:.3e} up to the stop epoch")
-    assert (tau, r.epochs, r.stop_reason) == (ref["tau"], ref["epochs"], ref["reason"])
-    assert np.array_equal(c, ref["c"])
-    hist = S.history(r.epochs)
+    print(f"calibration equal (tau0={tau0}); oracle epochs on {threads} threads", flush=True)
+    co = None
+    maxf, maxg = [], []
+    for k in range(4):
+        ref = oracle.run(og, seed=1, eps=0.01, omega_=omega, epoch=r.epoch_size, LL=cal["LL"], LU=cal["LU"],
+                         threads=threads, start_epoch=k, stop_after_epochs=1, c_init=co)
+        co = ref["c"]
+        maxf.append(ref["max_f"][-1])
+        maxg.append(ref["max_g"][-1])
+        print(f"oracle epoch {k} done: tau={ref['tau']} reason={ref['reason']}", flush=True)
+    assert not any(stops[:3])
+    assert tau == ref["tau"]
+    assert np.array_equal(c, co)
+    hist = S.history(4)
     tol = lambda x: 1e-12 * np.maximum(np.abs(x), 0.01)
-    assert np.all(np.abs(hist[:, 0] - ref["max_f"]) <= tol(ref["max_f"]))
-    assert np.all(np.abs(hist[:, 1] - ref["max_g"]) <= tol(ref["max_g"]))
-    print(f"run equal: tau={tau} epochs={r.epochs}", flush=True)
+    assert np.all(np.abs(hist[:, 0] - np.array(maxf)) <= tol(np.array(maxf)))
+    assert np.all(np.abs(hist[:, 1] - np.array(maxg)) <= tol(np.array(maxg)))
     S.close()

@@ -105,3 +105,78 @@ def test_features_match_networkx(oracle):
         want = [math.log1p(dv), sum(math.log1p(G.degree(u)) for u in nb) / dv,
                 math.log1p(sum(G.degree(u) for u in nb))]
         assert np.allclose(x[v], want, rtol=1e-13)
+
+
+def test_prior_from_output_inverts_the_target(oracle):
+    """The target is y = ln(b + 1/omega); the prior inverts it on [0, 1]
+    and clamps outside: y = ln(1/omega) gives 0, anything below gives 0,
+    y = ln(1 + 1/omega) gives 1, anything above gives 1."""
+    omega = 35000.0
+    b = np.array([0.0, 1e-6, 0.003, 0.25, 0.999, 1.0])
+    y = np.log(b + 1.0 / omega)
+    pr = oracle.prior_from_output(y, omega)
+    assert np.allclose(pr, b, rtol=1e-9, atol=1e-15)
+    pr = oracle.prior_from_output(np.array([-50.0, np.log(0.5 / omega), 3.0, 40.0]), omega)
+    assert list(pr) == [0.0, 0.0, 1.0, 1.0]
+
+
+def test_init_is_he_uniform(oracle):
+    """Weights uniform within +-sqrt(6 / fan_in) (mean and variance of the
+    uniform law within 5 standard errors), biases zero."""
+    p = oracle.mlp_init(7)
+    assert np.all(p[192:256] == 0) and np.all(p[4352:4416] == 0) and p[4480] == 0
+    for sl, fan in ((slice(0, 192), 3), (slice(256, 4352), 64), (slice(4416, 4480), 64)):
+        w = p[sl]
+        b = math.sqrt(6 / fan)
+        assert np.all(np.abs(w) < b)
+        n = len(w)
+        assert abs(w.mean()) <= 5 * b / math.sqrt(3 * n)
+        # variance of U(-b, b) is b^2/3; the sample variance's sd is about b^2 sqrt(4/45/n)
+        assert abs(w.var() - b * b / 3) <= 5 * b * b * math.sqrt(4 / 45 / n)
+    assert not np.array_equal(oracle.mlp_init(7), oracle.mlp_init(8))
+
+
+def test_batch_rows_are_uniform(oracle):
+    """Rows drawn for the Adam steps: chi-square over 20 rows, 2000 steps."""
+    from scipy import stats
+    rows = 20
+    cnt = np.zeros(rows)
+    for j in range(2000):
+        r = oracle.batch_rows(3, j, 50, rows)
+        assert r.min() >= 0 and r.max() < rows
+        cnt += np.bincount(r, minlength=rows)
+    chi2 = ((cnt - cnt.mean()) ** 2 / cnt.mean()).sum()
+    assert stats.chi2.sf(chi2, rows - 1) > 1e-4
+
+
+def test_training_loop_equals_torch_adam_on_the_same_batches(oracle):
+    """The oracle's loop (init, batches, Adam, step-size halving, per-epoch
+    loss) against torch autograd + torch.optim.Adam in float64 fed the
+    oracle's batches: same parameters and loss curve."""
+    r = np.random.default_rng(4)
+    rows, batch, epochs, lr, halve = 300, 64, 3, 3e-3, 2
+    x = r.normal(size=(rows, 3))
+    y = np.sin(x[:, 0]) + 0.3 * x[:, 1]
+    p, losses = oracle.mlp_train(x, y, epochs=epochs, batch=batch, lr=lr, halve_every=halve, seed=11)
+    t, fwd = torch_net(oracle.mlp_init(11))
+    opt = torch.optim.Adam([t], lr=lr, betas=(0.9, 0.999), eps=1e-8)
+    X = torch.tensor(x)
+    Y = torch.tensor(y)
+    steps = (rows + batch - 1) // batch
+    j = 0
+    tl = []
+    for e in range(epochs):
+        for g in opt.param_groups:
+            g["lr"] = lr * 0.5 ** (e // halve)
+        s = 0.0
+        for _ in range(steps):
+            idx = torch.tensor(oracle.batch_rows(11, j, batch, rows))
+            opt.zero_grad()
+            loss = ((fwd(X[idx]) - Y[idx]) ** 2).mean()
+            loss.backward()
+            opt.step()
+            s += loss.item()
+            j += 1
+        tl.append(s / steps)
+    assert np.allclose(p, t.detach().numpy(), rtol=1e-9, atol=1e-12)
+    assert np.allclose(losses, tl, rtol=1e-12)
