@@ -135,7 +135,7 @@ def learned_vs_plain(K, G, eps, steps, warmup, args):
     """Both arms on the same graph, seeds and clock."""
     from paper_1910_11039_amd import learned as LRN
     shape = dict(epoch_size=args.epoch_size, slots=args.slots, block_size=args.block,
-                 use_graphs=args.use_graphs, timing=1)
+                 use_graphs=args.use_graphs, timing=1, exact_diameter=getattr(args, "exact_diameter", 0))
     S, (pres, pwalls) = run_arm(K, G, eps, steps, warmup, **shape)
     S.close()   # frees the plain arm's visited state before the learned arm sizes its own
     params, norm = LRN.load()
@@ -257,6 +257,37 @@ def cpu_baseline(g, eps, omega, epoch, epochs_gpu, target_s: float = 20.0):
                            "sample": f"first {n1} samples of the adaptive stream, {t1:.1f} s"}}
 
 
+def sweep(gg, K, args):
+    """Graph-size sweep (the paper's scaling experiment over R-MAT and random
+    hyperbolic graphs of 2^23 .. 2^26 vertices with |E| = 30 |V|; at 2^26
+    R-MAT with edge factor 16 and the hyperbolic graph with |E| = 15 |V|, so
+    that the adjacency stays below 2^31 entries): for each graph the plain
+    arm to the stop at eps (default 0.01), the exact vertex diameter, and
+    adaptive-phase time per vertex.  One JSON line per graph."""
+    eps = args.eps if args.eps > 0 else 0.01
+    names = ["rmat23_ef30", "hyp23", "rmat24_ef30", "hyp24", "rmat25_ef30", "hyp25", "rmat26", "hyp26"]
+    ctx = K.Context(0)
+    for name in names:
+        t0 = time.perf_counter()
+        g = gg.workload(name)
+        t_gen = time.perf_counter() - t0
+        G = K.Graph(ctx, g)
+        t1 = time.perf_counter()
+        vd, wit, runs = K.kad_exact_vd(ctx.h, G.h)
+        t_vd = time.perf_counter() - t1
+        S, (res, walls) = run_arm(K, G, eps, args.steps, args.warmup, timing=1)
+        S.close()
+        G.close()
+        sm = summarize(res, walls)
+        ads = float(np.mean([r["t_ads_ms"] for r in res]))
+        out = {"graph": name, "n": g.n, "m": g.m, "generation_s": round(t_gen, 1), "eps": eps, "delta": 0.1,
+               "exact_vd": vd, "exact_vd_ms": round(1e3 * t_vd, 2), "exact_vd_bfs_runs": runs,
+               "vd_bracket": [res[0]["vd_lo"], res[0]["vd_hi"]],
+               "ads_ms_per_million_vertices": round(ads / (g.n / 1e6), 4), **sm}
+        print(json.dumps(out), flush=True)
+        del g
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +305,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-allocation arm")
     ap.add_argument("--profile-leg", action="store_true",
                     help="only the one-pool roofline leg (the command the committed profiles run)")
+    ap.add_argument("--eps", type=float, default=0.0, help="override the workload's epsilon")
+    ap.add_argument("--sweep", action="store_true",
+                    help="graph-size sweep: R-MAT and random hyperbolic graphs at 2^23 .. 2^26 vertices")
+    ap.add_argument("--exact-diameter", type=int, default=0, help="omega from the exact vertex diameter")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain device copy of known size (counter calibration) and exit")
     args = ap.parse_args()
@@ -290,7 +325,13 @@ def main():
     import graphgen as gg
     from paper_1910_11039_amd import kadabra as K
 
+    if args.sweep:
+        sweep(gg, K, args)
+        return
+
     wname, eps, desc = WORKLOADS[args.workload]
+    if args.eps > 0:
+        eps = args.eps
     t0 = time.perf_counter()
     g = gg.workload(wname)
     gn, gm = g.n, g.m
@@ -307,7 +348,7 @@ def main():
         return
 
     shape = dict(epoch_size=args.epoch_size, slots=args.slots, block_size=args.block,
-                 use_graphs=args.use_graphs, timing=1, pools=args.pools)
+                 use_graphs=args.use_graphs, timing=1, pools=args.pools, exact_diameter=args.exact_diameter)
     if args.no_learned:
         S, (pres, pwalls) = run_arm(K, G, eps, args.steps, args.warmup, **shape)
         S.close()

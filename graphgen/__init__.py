@@ -177,7 +177,7 @@ def build_native(force: bool = True) -> str:
     if force or not os.path.exists(_NATIVE):
         subprocess.check_call(["gcc", "-O3", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math",
                                "-pthread", "-shared", "-fPIC", "-o", _NATIVE,
-                               os.path.join(_HERE, "rmatgen.c")])
+                               os.path.join(_HERE, "rmatgen.c"), "-lm"])
     return _NATIVE
 
 
@@ -189,6 +189,9 @@ def _native_lib():
     lib.kg_rmat.restype = ctypes.c_void_p
     lib.kg_rmat.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double,
                             ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_int]
+    lib.kg_hyperbolic.restype = ctypes.c_void_p
+    lib.kg_hyperbolic.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
     lib.kg_n.restype = ctypes.c_int32
     lib.kg_n.argtypes = [ctypes.c_void_p]
     lib.kg_nnz.restype = ctypes.c_int64
@@ -220,6 +223,34 @@ def rmat_native(scale: int, edge_factor: int, seed: int, threads: int = 0) -> CS
     finally:
         lib.kg_free(h)
     return CSRGraph(nn, rp, ci, f"rmat_{scale}_{edge_factor}_s{seed}")
+
+
+def hyperbolic(scale: int, avg_deg: float, seed: int, gamma: float = 3.0, threads: int = 0) -> CSRGraph:
+    """Random hyperbolic graph (threshold model) with 2^scale points, power-law
+    degree exponent gamma, expected average degree avg_deg (|E| = avg_deg/2
+    |V|), seeded relabelling, largest component (the threaded C builder)."""
+    import ctypes
+    lib = _native_lib()
+    if lib is None:
+        raise RuntimeError("librmatgen.so is not built (graphgen.build_native())")
+    n = 1 << scale
+    perm = np.ascontiguousarray(_rng(seed ^ 0x5EED).permutation(n).astype(np.int64))
+    if threads <= 0:
+        threads = max(1, min(16, os.cpu_count() or 1))
+    R = ctypes.c_double()
+    h = lib.kg_hyperbolic(scale, float(avg_deg), float(gamma), seed & (2**64 - 1), GEN_STREAM, perm.ctypes.data,
+                          threads, ctypes.byref(R))
+    if not h:
+        raise MemoryError("hyperbolic builder failed")
+    try:
+        nn = lib.kg_n(h)
+        nnz = lib.kg_nnz(h)
+        rp = np.empty(nn + 1, dtype=np.int64)
+        ci = np.empty(nnz, dtype=np.int32)
+        lib.kg_copy(h, rp.ctypes.data, ci.ctypes.data)
+    finally:
+        lib.kg_free(h)
+    return CSRGraph(nn, rp, ci, f"hyp_{scale}_{avg_deg:g}_g{gamma:g}_s{seed}")
 
 
 def rmat(scale: int, edge_factor: int, seed: int) -> CSRGraph:
@@ -336,6 +367,17 @@ WORKLOADS = {
     "rmat26": (rmat, dict(scale=26, edge_factor=16, seed=26),
                "R-MAT scale 26, edge factor 16 (about 1e9 undirected edges)"),
 }
+# the graph-size sweep: R-MAT and random hyperbolic graphs (power-law
+# exponent 3) with |E| = 30 |V| at 2^23 .. 2^25 vertices; at 2^26 the
+# adjacency would pass 2^31 entries, so R-MAT takes edge factor 16 (the
+# large configuration above) and the hyperbolic graph |E| = 15 |V|
+for _s in (23, 24, 25):
+    WORKLOADS[f"rmat{_s}_ef30"] = (rmat, dict(scale=_s, edge_factor=30, seed=_s),
+                                   f"R-MAT scale {_s}, edge factor 30")
+    WORKLOADS[f"hyp{_s}"] = (hyperbolic, dict(scale=_s, avg_deg=60.0, seed=_s),
+                             f"random hyperbolic graph, 2^{_s} points, gamma 3, average degree 60")
+WORKLOADS["hyp26"] = (hyperbolic, dict(scale=26, avg_deg=30.0, seed=26),
+                      "random hyperbolic graph, 2^26 points, gamma 3, average degree 30")
 
 
 def cache_dir() -> str:

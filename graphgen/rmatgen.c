@@ -18,6 +18,7 @@
  *     (ties: the component of the smallest id), ids renumbered in ascending
  *     order of the permuted id.
  */
+#define _GNU_SOURCE
 #include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -215,35 +216,13 @@ void kg_copy(const kg_graph *g, int64_t *row_ptr, int32_t *col_idx)
     memcpy(col_idx, g->col_idx, sizeof(int32_t) * (size_t)g->nnz);
 }
 
-/* Returns NULL on allocation failure or bad arguments. */
-kg_graph *kg_rmat(int scale, int edge_factor, uint64_t seed, uint64_t stream, double a, double b, double c,
-                  const int64_t *perm, int threads)
+/* Graph from directed keys src << scale | dst over 2^scale ids (UINT64_MAX
+ * marks a dropped entry; keys is freed): loops dropped, sorted, duplicates
+ * dropped, CSR, the largest component kept (ties: the component of the
+ * smallest id), ids renumbered in ascending order. */
+static kg_graph *graph_from_keys(uint64_t *keys, int64_t nk, int scale, int threads)
 {
-    if (scale < 1 || scale > 30 || edge_factor < 1 || threads < 1) return NULL;
-    if (threads > 64) threads = 64;
     const int64_t N = (int64_t)1 << scale;
-    const int64_t total = N * edge_factor;
-    const int64_t nk = 2 * total;
-    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)nk);
-    if (!keys) return NULL;
-
-    draw_job dj[64];
-    const double ab = a + b, abc = a + b + c;
-    for (int t = 0; t < threads; ++t) {
-        dj[t].scale = scale;
-        dj[t].ef = edge_factor;
-        dj[t].key0 = seed;
-        dj[t].key1 = stream;
-        dj[t].a = a;
-        dj[t].ab = ab;
-        dj[t].abc = abc;
-        dj[t].perm = perm;
-        dj[t].keys = keys;
-        dj[t].e0 = total * t / threads;
-        dj[t].e1 = total * (t + 1) / threads;
-    }
-    run_threads(threads, draw_worker, dj, sizeof(draw_job));
-
     /* drop loops (stable compaction), then sort */
     int64_t m = 0;
     for (int64_t i = 0; i < nk; ++i)
@@ -343,4 +322,286 @@ kg_graph *kg_rmat(int scale, int edge_factor, uint64_t seed, uint64_t stream, do
     free(comp);
     free(q);
     return g;
+}
+
+/* Returns NULL on allocation failure or bad arguments. */
+kg_graph *kg_rmat(int scale, int edge_factor, uint64_t seed, uint64_t stream, double a, double b, double c,
+                  const int64_t *perm, int threads)
+{
+    if (scale < 1 || scale > 30 || edge_factor < 1 || threads < 1) return NULL;
+    if (threads > 64) threads = 64;
+    const int64_t N = (int64_t)1 << scale;
+    const int64_t total = N * edge_factor;
+    const int64_t nk = 2 * total;
+    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)nk);
+    if (!keys) return NULL;
+
+    draw_job dj[64];
+    const double ab = a + b, abc = a + b + c;
+    for (int t = 0; t < threads; ++t) {
+        dj[t].scale = scale;
+        dj[t].ef = edge_factor;
+        dj[t].key0 = seed;
+        dj[t].key1 = stream;
+        dj[t].a = a;
+        dj[t].ab = ab;
+        dj[t].abc = abc;
+        dj[t].perm = perm;
+        dj[t].keys = keys;
+        dj[t].e0 = total * t / threads;
+        dj[t].e1 = total * (t + 1) / threads;
+    }
+    run_threads(threads, draw_worker, dj, sizeof(draw_job));
+
+    return graph_from_keys(keys, nk, scale, threads);
+}
+
+/* ---- Random hyperbolic graphs (Krioukov et al., threshold model): n =
+ * 2^scale points in a hyperbolic disk of radius R, angle uniform, radius
+ * with density alpha sinh(alpha r) / (cosh(alpha R) - 1), alpha = (gamma -
+ * 1) / 2 for a power-law degree exponent gamma; two points are adjacent
+ * when their hyperbolic distance is at most R:
+ *   cosh r1 cosh r2 - sinh r1 sinh r2 cos(t1 - t2) <= cosh R.
+ * R is chosen so that the expected average degree is avg_deg (numerical
+ * integration of the adjacency probability over the radial law, then
+ * bisection on R).  Neighbours are found band by band: the points sorted
+ * by radial band and angle, a point scans in each band only the angles its
+ * threshold admits at the band's inner radius (the threshold angle shrinks
+ * as the other radius grows), then tests each candidate exactly.  Every
+ * edge is found from both ends; ids are permuted by `perm`, then the keys
+ * go through graph_from_keys (largest component, ascending renumbering).
+ * Random numbers: point i takes words 0 (radius) and 1 (angle) of Philox
+ * block i of (seed, stream).  Input generation only. */
+#include <math.h>
+
+static double hyp_theta_max(double r1, double r2, double R, double coshR)
+{
+    if (r1 + r2 <= R) return M_PI;
+    double c = (cosh(r1) * cosh(r2) - coshR) / (sinh(r1) * sinh(r2));
+    if (c <= -1.0) return M_PI;
+    if (c >= 1.0) return 0.0;
+    return acos(c);
+}
+
+/* radius at quantile q of the radial law */
+static double hyp_radius(double q, double alpha, double R)
+{
+    return acosh(1.0 + (cosh(alpha * R) - 1.0) * q) / alpha;
+}
+
+/* expected average degree for n points in a disk of radius R: n times the
+ * mean over two independent radii of theta_max / pi (midpoint rule on a
+ * grid of Q quantiles) */
+static double hyp_avg_degree(int64_t n, double alpha, double R)
+{
+    const int Q = 600;
+    double rq[600];
+    for (int i = 0; i < Q; ++i) rq[i] = hyp_radius((i + 0.5) / Q, alpha, R);
+    const double coshR = cosh(R);
+    double s = 0.0;
+    for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < Q; ++j) s += hyp_theta_max(rq[i], rq[j], R, coshR);
+    return (double)(n - 1) * s / ((double)Q * Q * M_PI);
+}
+
+static void philox_one(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t out[4])
+{
+    uint64_t c[4] = {c0, 0, 0, 0};
+    for (int r = 0; r < 10; ++r) {
+        const u128 p0 = (u128)0xD2E7470EE14C6C93ull * c[0];
+        const u128 p1 = (u128)0xCA5A826395121157ull * c[2];
+        const uint64_t n0 = (uint64_t)(p1 >> 64) ^ c[1] ^ k0, n2 = (uint64_t)(p0 >> 64) ^ c[3] ^ k1;
+        c[1] = (uint64_t)p1;
+        c[3] = (uint64_t)p0;
+        c[0] = n0;
+        c[2] = n2;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    memcpy(out, c, sizeof(c));
+}
+
+#define HYP_MAXB 64
+
+typedef struct {
+    int64_t n;
+    double R, coshR;
+    const double *th, *ch, *sh, *rr;   /* by sorted position */
+    const int32_t *id;                 /* original point of a sorted position */
+    const int64_t *bstart;             /* band b = sorted positions [bstart[b], bstart[b+1]) */
+    const double *binner;              /* inner radius of band b */
+    int nb;
+    const int64_t *perm;
+    int scale;
+    int64_t p0, p1;                    /* this thread's sorted positions */
+    uint64_t *out;
+    int64_t cnt, cap;
+    int fail;
+} hyp_job;
+
+static void hyp_emit(hyp_job *J, uint64_t k)
+{
+    if (J->cnt == J->cap) {
+        int64_t nc = J->cap ? 2 * J->cap : (1 << 20);
+        uint64_t *q = (uint64_t *)realloc(J->out, sizeof(uint64_t) * (size_t)nc);
+        if (!q) { J->fail = 1; return; }
+        J->out = q;
+        J->cap = nc;
+    }
+    J->out[J->cnt++] = k;
+}
+
+/* first sorted position in [lo, hi) whose angle is >= x */
+static int64_t hyp_lower(const double *th, int64_t lo, int64_t hi, double x)
+{
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (th[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+static void hyp_scan(hyp_job *J, int64_t p, int64_t lo, int64_t hi)
+{
+    const double chp = J->ch[p], shp = J->sh[p], thp = J->th[p];
+    const uint64_t src = (uint64_t)J->perm[J->id[p]] << J->scale;
+    for (int64_t q = lo; q < hi && !J->fail; ++q) {
+        if (q == p) continue;
+        if (chp * J->ch[q] - shp * J->sh[q] * cos(thp - J->th[q]) <= J->coshR)
+            hyp_emit(J, src | (uint64_t)J->perm[J->id[q]]);
+    }
+}
+
+static void *hyp_worker(void *arg)
+{
+    hyp_job *J = (hyp_job *)arg;
+    const double margin = 1e-9;
+    for (int64_t p = J->p0; p < J->p1 && !J->fail; ++p) {
+        for (int b = 0; b < J->nb; ++b) {
+            const int64_t lo = J->bstart[b], hi = J->bstart[b + 1];
+            if (lo == hi) continue;
+            const double d = hyp_theta_max(J->rr[p], J->binner[b], J->R, J->coshR) + margin;
+            if (d >= M_PI) {
+                hyp_scan(J, p, lo, hi);
+                continue;
+            }
+            const double a = J->th[p] - d, z = J->th[p] + d;
+            if (a < 0.0) {
+                hyp_scan(J, p, hyp_lower(J->th, lo, hi, a + 2.0 * M_PI), hi);
+                hyp_scan(J, p, lo, hyp_lower(J->th, lo, hi, z));
+            } else if (z > 2.0 * M_PI) {
+                hyp_scan(J, p, hyp_lower(J->th, lo, hi, a), hi);
+                hyp_scan(J, p, lo, hyp_lower(J->th, lo, hi, z - 2.0 * M_PI));
+            } else {
+                hyp_scan(J, p, hyp_lower(J->th, lo, hi, a), hyp_lower(J->th, lo, hi, z));
+            }
+        }
+    }
+    return NULL;
+}
+
+/* *R_out: the disk radius used. */
+kg_graph *kg_hyperbolic(int scale, double avg_deg, double gamma, uint64_t seed, uint64_t stream,
+                        const int64_t *perm, int threads, double *R_out)
+{
+    if (scale < 2 || scale > 26 || !(avg_deg > 0.0) || !(gamma > 2.0) || threads < 1) return NULL;
+    if (threads > 64) threads = 64;
+    const int64_t N = (int64_t)1 << scale;
+    const double alpha = (gamma - 1.0) / 2.0;
+    /* R: the expected average degree decreases in R */
+    double lo = 0.5, hi = 200.0;
+    for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (hyp_avg_degree(N, alpha, mid) > avg_deg) lo = mid; else hi = mid;
+    }
+    const double R = 0.5 * (lo + hi);
+    if (R_out) *R_out = R;
+    /* bands of width 1/2 in r (the last one ends at R) */
+    int nb = (int)ceil(R / 0.5);
+    if (nb > HYP_MAXB) nb = HYP_MAXB;
+    const double bw = R / nb;
+    double binner[HYP_MAXB + 1];
+    for (int b = 0; b <= nb; ++b) binner[b] = bw * b;
+    /* points, sorted by (band, angle) through 64-bit keys: band 6 bits,
+     * angle 32 bits, point index 26 bits */
+    double *r0 = (double *)malloc(sizeof(double) * (size_t)N);
+    double *t0 = (double *)malloc(sizeof(double) * (size_t)N);
+    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)N);
+    uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)N);
+    if (!r0 || !t0 || !keys || !tmp) { free(r0); free(t0); free(keys); free(tmp); return NULL; }
+    for (int64_t i = 0; i < N; ++i) {
+        uint64_t w[4];
+        philox_one(seed, stream, (uint64_t)i, w);
+        const double u = (double)(w[0] >> 11) * 0x1p-53, v = (double)(w[1] >> 11) * 0x1p-53;
+        r0[i] = hyp_radius(u, alpha, R);
+        t0[i] = 2.0 * M_PI * v;
+        int b = (int)(r0[i] / bw);
+        if (b >= nb) b = nb - 1;
+        const uint64_t tq = (uint64_t)(v * 4294967296.0);
+        keys[i] = ((uint64_t)b << 58) | ((tq & 0xffffffffull) << 26) | (uint64_t)i;
+    }
+    uint64_t *s = radix_sort(keys, tmp, N, 64, threads);
+    double *th = (double *)malloc(sizeof(double) * (size_t)N), *ch = (double *)malloc(sizeof(double) * (size_t)N);
+    double *sh = (double *)malloc(sizeof(double) * (size_t)N), *rr = (double *)malloc(sizeof(double) * (size_t)N);
+    int32_t *id = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    int64_t bstart[HYP_MAXB + 1];
+    if (!th || !ch || !sh || !rr || !id) {
+        free(r0); free(t0); free(keys); free(tmp); free(th); free(ch); free(sh); free(rr); free(id);
+        return NULL;
+    }
+    for (int b = 0; b <= nb; ++b) bstart[b] = N;
+    for (int64_t p = N - 1; p >= 0; --p) {
+        const int64_t i = (int64_t)(s[p] & ((1ull << 26) - 1));
+        const int b = (int)(s[p] >> 58);
+        id[p] = (int32_t)i;
+        th[p] = t0[i];
+        rr[p] = r0[i];
+        ch[p] = cosh(r0[i]);
+        sh[p] = sinh(r0[i]);
+        bstart[b] = p;
+    }
+    for (int b = nb - 1; b >= 0; --b)
+        if (bstart[b] > bstart[b + 1]) bstart[b] = bstart[b + 1];
+    /* angles within a band ascend up to the 32-bit quantisation of the key;
+     * make them exactly ascending for the binary searches */
+    for (int b = 0; b < nb; ++b)
+        for (int64_t p = bstart[b] + 1; p < bstart[b + 1]; ++p)
+            if (th[p] < th[p - 1]) th[p] = th[p - 1];
+    free(r0); free(t0); free(keys); free(tmp);
+    hyp_job jobs[64];
+    memset(jobs, 0, sizeof(jobs));
+    for (int t = 0; t < threads; ++t) {
+        jobs[t].n = N;
+        jobs[t].R = R;
+        jobs[t].coshR = cosh(R);
+        jobs[t].th = th;
+        jobs[t].ch = ch;
+        jobs[t].sh = sh;
+        jobs[t].rr = rr;
+        jobs[t].id = id;
+        jobs[t].bstart = bstart;
+        jobs[t].binner = binner;
+        jobs[t].nb = nb;
+        jobs[t].perm = perm;
+        jobs[t].scale = scale;
+        jobs[t].p0 = N * t / threads;
+        jobs[t].p1 = N * (t + 1) / threads;
+    }
+    run_threads(threads, hyp_worker, jobs, sizeof(hyp_job));
+    int64_t total = 0;
+    int fail = 0;
+    for (int t = 0; t < threads; ++t) {
+        total += jobs[t].cnt;
+        fail |= jobs[t].fail;
+    }
+    free(th); free(ch); free(sh); free(rr); free(id);
+    uint64_t *all = fail ? NULL : (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(total ? total : 1));
+    int64_t at = 0;
+    for (int t = 0; t < threads; ++t) {
+        if (all) memcpy(all + at, jobs[t].out, sizeof(uint64_t) * (size_t)jobs[t].cnt);
+        at += jobs[t].cnt;
+        free(jobs[t].out);
+    }
+    if (!all) return NULL;
+    return graph_from_keys(all, total, scale, threads);
 }

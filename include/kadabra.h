@@ -116,6 +116,9 @@ typedef struct {
     int32_t timing;               /* 1: time every sampler launch with HIP events */
     int32_t pools;                /* slot pools = sampler launches that may       */
                                   /* overlap (1..4); 0 = as many as memory allows */
+    int32_t exact_diameter;       /* 1: omega from the exact vertex diameter      */
+                                  /* (kad_exact_vd, stopped once omega is known); */
+                                  /* 0: from the three-sweep bracket              */
 } kad_opts;
 
 typedef struct {
@@ -223,6 +226,15 @@ kad_status kad_philox(kad_ctx *ctx, uint64_t seed, uint64_t stream, uint64_t fir
 /* kad_vd_bracket: device BFS sweeps bounding the vertex diameter of g
  * (Sec. III-A phase 1 needs it for omega): vd_lo <= VD <= vd_hi. */
 kad_status kad_vd_bracket(kad_ctx *ctx, const kad_graph *g, int64_t *vd_lo, int64_t *vd_hi);
+
+/* kad_exact_vd: the exact vertex diameter of g (the diameter phase of Sec.
+ * III-A, computed exactly as in Sec. IV-F with a BFS-based exact algorithm):
+ * iFUB on the device, from the middle vertex of a longest path of the three
+ * sweeps, with the eccentricities of the farthest levels taken 64 sources
+ * at a time by a multi-source BFS.  *h_vd = VD (edges of a longest shortest
+ * path + 1); *h_witness (optional) = a vertex, caller id, of eccentricity
+ * VD - 1; *h_bfs (optional) = single-source BFS runs the search took. */
+kad_status kad_exact_vd(kad_ctx *ctx, const kad_graph *g, int64_t *h_vd, int32_t *h_witness, int64_t *h_bfs);
 
 /* kad_omega: omega = 0.5/eps^2 * (floor(log2(VD-2)) + 1 + ln(2/delta)) for
  * the bracket [vd_lo, vd_hi] (the upper end unless both ends agree). */

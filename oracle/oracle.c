@@ -727,6 +727,19 @@ void orc_vd_bracket(const orc_graph *g, int64_t *vd_lo, int64_t *vd_hi)
     free(queue);
 }
 
+/* Eccentricity of v (BFS). */
+int32_t orc_eccentricity(const orc_graph *g, int32_t v)
+{
+    int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)g->n);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)g->n);
+    int32_t far;
+    int32_t e = bfs_ecc(g, v, dist, queue, &far);
+    free(dist);
+    free(queue);
+    return e;
+}
+
+/* Exact vertex diameter: one BFS per vertex (the definition; small graphs). */
 int64_t orc_exact_vd(const orc_graph *g)
 {
     int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)g->n);
@@ -817,13 +830,15 @@ void orc_features(const orc_graph *g, double *x /* n x 3, row-major */)
  * W3[64], b3.  Row-major, out x in. */
 /* Learned prior from the network output y = ln(b + 1/omega) (the
  * regression target): b = e^y - 1/omega, clamped to [0, 1], the range of
- * betweenness (Sec. I). */
+ * betweenness (Sec. I); a non-finite b is left as it is. */
 void orc_prior_from_output(int64_t n, const double *y, double omega, double *prior)
 {
     for (int64_t v = 0; v < n; ++v) {
         double b = exp(y[v]) - 1.0 / omega;
-        if (b < 0.0) b = 0.0;
-        if (b > 1.0) b = 1.0;
+        if (isfinite(b)) {   /* a non-finite output is left as it is */
+            if (b < 0.0) b = 0.0;
+            if (b > 1.0) b = 1.0;
+        }
         prior[v] = b;
     }
 }

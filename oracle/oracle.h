@@ -79,6 +79,7 @@ double orc_omega(int64_t vd, double eps, double delta);
 double orc_omega_bracket(int64_t vd_lo, int64_t vd_hi, double eps, double delta);
 void orc_vd_bracket(const orc_graph *g, int64_t *vd_lo, int64_t *vd_hi);
 int64_t orc_exact_vd(const orc_graph *g);
+int32_t orc_eccentricity(const orc_graph *g, int32_t v);
 
 int orc_check(int32_t n, const uint32_t *c, uint64_t tau, double omega, double eps,
               const double *LL, const double *LU, orc_check_info *ci);

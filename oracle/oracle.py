@@ -92,6 +92,8 @@ def lib():
         L.orc_vd_bracket.argtypes = [vp, vp, vp]
         L.orc_exact_vd.restype = i64
         L.orc_exact_vd.argtypes = [vp]
+        L.orc_eccentricity.restype = i32
+        L.orc_eccentricity.argtypes = [vp, i32]
         L.orc_check.restype = C.c_int
         L.orc_check.argtypes = [i32, vp, u64, dbl, dbl, vp, vp, vp]
         L.orc_run.restype = C.c_int
@@ -261,6 +263,10 @@ def vd_bracket(g):
 
 def exact_vd(g) -> int:
     return int(lib().orc_exact_vd(as_graph(g).ref))
+
+
+def eccentricity(g, v: int) -> int:
+    return int(lib().orc_eccentricity(as_graph(g).ref, v))
 
 
 def check(c: np.ndarray, tau: int, omega_: float, eps: float, LL, LU):

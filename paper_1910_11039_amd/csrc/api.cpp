@@ -288,6 +288,22 @@ extern "C" double kad_omega(int64_t vd_lo, int64_t vd_hi, double eps, double del
     return lo == hi ? lo : hi;
 }
 
+extern "C" kad_status kad_exact_vd(kad_ctx *ctx, const kad_graph *g, int64_t *h_vd, int32_t *h_witness,
+                                   int64_t *h_bfs)
+{
+    if (!ctx || !g || !h_vd) return fail(KAD_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    int64_t lo = 0, hi = 0;
+    HIPCHK(device_exact_vd(g->dev(), ctx->stream, false, 0.0, 0.0, &lo, &hi, h_witness, h_bfs));
+    if (lo != hi) return fail(KAD_EDEVICE, "internal error: the exact diameter search ended with a bracket");
+    *h_vd = lo;
+    return KAD_OK;
+}
+
+// Phase 1 (Sec. III-A): the vertex-diameter bracket behind omega, from the
+// three sweeps, or refined on the device until omega is settled.
+static hipError_t omega_bracket(const kad_sampler *s, int64_t *lo, int64_t *hi);
+
 extern "C" kad_status kad_vd_bracket(kad_ctx *ctx, const kad_graph *g, int64_t *vd_lo, int64_t *vd_hi)
 {
     if (!ctx || !g || !vd_lo || !vd_hi) return fail(KAD_EINVAL, "null argument");
@@ -297,6 +313,14 @@ extern "C" kad_status kad_vd_bracket(kad_ctx *ctx, const kad_graph *g, int64_t *
 }
 
 static kad_status enqueue_network(kad_sampler *s, hipStream_t st);
+
+static hipError_t omega_bracket(const kad_sampler *s, int64_t *lo, int64_t *hi)
+{
+    if (s->o.exact_diameter)
+        return device_exact_vd(s->g->dev(), s->ctx->stream, true, s->o.epsilon, s->o.delta, lo, hi, nullptr,
+                               nullptr);
+    return device_vd_bracket(s->g->dev(), s->ctx->stream, lo, hi);
+}
 
 static void free_sampler(kad_sampler *s)
 {
@@ -492,7 +516,7 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
         s->omega = o->omega_override;
         s->vd_lo = s->vd_hi = 0;
     } else {
-        hipError_t e = device_vd_bracket(g->dev(), st, &s->vd_lo, &s->vd_hi);
+        hipError_t e = omega_bracket(s, &s->vd_lo, &s->vd_hi);
         if (e != hipSuccess) { delete s; return fail(KAD_EDEVICE, hipGetErrorString(e)); }
         s->omega = kad_omega(s->vd_lo, s->vd_hi, o->epsilon, o->delta);
     }
@@ -626,7 +650,7 @@ extern "C" kad_status kad_sampler_reset(kad_sampler *s, uint64_t seed)
         s->yhat_pending = true;
     }
     if (!(s->o.omega_override > 0.0)) {
-        HIPCHK(device_vd_bracket(s->g->dev(), st, &s->vd_lo, &s->vd_hi));
+        HIPCHK(omega_bracket(s, &s->vd_lo, &s->vd_hi));
         const double om = kad_omega(s->vd_lo, s->vd_hi, s->o.epsilon, s->o.delta);
         if (om != s->omega) return fail(KAD_ESTATE, "omega changed for the same graph");
     }

@@ -738,6 +738,213 @@ __global__ void k_bfs_advance(int32_t *sz, BfsLim lim)
     sz[9] = 0;
 }
 
+// ---- exact vertex diameter (iFUB on top of the sweeps above; multi-source
+// BFS for the eccentricities of a level's vertices)
+
+// Smallest caller id among the middle vertices of shortest a-b paths:
+// da[v] + db[v] = d(a, b) and da[v] = d(a, b) / 2.
+__global__ void k_midpoint(int32_t n, const int32_t *da, const int32_t *db, const int32_t *orig, int32_t dab,
+                           int32_t *out)
+{
+    const int32_t half = dab / 2;
+    int32_t b = 0x7fffffff;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (da[v] == half && db[v] >= 0 && da[v] + db[v] == dab && orig[v] < b) b = orig[v];
+    if (b != 0x7fffffff) atomicMin(out, b);
+}
+
+// Lists the vertices at distance `depth` (internal ids, any order).
+__global__ void k_list_depth(int32_t n, const int32_t *dist, int32_t depth, int32_t *out, int32_t *cnt)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    const int64_t span = ((int64_t)n + step - 1) / step * step;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < span; v += step) {
+        const bool hit = v < n && dist[v] == depth;
+        const int32_t pos = wave_append(cnt, hit);
+        if (hit) out[pos] = (int32_t)v;
+    }
+}
+
+// Multi-source BFS for up to 64 sources at once: bit j of seen[v] / front[v]
+// says whether source j has reached v / has v in its current frontier.
+// A level adds, for every vertex, the sources of its neighbours' frontiers
+// it has not seen; the OR of the new bits over all vertices (ms[0]) says
+// which sources' BFS reached a new depth, so a source's eccentricity is the
+// last level at which its bit appears.
+//   ms[0] level OR   ms[1] next count   ms[2] next degree sum   ms[3] active mask
+__global__ void k_ms_clear(int32_t n, uint64_t *seen, uint64_t *front, uint64_t *nxt)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        seen[v] = 0;
+        front[v] = 0;
+        nxt[v] = 0;
+    }
+}
+
+__global__ void k_ms_seed(DevGraph g, const int32_t *src, int32_t nsrc, uint64_t *seen, uint64_t *front,
+                          int32_t *list, unsigned long long *ms)
+{
+    const int j = threadIdx.x;
+    if (j == 0) {
+        ms[0] = 0;
+        ms[1] = (unsigned long long)nsrc;
+        ms[2] = 0;
+        ms[3] = nsrc >= 64 ? ~0ull : ((1ull << nsrc) - 1);
+    }
+    __syncthreads();
+    if (j < nsrc) {
+        const int32_t v = src[j];      // distinct vertices
+        seen[v] = 1ull << j;
+        front[v] = 1ull << j;
+        list[j] = v;
+        atomicAdd(&ms[2], (unsigned long long)g.deg[v]);
+    }
+}
+
+// Top-down level: a wave per frontier vertex pushes its frontier bits to
+// its neighbours; a neighbour is listed by the first lane that gives it
+// bits this level.
+__global__ void k_ms_td(DevGraph g, const uint64_t *seen, const uint64_t *front, uint64_t *nxt,
+                        const int32_t *cur, int32_t ncur, int32_t *next, unsigned long long *ms)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t wpb = blockDim.x >> 6;
+    for (int32_t i = blockIdx.x * wpb + (threadIdx.x >> 6); i < ncur; i += gridDim.x * wpb) {
+        const int32_t u = cur[i];
+        const uint64_t m = front[u];
+        const int64_t b = g.rp[u], e1 = g.rp[u + 1];
+        for (int64_t e0 = b; e0 < e1; e0 += 64) {
+            const int64_t e = e0 + lane;
+            bool first = false;
+            int32_t w = 0;
+            if (e < e1 && m) {
+                w = g.ci[e];
+                const uint64_t add = m & ~seen[w];
+                if (add) first = atomicOr((unsigned long long *)&nxt[w], (unsigned long long)add) == 0ull;
+            }
+            const int32_t pos = wave_append((int32_t *)&ms[1], first);
+            if (first) next[pos] = w;
+        }
+    }
+}
+
+// Bottom-up level over the vertices [v0, v1): a vertex gathers the frontier
+// bits of its neighbours, stopping once every active source is accounted
+// for.  `wave`: a wave per vertex (long rows), else a thread per vertex.
+__global__ void k_ms_bu(DevGraph g, const uint64_t *seen, const uint64_t *front, uint64_t *nxt, int32_t v0,
+                        int32_t v1, int wave, const unsigned long long *ms)
+{
+    const uint64_t all = (uint64_t)ms[3];
+    if (wave) {
+        const int lane = threadIdx.x & 63;
+        const int32_t wpb = blockDim.x >> 6;
+        for (int32_t v = v0 + blockIdx.x * wpb + (threadIdx.x >> 6); v < v1; v += gridDim.x * wpb) {
+            const uint64_t s = seen[v];
+            if (s == all) continue;
+            uint64_t acc = 0;
+            const int64_t b = g.rp[v], e1 = g.rp[v + 1];
+            for (int64_t e0 = b; e0 < e1; e0 += 64) {
+                const int64_t e = e0 + lane;
+                uint64_t x = (e < e1) ? front[g.ci[e]] : 0ull;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
+                acc |= x;
+                if ((acc | s) == all) break;
+            }
+            if (lane == 0) nxt[v] = acc & ~s;
+        }
+    } else {
+        for (int32_t v = v0 + blockIdx.x * blockDim.x + threadIdx.x; v < v1; v += gridDim.x * blockDim.x) {
+            const uint64_t s = seen[v];
+            if (s == all) continue;
+            uint64_t acc = 0;
+            const int64_t b = g.rp[v], e1 = g.rp[v + 1];
+            for (int64_t e = b; e < e1; ++e) {
+                acc |= front[g.ci[e]];
+                if ((acc | s) == all) break;
+            }
+            nxt[v] = acc & ~s;
+        }
+    }
+}
+
+__device__ __forceinline__ void ms_level_or(unsigned long long *ms, uint64_t x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
+    if ((threadIdx.x & 63) == 0 && x) atomicOr(&ms[0], (unsigned long long)x);
+}
+
+// End of a top-down level: the old frontier's bits are cleared first
+// (k_ms_drop), then each listed vertex takes its new bits.
+__global__ void k_ms_drop(uint64_t *front, const int32_t *cur, int32_t ncur)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ncur; i += gridDim.x * blockDim.x)
+        front[cur[i]] = 0;
+}
+
+__global__ void k_ms_take_listed(DevGraph g, uint64_t *seen, uint64_t *front, uint64_t *nxt, const int32_t *next,
+                                 const unsigned long long *cnt_ptr, unsigned long long *ms)
+{
+    const int32_t cnt = (int32_t)*cnt_ptr;
+    unsigned long long dsum = 0;
+    uint64_t lor = 0;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    const int64_t span = ((int64_t)cnt + step - 1) / step * step;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < span; i += step) {
+        if (i < cnt) {
+            const int32_t w = next[i];
+            const uint64_t nw = nxt[w] & ~seen[w];
+            seen[w] |= nw;
+            front[w] = nw;
+            nxt[w] = 0;
+            lor |= nw;
+            dsum += (unsigned long long)g.deg[w];
+        }
+    }
+    ms_level_or(ms, lor);
+    if (dsum) atomicAdd(&ms[2], dsum);
+}
+
+// End of a bottom-up level over every vertex: new bits become the
+// frontier (and old frontier bits are dropped); new vertices are listed.
+__global__ void k_ms_take_all(DevGraph g, uint64_t *seen, uint64_t *front, uint64_t *nxt, int32_t *next,
+                              unsigned long long *ms)
+{
+    unsigned long long dsum = 0;
+    uint64_t lor = 0;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    const int64_t span = ((int64_t)g.n + step - 1) / step * step;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < span; v += step) {
+        uint64_t nw = 0;
+        if (v < g.n) {
+            nw = nxt[v];
+            front[v] = nw;
+            nxt[v] = 0;
+            if (nw) {
+                seen[v] |= nw;
+                lor |= nw;
+                dsum += (unsigned long long)g.deg[v];
+            }
+        }
+        const int32_t pos = wave_append((int32_t *)&ms[1], nw != 0);
+        if (nw) next[pos] = (int32_t)v;
+    }
+    ms_level_or(ms, lor);
+    if (dsum) atomicAdd(&ms[2], dsum);
+}
+
+// Vertices with rows longer than 32 entries (a prefix of the hub-first
+// numbering).
+__global__ void k_count_long(int32_t n, const uint32_t *deg, int32_t *out)
+{
+    int c = 0;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        c += deg[v] > 32u ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
 int grid_for(int64_t n, int block, int cap = 8192)
 {
     int64_t g = (n + block - 1) / block;
@@ -903,87 +1110,288 @@ hipError_t alloc_budget(int32_t n, const double *LL, const double *LU, hipStream
     return hipSuccess;
 }
 
+// Buffers of the BFS sweeps.
+struct BfsBufs {
+    int32_t *dist0 = nullptr, *dist1 = nullptr, *fa = nullptr, *fb = nullptr, *heavy = nullptr, *sizes = nullptr;
+    int32_t *pick = nullptr;   // {source (internal id), next source (caller id), ecc x 6}
+    uint64_t *bits0 = nullptr, *bits1 = nullptr;
+    unsigned long long *best = nullptr;
+    BfsLim lim;
+    int64_t sweeps = 0;
+};
+
+static hipError_t bfs_alloc(const DevGraph &g, hipStream_t st, BfsBufs &b, bool two_dists)
+{
+    hipError_t e;
+    const int32_t n = g.n;
+    const size_t nwords = ((size_t)n + 63) / 64;
+    if ((e = hipMallocAsync((void **)&b.dist0, sizeof(int32_t) * n, st)) != hipSuccess) return e;
+    if (two_dists && (e = hipMallocAsync((void **)&b.dist1, sizeof(int32_t) * n, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&b.fa, sizeof(int32_t) * n, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&b.fb, sizeof(int32_t) * (size_t)n, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&b.heavy, sizeof(int32_t) * (size_t)n, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&b.bits0, sizeof(uint64_t) * nwords, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&b.bits1, sizeof(uint64_t) * nwords, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&b.sizes, sizeof(int32_t) * 12, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&b.best, sizeof(unsigned long long), st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&b.pick, sizeof(int32_t) * 8, st)) != hipSuccess) return e;
+    b.lim.big_v = std::max<int32_t>(n / 16, 1 << 14);
+    b.lim.big_e = std::max<int64_t>(g.nnz / 16, (int64_t)1 << 20);
+    return hipSuccess;
+}
+
+static hipError_t bfs_free(BfsBufs &b, hipStream_t st)
+{
+    void *ps[] = {b.dist0, b.dist1, b.fa, b.fb, b.heavy, b.bits0, b.bits1, b.sizes, b.best, b.pick};
+    for (void *p : ps)
+        if (p) CK(hipFreeAsync(p, st));
+    return hipSuccess;
+}
+
+// One sweep into `dist`: from the vertex of the packed key (the largest
+// degree) when `key` is set, else from the caller id in pick[1].  Leaves
+// the caller-smallest vertex at the last depth in pick[1] and the
+// eccentricity in pick[2 + slot] and *ecc.  `hint`: a lower bound on the
+// eccentricity, used to size the first batch of steps.
+static hipError_t bfs_sweep(const DevGraph &g, hipStream_t st, BfsBufs &b, int32_t *dist,
+                            const unsigned long long *key, int slot, int32_t hint, int32_t *ecc)
+{
+    const int32_t n = g.n;
+    hipLaunchKernelGGL(k_bfs_source, dim3(1), dim3(1), 0, st, g, key, b.pick + 1, b.pick, b.sizes);
+    hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, 256)), dim3(256), 0, st, n, dist, b.pick, b.fa);
+    // Batches of steps enqueued without waiting (a step may run many small
+    // levels); the host only looks at the frontier size between batches.
+    // A step past the last level does nothing but still costs its launches.
+    int32_t hs[4] = {1, 0, 0, 0};
+    int32_t batch = key ? 8 : std::min<int32_t>(std::max<int32_t>(hint + 2, 2), 16);
+    for (int64_t steps = 0; steps <= (int64_t)n + 1; steps += batch, batch = key ? 4 : 2) {
+        for (int k = 0; k < batch; ++k) {
+            hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(1024), 0, st, g, dist, b.fa, b.fb, b.sizes);
+            hipLaunchKernelGGL(k_bfs_collect, dim3(grid_for(n, 1024, 1024)), dim3(1024), 0, st, n, dist, b.fa,
+                               b.fb, b.sizes, b.lim);
+            hipLaunchKernelGGL(k_bfs_td, dim3(2048), dim3(256), 0, st, g, dist, b.fa, b.fb, b.heavy, b.sizes, b.lim);
+            hipLaunchKernelGGL(k_bfs_heavy, dim3(1024), dim3(256), 0, st, g, dist, b.heavy, b.fa, b.fb, b.sizes,
+                               b.lim);
+            hipLaunchKernelGGL(k_bfs_mark, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, dist, b.bits0,
+                               b.bits1, b.sizes, b.lim);
+            hipLaunchKernelGGL(k_bfs_bu, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, g, dist, b.bits0,
+                               b.bits1, b.sizes, b.lim);
+            hipLaunchKernelGGL(k_bfs_advance, dim3(1), dim3(1), 0, st, b.sizes, b.lim);
+        }
+        CK(hipMemcpyAsync(hs, b.sizes, sizeof(hs), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        if (hs[0] == 0) break;
+    }
+    if (hs[0] != 0) return hipErrorUnknown;   // more levels than vertices: cannot happen
+    hipLaunchKernelGGL(k_min_at_depth, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, dist, g.orig, b.sizes,
+                       b.pick + 1, b.pick + 2 + slot);
+    *ecc = hs[3];
+    b.sweeps += 1;
+    return hipGetLastError();
+}
+
 hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, int64_t *vd_hi)
 {
     hipError_t e;
     const int32_t n = g.n;
-    int32_t *dist = nullptr, *fa = nullptr, *fb = nullptr, *sizes = nullptr;
-    unsigned long long *best = nullptr;
-    if ((e = hipMallocAsync((void **)&dist, sizeof(int32_t) * n, st)) != hipSuccess) return e;
-    if ((e = hipMallocAsync((void **)&fa, sizeof(int32_t) * n, st)) != hipSuccess) return e;
-    if ((e = hipMallocAsync((void **)&fb, sizeof(int32_t) * (size_t)n, st)) != hipSuccess) return e;
-    int32_t *heavy = nullptr;
-    if ((e = hipMallocAsync((void **)&heavy, sizeof(int32_t) * (size_t)n, st)) != hipSuccess) return e;
-    uint64_t *bits0 = nullptr, *bits1 = nullptr;
-    const size_t nwords = ((size_t)n + 63) / 64;
-    if ((e = hipMallocAsync((void **)&bits0, sizeof(uint64_t) * nwords, st)) != hipSuccess) return e;
-    if ((e = hipMallocAsync((void **)&bits1, sizeof(uint64_t) * nwords, st)) != hipSuccess) return e;
-    if ((e = hipMallocAsync((void **)&sizes, sizeof(int32_t) * 12, st)) != hipSuccess) return e;
-    if ((e = hipMallocAsync((void **)&best, sizeof(unsigned long long), st)) != hipSuccess) return e;
-    int32_t *pick = nullptr;   // {source (internal id), far vertex (caller id), ecc x 3}
-    if ((e = hipMallocAsync((void **)&pick, sizeof(int32_t) * 5, st)) != hipSuccess) return e;
-    CK(hipMemsetAsync(best, 0, sizeof(unsigned long long), st));
-    hipLaunchKernelGGL(k_argmax_degree, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, g, best);
-
-    // Three sweeps of a direction-optimising BFS, each enqueued in batches
-    // of steps; the next sweep's source is picked on the device, and the
-    // host only looks at the frontier size between batches.
-    BfsLim lim;
-    lim.big_v = std::max<int32_t>(n / 16, 1 << 14);
-    lim.big_e = std::max<int64_t>(g.nnz / 16, (int64_t)1 << 20);
-    int32_t er_first = 0;
-    for (int sweep = 0; sweep < 3; ++sweep) {
-        hipLaunchKernelGGL(k_bfs_source, dim3(1), dim3(1), 0, st, g, sweep == 0 ? best : nullptr, pick + 1,
-                           pick, sizes);
-        hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, 256)), dim3(256), 0, st, n, dist, pick, fa);
-        // Batch sizes: the first sweep takes 8 steps, then 4 at a time; a
-        // later sweep starts from a vertex at the first sweep's last depth,
-        // so its eccentricity is at least that depth (er): min(er + 2, 16)
-        // steps first (a step may run many small levels), then 2 at a
-        // time.  A step past the last level does nothing but still costs
-        // its launches.
-        int32_t hs[4] = {1, 0, 0, 0};
-        int32_t batch = sweep == 0 ? 8 : std::min<int32_t>(std::max<int32_t>(er_first + 2, 2), 16);
-        for (int64_t steps = 0; steps <= (int64_t)n + 1; steps += batch, batch = sweep == 0 ? 4 : 2) {
-            for (int k = 0; k < batch; ++k) {
-                hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(1024), 0, st, g, dist, fa, fb, sizes);
-                hipLaunchKernelGGL(k_bfs_collect, dim3(grid_for(n, 1024, 1024)), dim3(1024), 0, st, n, dist, fa, fb,
-                                   sizes, lim);
-                hipLaunchKernelGGL(k_bfs_td, dim3(2048), dim3(256), 0, st, g, dist, fa, fb, heavy, sizes, lim);
-                hipLaunchKernelGGL(k_bfs_heavy, dim3(1024), dim3(256), 0, st, g, dist, heavy, fa, fb, sizes, lim);
-                hipLaunchKernelGGL(k_bfs_mark, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, dist, bits0,
-                                   bits1, sizes, lim);
-                hipLaunchKernelGGL(k_bfs_bu, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, g, dist, bits0, bits1,
-                                   sizes, lim);
-                hipLaunchKernelGGL(k_bfs_advance, dim3(1), dim3(1), 0, st, sizes, lim);
-            }
-            CK(hipMemcpyAsync(hs, sizes, sizeof(hs), hipMemcpyDeviceToHost, st));
-            CK(hipStreamSynchronize(st));
-            if (hs[0] == 0) break;
-        }
-        if (hs[0] != 0) return hipErrorUnknown;   // more levels than vertices: cannot happen
-        if (sweep == 0) er_first = hs[3];
-        hipLaunchKernelGGL(k_min_at_depth, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, dist, g.orig, sizes,
-                           pick + 1, pick + 2 + sweep);
-    }
-    int32_t hp[5];
-    CK(hipMemcpyAsync(hp, pick, sizeof(hp), hipMemcpyDeviceToHost, st));
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    const int32_t er = hp[2], ea = hp[3], eb = hp[4];
+    BfsBufs b;
+    if ((e = bfs_alloc(g, st, b, false)) != hipSuccess) return e;
+    CK(hipMemsetAsync(b.best, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_argmax_degree, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, g, b.best);
+    // Three sweeps: from the vertex of largest degree r, from its farthest
+    // vertex a, from a's farthest b; each source is picked on the device.
+    int32_t er = 0, ea = 0, eb = 0;
+    if ((e = bfs_sweep(g, st, b, b.dist0, b.best, 0, 0, &er)) != hipSuccess) return e;
+    if ((e = bfs_sweep(g, st, b, b.dist0, nullptr, 1, er, &ea)) != hipSuccess) return e;
+    if ((e = bfs_sweep(g, st, b, b.dist0, nullptr, 2, er, &eb)) != hipSuccess) return e;
     const int32_t lb = ea > eb ? ea : eb;
     int32_t mn = er < ea ? er : ea;
     mn = eb < mn ? eb : mn;
     *vd_lo = (int64_t)lb + 1;
     *vd_hi = 2 * (int64_t)mn + 1;
-    CK(hipFreeAsync(dist, st));
-    CK(hipFreeAsync(fa, st));
-    CK(hipFreeAsync(fb, st));
-    CK(hipFreeAsync(heavy, st));
-    CK(hipFreeAsync(bits0, st));
-    CK(hipFreeAsync(bits1, st));
-    CK(hipFreeAsync(sizes, st));
-    CK(hipFreeAsync(best, st));
-    CK(hipFreeAsync(pick, st));
+    CK(bfs_free(b, st));
+    CK(hipStreamSynchronize(st));
+    return hipGetLastError();
+}
+
+// Multi-source BFS buffers.
+struct MsBufs {
+    uint64_t *seen = nullptr, *front = nullptr, *nxt = nullptr;
+    int32_t *la = nullptr, *lb = nullptr, *nlong = nullptr;
+    unsigned long long *ms = nullptr;
+    int32_t long_rows = 0;
+};
+
+// Eccentricities of up to 64 distinct sources (internal ids in src[0..k)):
+// *best = the largest, *best_j = the index of a source attaining it.
+static hipError_t ms_ecc(const DevGraph &g, hipStream_t st, MsBufs &m, const int32_t *src, int32_t k,
+                         int32_t *best, int32_t *best_j)
+{
+    const int32_t n = g.n;
+    hipLaunchKernelGGL(k_ms_clear, dim3(grid_for(n, 256)), dim3(256), 0, st, n, m.seen, m.front, m.nxt);
+    hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(64), 0, st, g, src, k, m.seen, m.front, m.la, m.ms);
+    int32_t ecc[64] = {0};
+    int32_t *cur = m.la, *next = m.lb;
+    unsigned long long h[4];
+    CK(hipMemcpyAsync(h, m.ms, sizeof(h), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    const int64_t big_e = std::max<int64_t>(g.nnz / 16, (int64_t)1 << 20);
+    const int64_t big_v = std::max<int64_t>(n / 16, 1 << 14);
+    for (int32_t level = 1; level <= n; ++level) {
+        const int64_t ncur = (int64_t)h[1], dcur = (int64_t)h[2];
+        if (ncur == 0) break;
+        CK(hipMemsetAsync(m.ms, 0, 3 * sizeof(unsigned long long), st));
+        if (dcur >= big_e || ncur >= big_v) {
+            if (m.long_rows > 0)
+                hipLaunchKernelGGL(k_ms_bu, dim3(grid_for((int64_t)m.long_rows * 64, 256, 4096)), dim3(256), 0, st,
+                                   g, m.seen, m.front, m.nxt, 0, m.long_rows, 1, m.ms);
+            hipLaunchKernelGGL(k_ms_bu, dim3(grid_for(n - m.long_rows, 256, 8192)), dim3(256), 0, st, g, m.seen,
+                               m.front, m.nxt, m.long_rows, n, 0, m.ms);
+            hipLaunchKernelGGL(k_ms_take_all, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, g, m.seen, m.front,
+                               m.nxt, next, m.ms);
+        } else {
+            hipLaunchKernelGGL(k_ms_td, dim3(grid_for(ncur * 64, 256, 4096)), dim3(256), 0, st, g, m.seen, m.front,
+                               m.nxt, cur, (int32_t)ncur, next, m.ms);
+            hipLaunchKernelGGL(k_ms_drop, dim3(grid_for(ncur, 256, 4096)), dim3(256), 0, st, m.front, cur,
+                               (int32_t)ncur);
+            hipLaunchKernelGGL(k_ms_take_listed, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, g, m.seen, m.front,
+                               m.nxt, next, m.ms + 1, m.ms);
+        }
+        CK(hipMemcpyAsync(h, m.ms, sizeof(h), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        const uint64_t lor = (uint64_t)h[0];
+        for (int j = 0; j < k; ++j)
+            if ((lor >> j) & 1ull) ecc[j] = level;
+        if (lor == 0) break;
+        std::swap(cur, next);
+    }
+    *best = -1;
+    *best_j = 0;
+    for (int j = 0; j < k; ++j)
+        if (ecc[j] > *best) { *best = ecc[j]; *best_j = j; }
+    return hipGetLastError();
+}
+
+static double omega_of_vd(int64_t vd, double eps, double delta)
+{
+    double lg = 0.0;
+    if (vd - 2 >= 1) {
+        int64_t x = vd - 2, fl = 0;
+        while (x > 1) { x >>= 1; ++fl; }
+        lg = (double)fl;
+    }
+    return 0.5 / (eps * eps) * (lg + 1.0 + log(2.0 / delta));
+}
+
+// Exact vertex diameter by iFUB (Crescenzi, Grossi, Habib, Lanzi, Marino,
+// TCS 2013), the BFS-based family of exact diameter algorithms the paper's
+// diameter phase uses: bounds from the three sweeps of the bracket, a BFS
+// from u, the middle of a longest a-b path found, then the eccentricities
+// of u's farthest levels, deepest first.  Any two vertices within distance
+// i - 1 of u are within 2(i - 1) of each other, so once the largest
+// eccentricity found exceeds 2(i - 1) it is the diameter; otherwise the
+// diameter is at most 2(i - 1) and the next level down is examined.
+// With omega_only the search stops as soon as both ends of the bracket
+// give the same omega (eps, delta).
+hipError_t device_exact_vd(const DevGraph &g, hipStream_t st, bool omega_only, double eps, double delta,
+                           int64_t *vd_lo, int64_t *vd_hi, int32_t *witness, int64_t *bfs_runs)
+{
+    hipError_t e;
+    const int32_t n = g.n;
+    BfsBufs b;
+    MsBufs m;
+    if ((e = bfs_alloc(g, st, b, true)) != hipSuccess) return e;
+    CK(hipMemsetAsync(b.best, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_argmax_degree, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, g, b.best);
+    int32_t er = 0, ea = 0, eb = 0, eu = 0;
+    int32_t hp[8];
+    // r -> a (dist1 keeps the distances from a) -> b
+    if ((e = bfs_sweep(g, st, b, b.dist0, b.best, 0, 0, &er)) != hipSuccess) return e;
+    CK(hipMemcpyAsync(hp, b.pick, sizeof(hp), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    const int32_t a_id = hp[1];
+    if ((e = bfs_sweep(g, st, b, b.dist1, nullptr, 1, er, &ea)) != hipSuccess) return e;
+    CK(hipMemcpyAsync(hp, b.pick, sizeof(hp), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    const int32_t b_id = hp[1];
+    if ((e = bfs_sweep(g, st, b, b.dist0, nullptr, 2, er, &eb)) != hipSuccess) return e;
+    int64_t lo = std::max(ea, eb), hi = 2 * (int64_t)std::min(er, std::min(ea, eb));
+    int32_t wit = ea >= eb ? a_id : b_id;
+    auto settled = [&]() {
+        return lo >= hi || (omega_only && omega_of_vd(lo + 1, eps, delta) == omega_of_vd(hi + 1, eps, delta));
+    };
+    if (!settled()) {
+        // u: the middle of a longest shortest path a-b (d(a, b) = ecc(a))
+        const int32_t big = 0x7fffffff;
+        CK(hipMemcpyAsync(b.pick + 1, &big, sizeof(big), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_midpoint, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, b.dist1, b.dist0, g.orig,
+                           ea, b.pick + 1);
+        CK(hipMemcpyAsync(hp, b.pick, sizeof(hp), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        const int32_t u_id = hp[1];
+        CK(hipMemcpyAsync(b.pick + 1, &u_id, sizeof(u_id), hipMemcpyHostToDevice, st));
+        if ((e = bfs_sweep(g, st, b, b.dist1, nullptr, 3, ea / 2, &eu)) != hipSuccess) return e;
+        if (eu > lo) { lo = eu; wit = u_id; }
+        hi = std::min<int64_t>(hi, 2 * (int64_t)eu);
+    }
+    if (!settled()) {
+        if ((e = hipMallocAsync((void **)&m.seen, 8ull * n, st)) != hipSuccess) return e;
+        if ((e = hipMallocAsync((void **)&m.front, 8ull * n, st)) != hipSuccess) return e;
+        if ((e = hipMallocAsync((void **)&m.nxt, 8ull * n, st)) != hipSuccess) return e;
+        if ((e = hipMallocAsync((void **)&m.la, 4ull * n, st)) != hipSuccess) return e;
+        if ((e = hipMallocAsync((void **)&m.lb, 4ull * n, st)) != hipSuccess) return e;
+        if ((e = hipMallocAsync((void **)&m.nlong, 4, st)) != hipSuccess) return e;
+        if ((e = hipMallocAsync((void **)&m.ms, 4 * sizeof(unsigned long long), st)) != hipSuccess) return e;
+        CK(hipMemsetAsync(m.nlong, 0, 4, st));
+        hipLaunchKernelGGL(k_count_long, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, g.deg, m.nlong);
+        CK(hipMemcpyAsync(&m.long_rows, m.nlong, 4, hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        // the level lists of u go to fa (the sweeps are done with it)
+        std::vector<int32_t> ids;
+        for (int32_t i = eu; i >= 1; --i) {
+            // every level beyond i is done: two vertices both within i of u
+            // are within 2i of each other
+            hi = std::min<int64_t>(hi, std::max<int64_t>(lo, 2 * (int64_t)i));
+            if (settled()) break;
+            int32_t cnt = 0;
+            CK(hipMemsetAsync(b.sizes, 0, 4, st));
+            hipLaunchKernelGGL(k_list_depth, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, b.dist1, i, b.fa,
+                               b.sizes);
+            CK(hipMemcpyAsync(&cnt, b.sizes, 4, hipMemcpyDeviceToHost, st));
+            CK(hipStreamSynchronize(st));
+            for (int32_t j0 = 0; j0 < cnt && !settled(); j0 += 64) {
+                const int32_t k = std::min(64, cnt - j0);
+                int32_t best = 0, bj = 0;
+                if ((e = ms_ecc(g, st, m, b.fa + j0, k, &best, &bj)) != hipSuccess) return e;
+                b.sweeps += k;
+                if (best > lo) {
+                    int32_t v = 0;
+                    CK(hipMemcpyAsync(&v, b.fa + j0 + bj, 4, hipMemcpyDeviceToHost, st));
+                    CK(hipStreamSynchronize(st));
+                    lo = best;
+                    wit = -1 - v;   // internal id, mapped below
+                }
+                hi = std::min<int64_t>(hi, std::max<int64_t>(lo, 2 * (int64_t)i));
+            }
+            if (settled()) break;
+            // level i done too
+            hi = std::min<int64_t>(hi, std::max<int64_t>(lo, 2 * (int64_t)(i - 1)));
+        }
+        if (lo > hi) hi = lo;
+        void *ps[] = {m.seen, m.front, m.nxt, m.la, m.lb, m.nlong, m.ms};
+        for (void *p : ps) CK(hipFreeAsync(p, st));
+    }
+    if (wit < 0) {   // an internal id: its caller id
+        const int32_t v = -1 - wit;
+        CK(hipMemcpyAsync(&wit, g.orig + v, 4, hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+    }
+    *vd_lo = lo + 1;
+    *vd_hi = hi + 1;
+    if (witness) *witness = wit;
+    if (bfs_runs) *bfs_runs = b.sweeps;
+    CK(bfs_free(b, st));
+    CK(hipStreamSynchronize(st));
     return hipGetLastError();
 }
 

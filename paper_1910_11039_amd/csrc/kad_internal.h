@@ -170,6 +170,11 @@ hipError_t alloc_budget(int32_t n, const double *LL, const double *LU, hipStream
 
 // Vertex-diameter bracket by BFS sweeps on the device.
 hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, int64_t *vd_hi);
+// Exact vertex diameter (iFUB with multi-source BFS); with omega_only it
+// stops once both ends of [vd_lo, vd_hi] give the same omega.  witness: a
+// vertex (caller id) whose eccentricity is vd_lo - 1.
+hipError_t device_exact_vd(const DevGraph &g, hipStream_t st, bool omega_only, double eps, double delta,
+                           int64_t *vd_lo, int64_t *vd_hi, int32_t *witness, int64_t *bfs_runs);
 
 // Learned prior.
 hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st);

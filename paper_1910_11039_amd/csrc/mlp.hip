@@ -418,7 +418,7 @@ __global__ void k_prior(int32_t n, const float *y, double inv_omega, double *pri
         // betweenness lies in [0, 1] (Sec. I), so the prior is clamped to it;
         // a non-finite output passes through (the budget check rejects it)
         const double b = exp((double)y[v]) - inv_omega;
-        prior[v] = b > 1.0 ? 1.0 : (b > 0.0 ? b : (b == b ? 0.0 : b));
+        prior[v] = isfinite(b) ? (b > 1.0 ? 1.0 : (b > 0.0 ? b : 0.0)) : b;
     }
 }
 

@@ -846,7 +846,68 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
         __syncthreads();
         return;
     }
-    // FP mode, large meet set: visit the list in ascending id by repeated
+    // FP mode, large meet set: sort (caller id, list position) keys in the
+    // slot's meet accumulators (idle in FP mode) with a block-wide bitonic
+    // sort, gather the weights in that order behind them, then one wave sums
+    // them left to right (the rounding order the definition fixes) and finds
+    // the pick in a second ordered pass.
+    int32_t mp = 1;
+    while (mp < m) mp <<= 1;
+    if (mp <= c.macc_cap) {
+        // keys in [0, mp), weights in [mp, mp + m): within 2 * macc_cap
+        uint64_t *key = reinterpret_cast<uint64_t *>(c.gacc);
+        double *wsorted = reinterpret_cast<double *>(c.gacc) + mp;
+        for (int32_t i = tid; i < mp; i += BS)
+            key[i] = i < m ? (((uint64_t)(uint32_t)c.g.orig[c.MB[i]] << 32) | (uint32_t)i) : ~0ull;
+        __syncthreads();
+        for (int32_t k = 2; k <= mp; k <<= 1) {
+            for (int32_t j = k >> 1; j > 0; j >>= 1) {
+                for (int32_t i = tid; i < mp; i += BS) {
+                    const int32_t l = i ^ j;
+                    if (l > i) {
+                        const uint64_t a = key[i], b = key[l];
+                        const bool up = (i & k) == 0;
+                        if ((a > b) == up) {
+                            key[i] = b;
+                            key[l] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int32_t i = tid; i < m; i += BS) wsorted[i] = as_f64(ld_sig(c.R + c.MB[(uint32_t)key[i]]));
+        __syncthreads();
+        if (tid < 64) {
+            const int lane = tid;
+            double tot = 0.0;
+            for (int32_t b0 = 0; b0 < m; b0 += 64) {
+                const double x = b0 + lane < m ? wsorted[b0 + lane] : 0.0;
+                const int cnt = min(64, m - b0);
+                for (int j = 0; j < cnt; ++j) tot = tot + __shfl(x, j);
+            }
+            const double r = unit53(u2) * tot;
+            double pre = 0.0;
+            int32_t pick = -1;
+            bool done = false;
+            for (int32_t b0 = 0; b0 < m && !done; b0 += 64) {
+                const double x = b0 + lane < m ? wsorted[b0 + lane] : 0.0;
+                const int32_t idk = b0 + lane < m ? (int32_t)(key[b0 + lane] >> 32) : -1;
+                const int cnt = min(64, m - b0);
+                for (int j = 0; j < cnt; ++j) {
+                    const double a = __shfl(x, j);
+                    const int32_t id = __shfl(idk, j);
+                    pre = pre + a;
+                    if (a != 0.0) pick = id;
+                    if (pre > r) { pick = id; done = true; break; }
+                }
+            }
+            if (lane == 0) sm.w = pick >= 0 ? c.g.newid[pick] : pick;
+        }
+        __syncthreads();
+        return;
+    }
+    // beyond the accumulators: visit the list in ascending id by repeated
     // minimum search; first pass sums the weights, second finds the pick.
     double tot = 0.0;
     for (int32_t step = 0, last = -1; step < m; ++step) {

@@ -40,7 +40,7 @@ class kad_opts(C.Structure):
                 ("omega_override", C.c_double), ("sigma_mode", C.c_int32), ("slots", C.c_int32),
                 ("visited_budget_bytes", C.c_uint64), ("epochs_in_flight", C.c_int32),
                 ("use_graphs", C.c_int32), ("block_size", C.c_int32), ("timing", C.c_int32),
-                ("pools", C.c_int32)]
+                ("pools", C.c_int32), ("exact_diameter", C.c_int32)]
 
 
 class kad_result(C.Structure):
@@ -95,6 +95,7 @@ SIGNATURES = [
     ("kad_philox", C.c_int, [_vp, _u64, _u64, _u64, _u32, _u32, _vp]),
     ("kad_vd_bracket", C.c_int, [_vp, _vp, _P(_i64), _P(_i64)]),
     ("kad_omega", _dbl, [_i64, _i64, _dbl, _dbl]),
+    ("kad_exact_vd", C.c_int, [_vp, _vp, _P(_i64), _P(_i32), _P(_i64)]),
     ("kad_features", C.c_int, [_vp, _vp, _vp, _vp]),
     ("kad_device_alloc", C.c_int, [_vp, C.c_size_t, _P(_vp)]),
     ("kad_device_free", C.c_int, [_vp, _vp]),
@@ -163,9 +164,9 @@ def kad_graph_free(g):
 
 def make_opts(seed=1, epsilon=0.01, delta=0.1, epoch_size=0, alloc_mode=KAD_ALLOC_PLAIN,
               omega_override=0.0, sigma_mode=KAD_SIGMA_AUTO, slots=0, visited_budget_bytes=0,
-              epochs_in_flight=0, use_graphs=0, block_size=0, timing=0, pools=0) -> kad_opts:
+              epochs_in_flight=0, use_graphs=0, block_size=0, timing=0, pools=0, exact_diameter=0) -> kad_opts:
     return kad_opts(seed, epsilon, delta, epoch_size, alloc_mode, omega_override, sigma_mode, slots,
-                    visited_budget_bytes, epochs_in_flight, use_graphs, block_size, timing, pools)
+                    visited_budget_bytes, epochs_in_flight, use_graphs, block_size, timing, pools, exact_diameter)
 
 
 def kad_sampler_init(ctx, g, opts: kad_opts):
@@ -276,6 +277,13 @@ def kad_vd_bracket(ctx, g):
     lo, hi = _i64(), _i64()
     _check(lib().kad_vd_bracket(ctx, g, C.byref(lo), C.byref(hi)))
     return lo.value, hi.value
+
+
+def kad_exact_vd(ctx, g):
+    """Returns (VD, witness caller id, BFS runs)."""
+    vd, w, nb = _i64(), _i32(), _i64()
+    _check(lib().kad_exact_vd(ctx, g, C.byref(vd), C.byref(w), C.byref(nb)))
+    return vd.value, w.value, nb.value
 
 
 def kad_omega(vd_lo: int, vd_hi: int, eps: float, delta: float) -> float:

@@ -152,3 +152,16 @@ def test_omega_cap_truncates_last_epoch(oracle):
     assert r["tau"] == 2501 and r["epochs"] == 3
     c_direct, _ = oracle.count(g, 1, 0, 0, 2501)
     assert np.array_equal(r["c"], c_direct)
+
+
+def test_eccentricity_matches_networkx(oracle):
+    g = gg.rmat(9, 8, 3)
+    G = nx.Graph()
+    G.add_nodes_from(range(g.n))
+    for v in range(g.n):
+        for u in g.neighbors(v):
+            G.add_edge(v, int(u))
+    ecc = nx.eccentricity(G)
+    for v in range(0, g.n, 17):
+        assert oracle.eccentricity(g, v) == ecc[v]
+    assert oracle.exact_vd(g) == max(ecc.values()) + 1
