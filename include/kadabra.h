@@ -116,8 +116,9 @@ typedef struct {
     int32_t timing;               /* 1: time every sampler launch with HIP events */
     int32_t pools;                /* slot pools = sampler launches that may       */
                                   /* overlap (1..4); 0 = as many as memory allows */
-    int32_t exact_diameter;       /* 1: omega from the exact vertex diameter      */
-                                  /* (kad_exact_vd, stopped once omega is known); */
+    int32_t exact_diameter;       /* 1: omega from the bracket refined as in      */
+                                  /* kad_exact_vd until its ends give one omega   */
+                                  /* (at most 64 BFS runs, then its upper end);   */
                                   /* 0: from the three-sweep bracket              */
 } kad_opts;
 
@@ -229,11 +230,15 @@ kad_status kad_vd_bracket(kad_ctx *ctx, const kad_graph *g, int64_t *vd_lo, int6
 
 /* kad_exact_vd: the exact vertex diameter of g (the diameter phase of Sec.
  * III-A, computed exactly as in Sec. IV-F with a BFS-based exact algorithm):
- * iFUB on the device, from the middle vertex of a longest path of the three
- * sweeps, with the eccentricities of the farthest levels taken 64 sources
- * at a time by a multi-source BFS.  *h_vd = VD (edges of a longest shortest
+ * bound refinement on the device -- every BFS from x bounds each vertex's
+ * eccentricity by max(d, e - d) <= ecc <= e + d; sources are the bracket's
+ * three sweeps, then alternately the vertex of smallest lower bound and the
+ * vertex of largest upper bound, until the largest eccentricity found
+ * equals the largest upper bound.  *h_vd = VD (edges of a longest shortest
  * path + 1); *h_witness (optional) = a vertex, caller id, of eccentricity
- * VD - 1; *h_bfs (optional) = single-source BFS runs the search took. */
+ * VD - 1; *h_bfs (optional) = BFS runs the search took.  KAD_EOVERFLOW when
+ * 2000 BFS runs do not settle it (graphs with very many vertices of
+ * near-diametral eccentricity, such as random hyperbolic graphs). */
 kad_status kad_exact_vd(kad_ctx *ctx, const kad_graph *g, int64_t *h_vd, int32_t *h_witness, int64_t *h_bfs);
 
 /* kad_omega: omega = 0.5/eps^2 * (floor(log2(VD-2)) + 1 + ln(2/delta)) for

@@ -91,6 +91,7 @@ struct kad_sampler {
     int32_t macc_cap;
     uint32_t *stamps;
     unsigned long long *work_ctr;
+    unsigned long long *pool_epoch;   // replayed graphs: the next epoch of each pool, then the seed
     SampleStats *stats;
     SampleStats *cal_stats;   // the calibration's samples (they may run beside adaptive epochs)
     uint32_t *cal_hist = nullptr;   // histogram of the calibration counts, kept by its sampler
@@ -111,6 +112,10 @@ struct kad_sampler {
     hipEvent_t ev_aux;
     float *yhat;
     bool yhat_pending;
+    // the network's inputs, kept for every run: features (n x 3), weights
+    // and standardisation vector, the feature pass's workspace
+    float *feat_buf = nullptr, *mlp_dev = nullptr;
+    void *feat_ws = nullptr;
     kad_result res;
     double t_kernel_ms;
     uint32_t launches;
@@ -294,8 +299,8 @@ extern "C" kad_status kad_exact_vd(kad_ctx *ctx, const kad_graph *g, int64_t *h_
     if (!ctx || !g || !h_vd) return fail(KAD_EINVAL, "null argument");
     HIPCHK(hipSetDevice(ctx->device));
     int64_t lo = 0, hi = 0;
-    HIPCHK(device_exact_vd(g->dev(), ctx->stream, false, 0.0, 0.0, &lo, &hi, h_witness, h_bfs));
-    if (lo != hi) return fail(KAD_EDEVICE, "internal error: the exact diameter search ended with a bracket");
+    HIPCHK(device_exact_vd(g->dev(), ctx->stream, false, 0.0, 0.0, 2000, &lo, &hi, h_witness, h_bfs));
+    if (lo != hi) return fail(KAD_EOVERFLOW, "the exact diameter search did not settle within its BFS budget");
     *h_vd = lo;
     return KAD_OK;
 }
@@ -317,7 +322,7 @@ static kad_status enqueue_network(kad_sampler *s, hipStream_t st);
 static hipError_t omega_bracket(const kad_sampler *s, int64_t *lo, int64_t *hi)
 {
     if (s->o.exact_diameter)
-        return device_exact_vd(s->g->dev(), s->ctx->stream, true, s->o.epsilon, s->o.delta, lo, hi, nullptr,
+        return device_exact_vd(s->g->dev(), s->ctx->stream, true, s->o.epsilon, s->o.delta, 64, lo, hi, nullptr,
                                nullptr);
     return device_vd_bracket(s->g->dev(), s->ctx->stream, lo, hi);
 }
@@ -336,9 +341,12 @@ static void free_sampler(kad_sampler *s)
     if (s->ev_cal) (void)hipEventDestroy(s->ev_cal);
     if (s->cal_hist) (void)hipFree(s->cal_hist);
     if (s->yhat) (void)hipFree(s->yhat);
+    if (s->feat_buf) (void)hipFree(s->feat_buf);
+    if (s->mlp_dev) (void)hipFree(s->mlp_dev);
+    if (s->feat_ws) (void)hipFree(s->feat_ws);
     if (s->h_status) (void)hipHostFree(s->h_status);
     void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->sf[2], s->sf[3], s->cprime, s->scratch_counts, s->LL, s->LU, s->lo_hi, s->macc,
-                    s->partials, s->prior, s->recs, s->queues, s->mbufs, s->stamps, s->work_ctr,
+                    s->partials, s->prior, s->recs, s->queues, s->mbufs, s->stamps, s->work_ctr, s->pool_epoch,
                     s->stats, s->cal_stats, s->es, s->hist};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -369,6 +377,11 @@ static kad_status reset_epochs(kad_sampler *s)
     HIPCHK(hipMemsetAsync(s->c, 0, sizeof(uint32_t) * s->g->n, st));
     for (int i = 0; i < s->P; ++i) HIPCHK(hipMemsetAsync(s->sf[i], 0, sizeof(uint32_t) * s->g->n, st));
     HIPCHK(hipMemsetAsync(s->work_ctr, 0, 4 * sizeof(unsigned long long), st));
+    {
+        // pool p starts at epoch p; the run's seed for replayed graphs
+        const unsigned long long pe[5] = {0, 1, 2, 3, (unsigned long long)s->o.seed};
+        HIPCHK(hipMemcpyAsync(s->pool_epoch, pe, sizeof(pe), hipMemcpyHostToDevice, st));
+    }
     HIPCHK(hipMemsetAsync(s->stats, 0, sizeof(SampleStats), st));
     HIPCHK(hipStreamSynchronize(st));
     if (s->h_status) memset(s->h_status, 0, sizeof(HostStatus));
@@ -597,6 +610,7 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
               alloc((void **)&s->mbufs, 4ull * n * pools_alloc * s->slots) &&
               alloc((void **)&s->macc, 16ull * (size_t)s->macc_cap * pools_alloc * s->slots) &&
               alloc((void **)&s->stamps, 4ull * pools_alloc * s->slots) && alloc((void **)&s->work_ctr, 64) &&
+              alloc((void **)&s->pool_epoch, 64) &&
               alloc((void **)&s->stats, sizeof(SampleStats)) && alloc((void **)&s->cal_stats, sizeof(SampleStats)) &&
               alloc((void **)&s->es, sizeof(EpochState)) &&
               alloc((void **)&s->hist, epoch_hist_bytes() * s->hist_cap);
@@ -770,6 +784,17 @@ extern "C" kad_status kad_set_mlp_weights(kad_sampler *s, const float *h_params,
     s->yhat_pending = false;
     s->mlp_params.assign(h_params, h_params + 4481);
     s->mlp_norm.assign(h_norm, h_norm + 6);
+    HIPCHK(hipSetDevice(s->device));
+    const size_t n = (size_t)s->g->n;
+    if (!s->yhat && hipMalloc((void **)&s->yhat, sizeof(float) * n) != hipSuccess) s->yhat = nullptr;
+    if (!s->feat_buf && hipMalloc((void **)&s->feat_buf, sizeof(float) * 3 * n) != hipSuccess) s->feat_buf = nullptr;
+    if (!s->mlp_dev && hipMalloc((void **)&s->mlp_dev, sizeof(float) * (4544 + 64)) != hipSuccess) s->mlp_dev = nullptr;
+    if (!s->feat_ws && hipMalloc(&s->feat_ws, features_workspace_bytes(s->g->dev())) != hipSuccess) s->feat_ws = nullptr;
+    if (!s->yhat || !s->feat_buf || !s->mlp_dev || !s->feat_ws)
+        return fail(KAD_ENOMEM, "learned-prior buffers");
+    // weights at the front, the standardisation vector 256-byte aligned behind
+    HIPCHK(hipMemcpy(s->mlp_dev, h_params, sizeof(float) * 4481, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s->mlp_dev + 4544, h_norm, sizeof(float) * 6, hipMemcpyHostToDevice));
     s->have_mlp = true;
     return KAD_OK;
 }
@@ -779,20 +804,9 @@ extern "C" kad_status kad_set_mlp_weights(kad_sampler *s, const float *h_params,
 static kad_status enqueue_network(kad_sampler *s, hipStream_t st)
 {
     const int32_t n = s->g->n;
-    if (!s->yhat && hipMalloc((void **)&s->yhat, sizeof(float) * (size_t)n) != hipSuccess)
-        return fail(KAD_ENOMEM, "network output allocation failed");
-    float *feat = nullptr, *params = nullptr, *norm = nullptr;
-    HIPCHK(hipMallocAsync((void **)&feat, sizeof(float) * 3 * (size_t)n, st));
-    HIPCHK(hipMallocAsync((void **)&params, sizeof(float) * 4481, st));
-    HIPCHK(hipMallocAsync((void **)&norm, sizeof(float) * 6, st));
-    HIPCHK(hipMemcpyAsync(params, s->mlp_params.data(), sizeof(float) * 4481, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(norm, s->mlp_norm.data(), sizeof(float) * 6, hipMemcpyHostToDevice, st));
-    HIPCHK(launch_features(s->g->dev(), feat, st));
-    HIPCHK(launch_normalize(n, feat, norm, st));
-    HIPCHK(launch_mlp_forward(params, feat, n, s->yhat, st));
-    HIPCHK(hipFreeAsync(feat, st));
-    HIPCHK(hipFreeAsync(params, st));
-    HIPCHK(hipFreeAsync(norm, st));
+    HIPCHK(launch_features_ws(s->g->dev(), s->feat_buf, s->feat_ws, st));
+    HIPCHK(launch_normalize(n, s->feat_buf, s->mlp_dev + 4544, st));
+    HIPCHK(launch_mlp_forward(s->mlp_dev, s->feat_buf, n, s->yhat, st));
     return KAD_OK;
 }
 
@@ -891,23 +905,6 @@ static kad_status ensure_delta(kad_sampler *s, const std::function<kad_status()>
     s->res.tau0 = learned ? 0 : s->tau0;
     s->res.t_alloc_ms = now_ms() - t0;
     s->delta_ready = true;
-    return KAD_OK;
-}
-
-// Enqueue one epoch for graph capture (single stream): sampler with the
-// range read on the device, then merge/stop.
-static kad_status enqueue_epoch(kad_sampler *s, hipEvent_t ev0, hipEvent_t ev1)
-{
-    hipStream_t st = s->ctx->stream;
-    SampleLaunch a = base_launch(s);
-    a.dev_range = s->es->range;
-    a.stop_flag = &s->es->stopped;
-    if (ev0) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_sampler(a, s->slots, s->block, st));
-    if (ev1) HIPCHK(hipEventRecord(ev1, st));
-    HIPCHK(launch_merge_stop_impl(s->g->dev(), s->c, s->sf[0], s->sf[1], s->LL, s->LU, s->omega,
-                                  s->o.epsilon, s->cap, s->E, s->es, s->work_ctr, s->hist, s->hist_cap,
-                                  s->d_status, st));
     return KAD_OK;
 }
 
@@ -1015,21 +1012,76 @@ static kad_status fill_result(kad_sampler *s)
     return KAD_OK;
 }
 
+// The pooled epoch schedule captured as one graph: the epochs of a replay
+// are dealt to the pools in turn, each pool's sampler reads its epoch from
+// the device (its merge advances it by P), and every merge waits for the
+// previous epoch's merge, so c~ grows and the rule is checked in epoch
+// order.  A replay covers G epochs (a multiple of P, enough for the run
+// unless omega is far away); samplers and merges after the stop return at
+// once.  Streams join the capture through events; nothing is cleared with
+// a memset node (the merges clear their frames and counters).
 static kad_status build_graph(kad_sampler *s)
 {
     hipStream_t st = s->ctx->stream;
+    const unsigned long long total = (s->cap + s->E - 1) / s->E;
+    const int per = (int)std::min<unsigned long long>(std::max<unsigned long long>((unsigned long long)s->P,
+                                                                                 std::min<unsigned long long>(total, 16)),
+                                                      64);
+    const int G = (per + s->P - 1) / s->P * s->P;
+    std::vector<hipEvent_t> evs((size_t)G + 2 * (size_t)s->P + 1);
+    for (auto &e : evs) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    auto cleanup = [&]() {
+        for (auto &e : evs) (void)hipEventDestroy(e);
+    };
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < s->inflight; ++i) {
-        kad_status r = enqueue_epoch(s, nullptr, nullptr);
-        if (r != KAD_OK) {
-            (void)hipStreamEndCapture(st, &graph);
-            return r;
-        }
+    kad_status r = KAD_OK;
+    auto chk = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && r == KAD_OK) r = fail(KAD_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    size_t ev = 0;
+    chk(hipEventRecord(evs[ev], st), "fork");
+    for (int p = 1; p < s->P; ++p) chk(hipStreamWaitEvent(s->sts[p], evs[ev], 0), "fork wait");
+    ++ev;
+    hipEvent_t prev_merge = nullptr;
+    for (int j = 0; j < G && r == KAD_OK; ++j) {
+        const int p = j % s->P;
+        hipStream_t sp = s->sts[p];
+        SampleLaunch a = base_launch(s, p);
+        a.dev_epoch = s->pool_epoch + p;
+        a.dev_seed = reinterpret_cast<const uint64_t *>(s->pool_epoch + 4);
+        a.E = s->E;
+        a.cap = s->cap;
+        a.sf[0] = a.sf[1] = s->sf[p];
+        a.stop_flag = &s->es->stopped;
+        chk(launch_sampler(a, s->slots, s->block, sp), "sampler");
+        if (prev_merge) chk(hipStreamWaitEvent(sp, prev_merge, 0), "merge order");
+        chk(launch_merge_stop_impl(s->g->dev(), s->c, s->sf[p], s->sf[p], s->LL, s->LU, s->omega, s->o.epsilon,
+                                   s->cap, s->E, s->es, s->work_ctr + p, s->hist, s->hist_cap, s->d_status, sp,
+                                   s->pool_epoch + p, s->P),
+            "merge");
+        chk(hipEventRecord(evs[ev], sp), "merge event");
+        prev_merge = evs[ev++];
     }
-    HIPCHK(hipStreamEndCapture(st, &graph));
-    HIPCHK(hipGraphInstantiate(&s->gexec, graph, nullptr, nullptr, 0));
-    HIPCHK(hipGraphDestroy(graph));
+    for (int p = 1; p < s->P; ++p) {
+        chk(hipEventRecord(evs[ev], s->sts[p]), "join");
+        chk(hipStreamWaitEvent(st, evs[ev], 0), "join wait");
+        ++ev;
+    }
+    const hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (r != KAD_OK) {
+        if (ce == hipSuccess) (void)hipGraphDestroy(graph);
+        cleanup();
+        return r;
+    }
+    if (ce != hipSuccess) {
+        cleanup();
+        return fail(KAD_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    }
+    const hipError_t ie = hipGraphInstantiate(&s->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    cleanup();
+    if (ie != hipSuccess) return fail(KAD_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
     s->have_graph = true;
     return KAD_OK;
 }
@@ -1058,7 +1110,8 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
     // learned allocation is a chain of short launches that would wait for
     // CUs behind those samplers, so it runs first on an idle GPU.
     const unsigned long long total = (s->cap + s->E - 1) / s->E;
-    const bool graph_path = s->o.use_graphs && !timing;
+    // (a run already advanced epoch by epoch stays on the stream loop)
+    const bool graph_path = s->o.use_graphs != 0 && s->next_epoch == 0;
     unsigned long long pre_hi = 0;
     kad_status r = read_state(s);   // the allocation does not touch the epoch state
     if (r != KAD_OK) return r;
@@ -1104,11 +1157,11 @@ extern "C" kad_status kad_run_to_stop(kad_sampler *s, kad_result *out)
         s->next_epoch = pre_hi;
     }
     const double t_ads0 = now_ms();
-    if (s->o.use_graphs && !timing && !s->have_graph) {
+    if (graph_path && !s->have_graph) {
         r = build_graph(s);
         if (r != KAD_OK) return r;
     }
-    if (s->have_graph && !timing) {
+    if (graph_path) {
         while (!s->h_es->stopped) {
             HIPCHK(hipGraphLaunch(s->gexec, st));
             r = read_state(s);

@@ -57,7 +57,8 @@ __global__ __launch_bounds__(MB) void k_merge_stop(int32_t n, uint32_t *c, uint3
                                                    double eps, unsigned long long cap,
                                                    unsigned long long E, EpochState *es,
                                                    unsigned long long *work_ctr, EpochHist *hist,
-                                                   int32_t hist_cap, HostStatus *hs)
+                                                   int32_t hist_cap, HostStatus *hs,
+                                                   unsigned long long *pool_epoch, int pools)
 {
     if (__hip_atomic_load(&es->stopped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const unsigned long long first = es->range[0], count = es->range[1];
@@ -135,6 +136,7 @@ __global__ __launch_bounds__(MB) void k_merge_stop(int32_t n, uint32_t *c, uint3
     es->range[1] = stop ? 0 : ((cap - nfirst) < E ? (cap - nfirst) : E);
     es->range[2] = ep + 1;
     if (work_ctr) *work_ctr = 0;
+    if (pool_epoch) *pool_epoch += (unsigned long long)pools;   // this pool's next epoch
     __threadfence();
     __hip_atomic_store(&es->stopped, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (hs) {
@@ -738,211 +740,51 @@ __global__ void k_bfs_advance(int32_t *sz, BfsLim lim)
     sz[9] = 0;
 }
 
-// ---- exact vertex diameter (iFUB on top of the sweeps above; multi-source
-// BFS for the eccentricities of a level's vertices)
+// ---- exact vertex diameter (bound refinement on top of the sweeps above)
 
-// Smallest caller id among the middle vertices of shortest a-b paths:
-// da[v] + db[v] = d(a, b) and da[v] = d(a, b) / 2.
-__global__ void k_midpoint(int32_t n, const int32_t *da, const int32_t *db, const int32_t *orig, int32_t dab,
-                           int32_t *out)
+// Eccentricity bounds after a BFS from x (distances d, eccentricity e):
+// every vertex v has max(d(v), e - d(v)) <= ecc(v) <= e + d(v).  Keeps the
+// tightest bounds seen, and reduces over the vertices whose upper bound
+// still exceeds lb (the diameter's lower bound): the largest upper bound
+// (with the caller-smallest such vertex) and the smallest lower bound (with
+// its caller-smallest vertex), packed into 64-bit keys.
+__global__ void k_ecc_bounds(int32_t n, const int32_t *dist, int32_t e, int32_t *L, int32_t *U,
+                             const int32_t *orig, int32_t lb, unsigned long long *keys)
 {
-    const int32_t half = dab / 2;
-    int32_t b = 0x7fffffff;
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        if (da[v] == half && db[v] >= 0 && da[v] + db[v] == dab && orig[v] < b) b = orig[v];
-    if (b != 0x7fffffff) atomicMin(out, b);
-}
-
-// Lists the vertices at distance `depth` (internal ids, any order).
-__global__ void k_list_depth(int32_t n, const int32_t *dist, int32_t depth, int32_t *out, int32_t *cnt)
-{
-    const int64_t step = (int64_t)gridDim.x * blockDim.x;
-    const int64_t span = ((int64_t)n + step - 1) / step * step;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < span; v += step) {
-        const bool hit = v < n && dist[v] == depth;
-        const int32_t pos = wave_append(cnt, hit);
-        if (hit) out[pos] = (int32_t)v;
+    unsigned long long ku = 0, kl = ~0ull;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int32_t d = dist[v];
+        int32_t l = L[v], u = U[v];
+        const int32_t lo = d > e - d ? d : e - d;
+        l = lo > l ? lo : l;
+        u = e + d < u ? e + d : u;
+        L[v] = l;
+        U[v] = u;
+        if (u > lb) {
+            const unsigned long long o = (unsigned long long)(uint32_t)orig[v];
+            const unsigned long long a = ((unsigned long long)(uint32_t)u << 32) | (0xFFFFFFFFull - o);
+            const unsigned long long b = ((unsigned long long)(uint32_t)l << 32) | o;
+            ku = a > ku ? a : ku;
+            kl = b < kl ? b : kl;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long x = __shfl_xor(ku, o), y = __shfl_xor(kl, o);
+        ku = x > ku ? x : ku;
+        kl = y < kl ? y : kl;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (ku) atomicMax(&keys[0], ku);
+        if (kl != ~0ull) atomicMin(&keys[1], kl);
     }
 }
 
-// Multi-source BFS for up to 64 sources at once: bit j of seen[v] / front[v]
-// says whether source j has reached v / has v in its current frontier.
-// A level adds, for every vertex, the sources of its neighbours' frontiers
-// it has not seen; the OR of the new bits over all vertices (ms[0]) says
-// which sources' BFS reached a new depth, so a source's eccentricity is the
-// last level at which its bit appears.
-//   ms[0] level OR   ms[1] next count   ms[2] next degree sum   ms[3] active mask
-__global__ void k_ms_clear(int32_t n, uint64_t *seen, uint64_t *front, uint64_t *nxt)
+__global__ void k_ecc_init(int32_t n, int32_t *L, int32_t *U)
 {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        seen[v] = 0;
-        front[v] = 0;
-        nxt[v] = 0;
+        L[v] = 0;
+        U[v] = 0x7fffffff;
     }
-}
-
-__global__ void k_ms_seed(DevGraph g, const int32_t *src, int32_t nsrc, uint64_t *seen, uint64_t *front,
-                          int32_t *list, unsigned long long *ms)
-{
-    const int j = threadIdx.x;
-    if (j == 0) {
-        ms[0] = 0;
-        ms[1] = (unsigned long long)nsrc;
-        ms[2] = 0;
-        ms[3] = nsrc >= 64 ? ~0ull : ((1ull << nsrc) - 1);
-    }
-    __syncthreads();
-    if (j < nsrc) {
-        const int32_t v = src[j];      // distinct vertices
-        seen[v] = 1ull << j;
-        front[v] = 1ull << j;
-        list[j] = v;
-        atomicAdd(&ms[2], (unsigned long long)g.deg[v]);
-    }
-}
-
-// Top-down level: a wave per frontier vertex pushes its frontier bits to
-// its neighbours; a neighbour is listed by the first lane that gives it
-// bits this level.
-__global__ void k_ms_td(DevGraph g, const uint64_t *seen, const uint64_t *front, uint64_t *nxt,
-                        const int32_t *cur, int32_t ncur, int32_t *next, unsigned long long *ms)
-{
-    const int lane = threadIdx.x & 63;
-    const int32_t wpb = blockDim.x >> 6;
-    for (int32_t i = blockIdx.x * wpb + (threadIdx.x >> 6); i < ncur; i += gridDim.x * wpb) {
-        const int32_t u = cur[i];
-        const uint64_t m = front[u];
-        const int64_t b = g.rp[u], e1 = g.rp[u + 1];
-        for (int64_t e0 = b; e0 < e1; e0 += 64) {
-            const int64_t e = e0 + lane;
-            bool first = false;
-            int32_t w = 0;
-            if (e < e1 && m) {
-                w = g.ci[e];
-                const uint64_t add = m & ~seen[w];
-                if (add) first = atomicOr((unsigned long long *)&nxt[w], (unsigned long long)add) == 0ull;
-            }
-            const int32_t pos = wave_append((int32_t *)&ms[1], first);
-            if (first) next[pos] = w;
-        }
-    }
-}
-
-// Bottom-up level over the vertices [v0, v1): a vertex gathers the frontier
-// bits of its neighbours, stopping once every active source is accounted
-// for.  `wave`: a wave per vertex (long rows), else a thread per vertex.
-__global__ void k_ms_bu(DevGraph g, const uint64_t *seen, const uint64_t *front, uint64_t *nxt, int32_t v0,
-                        int32_t v1, int wave, const unsigned long long *ms)
-{
-    const uint64_t all = (uint64_t)ms[3];
-    if (wave) {
-        const int lane = threadIdx.x & 63;
-        const int32_t wpb = blockDim.x >> 6;
-        for (int32_t v = v0 + blockIdx.x * wpb + (threadIdx.x >> 6); v < v1; v += gridDim.x * wpb) {
-            const uint64_t s = seen[v];
-            if (s == all) continue;
-            uint64_t acc = 0;
-            const int64_t b = g.rp[v], e1 = g.rp[v + 1];
-            for (int64_t e0 = b; e0 < e1; e0 += 64) {
-                const int64_t e = e0 + lane;
-                uint64_t x = (e < e1) ? front[g.ci[e]] : 0ull;
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
-                acc |= x;
-                if ((acc | s) == all) break;
-            }
-            if (lane == 0) nxt[v] = acc & ~s;
-        }
-    } else {
-        for (int32_t v = v0 + blockIdx.x * blockDim.x + threadIdx.x; v < v1; v += gridDim.x * blockDim.x) {
-            const uint64_t s = seen[v];
-            if (s == all) continue;
-            uint64_t acc = 0;
-            const int64_t b = g.rp[v], e1 = g.rp[v + 1];
-            for (int64_t e = b; e < e1; ++e) {
-                acc |= front[g.ci[e]];
-                if ((acc | s) == all) break;
-            }
-            nxt[v] = acc & ~s;
-        }
-    }
-}
-
-__device__ __forceinline__ void ms_level_or(unsigned long long *ms, uint64_t x)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
-    if ((threadIdx.x & 63) == 0 && x) atomicOr(&ms[0], (unsigned long long)x);
-}
-
-// End of a top-down level: the old frontier's bits are cleared first
-// (k_ms_drop), then each listed vertex takes its new bits.
-__global__ void k_ms_drop(uint64_t *front, const int32_t *cur, int32_t ncur)
-{
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ncur; i += gridDim.x * blockDim.x)
-        front[cur[i]] = 0;
-}
-
-__global__ void k_ms_take_listed(DevGraph g, uint64_t *seen, uint64_t *front, uint64_t *nxt, const int32_t *next,
-                                 const unsigned long long *cnt_ptr, unsigned long long *ms)
-{
-    const int32_t cnt = (int32_t)*cnt_ptr;
-    unsigned long long dsum = 0;
-    uint64_t lor = 0;
-    const int64_t step = (int64_t)gridDim.x * blockDim.x;
-    const int64_t span = ((int64_t)cnt + step - 1) / step * step;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < span; i += step) {
-        if (i < cnt) {
-            const int32_t w = next[i];
-            const uint64_t nw = nxt[w] & ~seen[w];
-            seen[w] |= nw;
-            front[w] = nw;
-            nxt[w] = 0;
-            lor |= nw;
-            dsum += (unsigned long long)g.deg[w];
-        }
-    }
-    ms_level_or(ms, lor);
-    if (dsum) atomicAdd(&ms[2], dsum);
-}
-
-// End of a bottom-up level over every vertex: new bits become the
-// frontier (and old frontier bits are dropped); new vertices are listed.
-__global__ void k_ms_take_all(DevGraph g, uint64_t *seen, uint64_t *front, uint64_t *nxt, int32_t *next,
-                              unsigned long long *ms)
-{
-    unsigned long long dsum = 0;
-    uint64_t lor = 0;
-    const int64_t step = (int64_t)gridDim.x * blockDim.x;
-    const int64_t span = ((int64_t)g.n + step - 1) / step * step;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < span; v += step) {
-        uint64_t nw = 0;
-        if (v < g.n) {
-            nw = nxt[v];
-            front[v] = nw;
-            nxt[v] = 0;
-            if (nw) {
-                seen[v] |= nw;
-                lor |= nw;
-                dsum += (unsigned long long)g.deg[v];
-            }
-        }
-        const int32_t pos = wave_append((int32_t *)&ms[1], nw != 0);
-        if (nw) next[pos] = (int32_t)v;
-    }
-    ms_level_or(ms, lor);
-    if (dsum) atomicAdd(&ms[2], dsum);
-}
-
-// Vertices with rows longer than 32 entries (a prefix of the hub-first
-// numbering).
-__global__ void k_count_long(int32_t n, const uint32_t *deg, int32_t *out)
-{
-    int c = 0;
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        c += deg[v] > 32u ? 1 : 0;
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
 }
 
 int grid_for(int64_t n, int block, int cap = 8192)
@@ -959,13 +801,14 @@ hipError_t launch_merge_stop_impl(const DevGraph &g, uint32_t *c, uint32_t *sf0,
                                   const double *LL, const double *LU, double omega, double eps,
                                   unsigned long long cap, unsigned long long E, EpochState *es,
                                   unsigned long long *work_ctr, void *hist, int32_t hist_cap,
-                                  HostStatus *hs, hipStream_t st)
+                                  HostStatus *hs, hipStream_t st, unsigned long long *pool_epoch, int pools)
 {
     // At most 256 workgroups: the merge runs while sampler workgroups hold
     // the CUs, and each of its workgroups waits for a slot that one of them
     // gives up; fewer, longer workgroups finish the merge sooner there.
     hipLaunchKernelGGL(k_merge_stop, dim3(grid_for(g.n, MB, 256)), dim3(MB), 0, st, g.n, c, sf0, sf1,
-                       LL, LU, omega, eps, cap, E, es, work_ctr, (EpochHist *)hist, hist_cap, hs);
+                       LL, LU, omega, eps, cap, E, es, work_ctr, (EpochHist *)hist, hist_cap, hs, pool_epoch,
+                       pools);
     return hipGetLastError();
 }
 
@@ -1214,64 +1057,6 @@ hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, 
     return hipGetLastError();
 }
 
-// Multi-source BFS buffers.
-struct MsBufs {
-    uint64_t *seen = nullptr, *front = nullptr, *nxt = nullptr;
-    int32_t *la = nullptr, *lb = nullptr, *nlong = nullptr;
-    unsigned long long *ms = nullptr;
-    int32_t long_rows = 0;
-};
-
-// Eccentricities of up to 64 distinct sources (internal ids in src[0..k)):
-// *best = the largest, *best_j = the index of a source attaining it.
-static hipError_t ms_ecc(const DevGraph &g, hipStream_t st, MsBufs &m, const int32_t *src, int32_t k,
-                         int32_t *best, int32_t *best_j)
-{
-    const int32_t n = g.n;
-    hipLaunchKernelGGL(k_ms_clear, dim3(grid_for(n, 256)), dim3(256), 0, st, n, m.seen, m.front, m.nxt);
-    hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(64), 0, st, g, src, k, m.seen, m.front, m.la, m.ms);
-    int32_t ecc[64] = {0};
-    int32_t *cur = m.la, *next = m.lb;
-    unsigned long long h[4];
-    CK(hipMemcpyAsync(h, m.ms, sizeof(h), hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
-    const int64_t big_e = std::max<int64_t>(g.nnz / 16, (int64_t)1 << 20);
-    const int64_t big_v = std::max<int64_t>(n / 16, 1 << 14);
-    for (int32_t level = 1; level <= n; ++level) {
-        const int64_t ncur = (int64_t)h[1], dcur = (int64_t)h[2];
-        if (ncur == 0) break;
-        CK(hipMemsetAsync(m.ms, 0, 3 * sizeof(unsigned long long), st));
-        if (dcur >= big_e || ncur >= big_v) {
-            if (m.long_rows > 0)
-                hipLaunchKernelGGL(k_ms_bu, dim3(grid_for((int64_t)m.long_rows * 64, 256, 4096)), dim3(256), 0, st,
-                                   g, m.seen, m.front, m.nxt, 0, m.long_rows, 1, m.ms);
-            hipLaunchKernelGGL(k_ms_bu, dim3(grid_for(n - m.long_rows, 256, 8192)), dim3(256), 0, st, g, m.seen,
-                               m.front, m.nxt, m.long_rows, n, 0, m.ms);
-            hipLaunchKernelGGL(k_ms_take_all, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, g, m.seen, m.front,
-                               m.nxt, next, m.ms);
-        } else {
-            hipLaunchKernelGGL(k_ms_td, dim3(grid_for(ncur * 64, 256, 4096)), dim3(256), 0, st, g, m.seen, m.front,
-                               m.nxt, cur, (int32_t)ncur, next, m.ms);
-            hipLaunchKernelGGL(k_ms_drop, dim3(grid_for(ncur, 256, 4096)), dim3(256), 0, st, m.front, cur,
-                               (int32_t)ncur);
-            hipLaunchKernelGGL(k_ms_take_listed, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, g, m.seen, m.front,
-                               m.nxt, next, m.ms + 1, m.ms);
-        }
-        CK(hipMemcpyAsync(h, m.ms, sizeof(h), hipMemcpyDeviceToHost, st));
-        CK(hipStreamSynchronize(st));
-        const uint64_t lor = (uint64_t)h[0];
-        for (int j = 0; j < k; ++j)
-            if ((lor >> j) & 1ull) ecc[j] = level;
-        if (lor == 0) break;
-        std::swap(cur, next);
-    }
-    *best = -1;
-    *best_j = 0;
-    for (int j = 0; j < k; ++j)
-        if (ecc[j] > *best) { *best = ecc[j]; *best_j = j; }
-    return hipGetLastError();
-}
-
 static double omega_of_vd(int64_t vd, double eps, double delta)
 {
     double lg = 0.0;
@@ -1283,113 +1068,89 @@ static double omega_of_vd(int64_t vd, double eps, double delta)
     return 0.5 / (eps * eps) * (lg + 1.0 + log(2.0 / delta));
 }
 
-// Exact vertex diameter by iFUB (Crescenzi, Grossi, Habib, Lanzi, Marino,
-// TCS 2013), the BFS-based family of exact diameter algorithms the paper's
-// diameter phase uses: bounds from the three sweeps of the bracket, a BFS
-// from u, the middle of a longest a-b path found, then the eccentricities
-// of u's farthest levels, deepest first.  Any two vertices within distance
-// i - 1 of u are within 2(i - 1) of each other, so once the largest
-// eccentricity found exceeds 2(i - 1) it is the diameter; otherwise the
-// diameter is at most 2(i - 1) and the next level down is examined.
-// With omega_only the search stops as soon as both ends of the bracket
-// give the same omega (eps, delta).
+// Exact vertex diameter by bound refinement on eccentricities, the
+// BFS-based family of exact diameter algorithms the paper's diameter phase
+// uses (Borassi et al.; the refinement is Takes and Kosters'): every BFS
+// from x gives max(d, e - d) <= ecc(v) <= e + d for every vertex v, the
+// largest eccentricity found is a lower bound lb of the diameter and the
+// largest upper bound among the vertices is an upper bound.  The first
+// three sources are the bracket's sweeps; then the sources alternate
+// between the vertex of smallest lower bound (a central vertex, whose BFS
+// tightens many upper bounds) and the vertex of largest upper bound, among
+// the vertices whose upper bound still exceeds lb (ties: the smallest
+// caller id).  With omega_only the search stops as soon as both ends of
+// the bracket give the same omega (eps, delta).  Stops with a bracket after
+// max_bfs BFS runs (graphs with many vertices of near-diametral
+// eccentricity, as random hyperbolic graphs, need very many).
 hipError_t device_exact_vd(const DevGraph &g, hipStream_t st, bool omega_only, double eps, double delta,
-                           int64_t *vd_lo, int64_t *vd_hi, int32_t *witness, int64_t *bfs_runs)
+                           int64_t max_bfs, int64_t *vd_lo, int64_t *vd_hi, int32_t *witness, int64_t *bfs_runs)
 {
     hipError_t e;
     const int32_t n = g.n;
     BfsBufs b;
-    MsBufs m;
     if ((e = bfs_alloc(g, st, b, true)) != hipSuccess) return e;
+    int32_t *Lb = b.dist1, *Ub = nullptr;
+    unsigned long long *keys = nullptr;
+    if ((e = hipMallocAsync((void **)&Ub, sizeof(int32_t) * (size_t)n, st)) != hipSuccess) return e;
+    if ((e = hipMallocAsync((void **)&keys, 2 * sizeof(unsigned long long), st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ecc_init, dim3(grid_for(n, 256)), dim3(256), 0, st, n, Lb, Ub);
     CK(hipMemsetAsync(b.best, 0, sizeof(unsigned long long), st));
     hipLaunchKernelGGL(k_argmax_degree, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, g, b.best);
-    int32_t er = 0, ea = 0, eb = 0, eu = 0;
+    int64_t lo = 0, hi = INT64_MAX;
+    int32_t wit = 0, hint = 0, r_int = 0;
     int32_t hp[8];
-    // r -> a (dist1 keeps the distances from a) -> b
-    if ((e = bfs_sweep(g, st, b, b.dist0, b.best, 0, 0, &er)) != hipSuccess) return e;
-    CK(hipMemcpyAsync(hp, b.pick, sizeof(hp), hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
-    const int32_t a_id = hp[1];
-    if ((e = bfs_sweep(g, st, b, b.dist1, nullptr, 1, er, &ea)) != hipSuccess) return e;
-    CK(hipMemcpyAsync(hp, b.pick, sizeof(hp), hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
-    const int32_t b_id = hp[1];
-    if ((e = bfs_sweep(g, st, b, b.dist0, nullptr, 2, er, &eb)) != hipSuccess) return e;
-    int64_t lo = std::max(ea, eb), hi = 2 * (int64_t)std::min(er, std::min(ea, eb));
-    int32_t wit = ea >= eb ? a_id : b_id;
     auto settled = [&]() {
         return lo >= hi || (omega_only && omega_of_vd(lo + 1, eps, delta) == omega_of_vd(hi + 1, eps, delta));
     };
-    if (!settled()) {
-        // u: the middle of a longest shortest path a-b (d(a, b) = ecc(a))
-        const int32_t big = 0x7fffffff;
-        CK(hipMemcpyAsync(b.pick + 1, &big, sizeof(big), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_midpoint, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, b.dist1, b.dist0, g.orig,
-                           ea, b.pick + 1);
-        CK(hipMemcpyAsync(hp, b.pick, sizeof(hp), hipMemcpyDeviceToHost, st));
-        CK(hipStreamSynchronize(st));
-        const int32_t u_id = hp[1];
-        CK(hipMemcpyAsync(b.pick + 1, &u_id, sizeof(u_id), hipMemcpyHostToDevice, st));
-        if ((e = bfs_sweep(g, st, b, b.dist1, nullptr, 3, ea / 2, &eu)) != hipSuccess) return e;
-        if (eu > lo) { lo = eu; wit = u_id; }
-        hi = std::min<int64_t>(hi, 2 * (int64_t)eu);
-    }
-    if (!settled()) {
-        if ((e = hipMallocAsync((void **)&m.seen, 8ull * n, st)) != hipSuccess) return e;
-        if ((e = hipMallocAsync((void **)&m.front, 8ull * n, st)) != hipSuccess) return e;
-        if ((e = hipMallocAsync((void **)&m.nxt, 8ull * n, st)) != hipSuccess) return e;
-        if ((e = hipMallocAsync((void **)&m.la, 4ull * n, st)) != hipSuccess) return e;
-        if ((e = hipMallocAsync((void **)&m.lb, 4ull * n, st)) != hipSuccess) return e;
-        if ((e = hipMallocAsync((void **)&m.nlong, 4, st)) != hipSuccess) return e;
-        if ((e = hipMallocAsync((void **)&m.ms, 4 * sizeof(unsigned long long), st)) != hipSuccess) return e;
-        CK(hipMemsetAsync(m.nlong, 0, 4, st));
-        hipLaunchKernelGGL(k_count_long, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, g.deg, m.nlong);
-        CK(hipMemcpyAsync(&m.long_rows, m.nlong, 4, hipMemcpyDeviceToHost, st));
-        CK(hipStreamSynchronize(st));
-        // the level lists of u go to fa (the sweeps are done with it)
-        std::vector<int32_t> ids;
-        for (int32_t i = eu; i >= 1; --i) {
-            // every level beyond i is done: two vertices both within i of u
-            // are within 2i of each other
-            hi = std::min<int64_t>(hi, std::max<int64_t>(lo, 2 * (int64_t)i));
-            if (settled()) break;
-            int32_t cnt = 0;
-            CK(hipMemsetAsync(b.sizes, 0, 4, st));
-            hipLaunchKernelGGL(k_list_depth, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, b.dist1, i, b.fa,
-                               b.sizes);
-            CK(hipMemcpyAsync(&cnt, b.sizes, 4, hipMemcpyDeviceToHost, st));
+    for (int64_t it = 0; it < max_bfs; ++it) {
+        // source: the largest degree, then the two sweeps, then the bounds
+        int32_t src_caller = -1;
+        if (it >= 3) {
+            unsigned long long hk[2];
+            CK(hipMemcpyAsync(hk, keys, sizeof(hk), hipMemcpyDeviceToHost, st));
             CK(hipStreamSynchronize(st));
-            for (int32_t j0 = 0; j0 < cnt && !settled(); j0 += 64) {
-                const int32_t k = std::min(64, cnt - j0);
-                int32_t best = 0, bj = 0;
-                if ((e = ms_ecc(g, st, m, b.fa + j0, k, &best, &bj)) != hipSuccess) return e;
-                b.sweeps += k;
-                if (best > lo) {
-                    int32_t v = 0;
-                    CK(hipMemcpyAsync(&v, b.fa + j0 + bj, 4, hipMemcpyDeviceToHost, st));
-                    CK(hipStreamSynchronize(st));
-                    lo = best;
-                    wit = -1 - v;   // internal id, mapped below
-                }
-                hi = std::min<int64_t>(hi, std::max<int64_t>(lo, 2 * (int64_t)i));
-            }
-            if (settled()) break;
-            // level i done too
-            hi = std::min<int64_t>(hi, std::max<int64_t>(lo, 2 * (int64_t)(i - 1)));
+            if (it % 2 == 1) src_caller = (int32_t)(hk[1] & 0xFFFFFFFFull);           // smallest lower bound
+            else src_caller = (int32_t)(0xFFFFFFFFull - (hk[0] & 0xFFFFFFFFull));    // largest upper bound
+            CK(hipMemcpyAsync(b.pick + 1, &src_caller, sizeof(src_caller), hipMemcpyHostToDevice, st));
+        } else if (it > 0) {
+            CK(hipMemcpyAsync(hp, b.pick, sizeof(hp), hipMemcpyDeviceToHost, st));
+            CK(hipStreamSynchronize(st));
+            src_caller = hp[1];   // the previous sweep's farthest vertex
         }
-        if (lo > hi) hi = lo;
-        void *ps[] = {m.seen, m.front, m.nxt, m.la, m.lb, m.nlong, m.ms};
-        for (void *p : ps) CK(hipFreeAsync(p, st));
+        int32_t ecc = 0;
+        if ((e = bfs_sweep(g, st, b, b.dist0, it == 0 ? b.best : nullptr, it < 3 ? (int)it : 3, hint, &ecc)) !=
+            hipSuccess)
+            return e;
+        if (it == 0) {
+            CK(hipMemcpyAsync(hp, b.pick, sizeof(hp), hipMemcpyDeviceToHost, st));
+            CK(hipStreamSynchronize(st));
+            hint = ecc;
+            r_int = hp[0];
+        }
+        if (ecc > lo) {
+            lo = ecc;
+            wit = src_caller;   // -1: the first source, resolved below
+        }
+        const unsigned long long init[2] = {0ull, ~0ull};
+        CK(hipMemcpyAsync(keys, init, sizeof(init), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_ecc_bounds, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, b.dist0, ecc, Lb, Ub,
+                           g.orig, (int32_t)lo, keys);
+        unsigned long long hk[2];
+        CK(hipMemcpyAsync(hk, keys, sizeof(hk), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        hi = hk[0] ? std::max<int64_t>(lo, (int64_t)(hk[0] >> 32)) : lo;
+        if (settled()) break;
     }
-    if (wit < 0) {   // an internal id: its caller id
-        const int32_t v = -1 - wit;
-        CK(hipMemcpyAsync(&wit, g.orig + v, 4, hipMemcpyDeviceToHost, st));
+    if (wit < 0) {   // the vertex of largest degree: the first sweep's source
+        CK(hipMemcpyAsync(&wit, g.orig + r_int, 4, hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));
     }
     *vd_lo = lo + 1;
     *vd_hi = hi + 1;
     if (witness) *witness = wit;
     if (bfs_runs) *bfs_runs = b.sweeps;
+    CK(hipFreeAsync(Ub, st));
+    CK(hipFreeAsync(keys, st));
     CK(bfs_free(b, st));
     CK(hipStreamSynchronize(st));
     return hipGetLastError();

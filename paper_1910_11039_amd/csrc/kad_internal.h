@@ -90,7 +90,9 @@ struct SampleLaunch {
     uint64_t stream;
     uint64_t first;                 // first sample index of the launch
     uint64_t count;                 // samples in the launch (from host), or
-    const unsigned long long *dev_range;  // if non-null: {first, count, sf_index} read on the device
+    const unsigned long long *dev_epoch;  // if non-null: the launch's epoch k, read on the device: samples
+    unsigned long long E, cap;            // [kE, min((k+1)E, cap)) into sf[0] (replayed graphs)
+    const uint64_t *dev_seed;             // if non-null: the Philox seed, read on the device
     uint32_t *sf[2];                // counter buffers (state frames)
     Rec *recs;                      // slots * n records
     int32_t *queues;                // slots * n frontier entries
@@ -139,7 +141,8 @@ hipError_t launch_merge_stop_impl(const DevGraph &g, uint32_t *c, uint32_t *sf0,
                                   const double *LL, const double *LU, double omega, double eps,
                                   unsigned long long cap, unsigned long long E, EpochState *es,
                                   unsigned long long *work_ctr, void *hist, int32_t hist_cap,
-                                  HostStatus *hs, hipStream_t st);
+                                  HostStatus *hs, hipStream_t st, unsigned long long *pool_epoch = nullptr,
+                                  int pools = 0);
 size_t epoch_hist_bytes();   // per-epoch record: max_f, max_g, min_margin (f64), ok (i32), pad
 size_t alloc_partials(int32_t n);
 hipError_t launch_fg(int32_t n, const uint32_t *c, double tau, const double *LL, const double *LU,
@@ -170,14 +173,17 @@ hipError_t alloc_budget(int32_t n, const double *LL, const double *LU, hipStream
 
 // Vertex-diameter bracket by BFS sweeps on the device.
 hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, int64_t *vd_hi);
-// Exact vertex diameter (iFUB with multi-source BFS); with omega_only it
-// stops once both ends of [vd_lo, vd_hi] give the same omega.  witness: a
-// vertex (caller id) whose eccentricity is vd_lo - 1.
+// Exact vertex diameter (eccentricity-bound refinement); with omega_only it
+// stops once both ends of [vd_lo, vd_hi] give the same omega; after
+// max_bfs BFS runs it stops with the bracket it has.  witness: a vertex
+// (caller id) whose eccentricity is vd_lo - 1.
 hipError_t device_exact_vd(const DevGraph &g, hipStream_t st, bool omega_only, double eps, double delta,
-                           int64_t *vd_lo, int64_t *vd_hi, int32_t *witness, int64_t *bfs_runs);
+                           int64_t max_bfs, int64_t *vd_lo, int64_t *vd_hi, int32_t *witness, int64_t *bfs_runs);
 
 // Learned prior.
 hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st);
+size_t features_workspace_bytes(const DevGraph &g);
+hipError_t launch_features_ws(const DevGraph &g, float *out, void *ws, hipStream_t st);
 hipError_t launch_normalize(int32_t n, float *x, const float *norm, hipStream_t st);
 hipError_t launch_mlp_forward(const float *params, const float *x, int64_t rows, float *y,
                               hipStream_t st);

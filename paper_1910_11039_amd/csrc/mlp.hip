@@ -542,18 +542,24 @@ int blocks_for_rows(int64_t rows)
 
 size_t mlp_scratch_floats(int64_t rows) { return (size_t)blocks_for_rows(rows) * PSTRIDE; }
 
-hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st)
+// Workspace of the feature pass: the prefix of the long rows' pieces, the
+// tier boundaries and the pieces' partial sums.  Long rows have more than
+// FPIECE entries each, so there are at most nnz / FPIECE of them and at
+// most 2 nnz / FPIECE + 1 pieces.
+size_t features_workspace_bytes(const DevGraph &g)
 {
-    hipError_t e;
-    // long rows: every such row has more than FPIECE entries, so there are
-    // at most nnz / FPIECE of them and at most 2 nnz / FPIECE + 1 pieces
     const int64_t hmax = g.nnz / FPIECE + 1, pmax = 2 * (g.nnz / FPIECE) + 1;
-    int64_t *pref = nullptr;
-    int32_t *H = nullptr;      // {first vertex of at most FPIECE entries, of at most FSHORT}
-    double2 *part = nullptr;
-    if ((e = hipMallocAsync((void **)&pref, sizeof(int64_t) * (size_t)(hmax + 1), st)) != hipSuccess) return e;
-    if ((e = hipMallocAsync((void **)&H, sizeof(int32_t) * 2, st)) != hipSuccess) return e;
-    if ((e = hipMallocAsync((void **)&part, sizeof(double2) * (size_t)pmax, st)) != hipSuccess) return e;
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    return up(sizeof(int64_t) * (size_t)(hmax + 1)) + 256 + up(sizeof(double2) * (size_t)pmax);
+}
+
+hipError_t launch_features_ws(const DevGraph &g, float *out, void *ws, hipStream_t st)
+{
+    const int64_t hmax = g.nnz / FPIECE + 1;
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    int64_t *pref = (int64_t *)ws;
+    int32_t *H = (int32_t *)((char *)ws + up(sizeof(int64_t) * (size_t)(hmax + 1)));  // tier boundaries
+    double2 *part = (double2 *)((char *)H + 256);
     hipLaunchKernelGGL(k_feat_pieces, dim3(1), dim3(1024), 0, st, g, pref, H);
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + 255) / 256, 8192));
     hipLaunchKernelGGL(k_features_short, dim3((unsigned)blocks), dim3(256), 0, st, g, H, out);
@@ -561,10 +567,17 @@ hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st)
     hipLaunchKernelGGL(k_features, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, H, out);
     hipLaunchKernelGGL(k_feat_sum, dim3(2048), dim3(256), 0, st, g, pref, H, part);
     hipLaunchKernelGGL(k_feat_combine, dim3(64), dim3(256), 0, st, g, pref, H, part, out);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    (void)hipFreeAsync(pref, st);
-    (void)hipFreeAsync(H, st);
-    return hipFreeAsync(part, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st)
+{
+    void *ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, features_workspace_bytes(g), st);
+    if (e != hipSuccess) return e;
+    e = launch_features_ws(g, out, ws, st);
+    const hipError_t f = hipFreeAsync(ws, st);
+    return e != hipSuccess ? e : f;
 }
 
 hipError_t launch_normalize(int32_t n, float *x, const float *norm, hipStream_t st)

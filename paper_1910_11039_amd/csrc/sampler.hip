@@ -1154,10 +1154,13 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
     if (a.stop_flag && __hip_atomic_load(a.stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     uint64_t first = a.first, count = a.count;
     uint32_t *sf = a.sf[0];
-    if (a.dev_range) {
-        first = a.dev_range[0];
-        count = a.dev_range[1];
-        sf = a.sf[a.dev_range[2] & 1];
+    // a replayed graph reads the run's seed from the device (its launch
+    // arguments were fixed when it was captured)
+    const uint64_t seed = a.dev_seed ? *a.dev_seed : a.seed;
+    if (a.dev_epoch) {
+        const unsigned long long k = *a.dev_epoch;
+        first = k * a.E;
+        count = first < a.cap ? (a.cap - first < a.E ? a.cap - first : a.E) : 0;
     }
     const int32_t n = a.g.n;
     const size_t slot = blockIdx.x;
@@ -1188,7 +1191,7 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
         int attempts = 0;
         if (tid == 0) {
             SampleDraws dr;
-            dr.init(a.seed, a.stream, idx);
+            dr.init(seed, a.stream, idx);
             const uint64_t u0 = dr.get(0), u1 = dr.get(1);
             const int32_t s = (int32_t)__umul64hi(u0, (uint64_t)n);
             int32_t t = (int32_t)__umul64hi(u1, (uint64_t)(n - 1));
@@ -1322,7 +1325,7 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
         t_mark = wall_clock64();
         {
             SampleDraws dr;
-            dr.init(a.seed, a.stream, idx);
+            dr.init(seed, a.stream, idx);
             const uint64_t u2 = dr.get(2);
             choose_meet<BS>(sm, c, m, u2, gacc);
         }
@@ -1363,7 +1366,7 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                 }
             }
             SampleDraws dr;
-            dr.init(a.seed, a.stream, idx);
+            dr.init(seed, a.stream, idx);
             const int32_t cap = (int32_t)(sizeof(sm.e.u) / sizeof(sm.e.u[0])) / WALKERS;
             for (int side = (WALKERS == 2 ? wid : 0); side < (WALKERS == 2 ? wid + 1 : 2); ++side) {
                 // draws 3, 4, ... go to the s side first, then to the t side

@@ -284,10 +284,25 @@ def test_step_epoch_and_omega_cap(ctx, oracle):
     assert S.result().stop_reason in (0, K.KAD_STOP_OMEGA)
 
 
-def test_graph_run_matches_oracle(ctx, oracle):
-    """Epochs replayed from a captured hipGraph (single stream) give the
-    oracle's run: counters, tau and stop epoch."""
-    _explicit_run(ctx, oracle, gg.rmat(12, 16, 5), 0.02, 512, use_graphs=1)
+@pytest.mark.parametrize("pools", [1, 2, 4])
+def test_graph_run_matches_oracle(ctx, oracle, pools):
+    """The pooled epoch schedule replayed from a captured hipGraph (epochs
+    dealt to 1, 2 or 4 pools and streams, each pool's epoch read on the
+    device), timing on, twice in a row: both runs give the oracle's run
+    (counters, tau, stop epoch)."""
+    g = gg.rmat(12, 16, 5)
+    G = upload(ctx, g)
+    omega = oracle.omega_bracket(*oracle.vd_bracket(g), 0.02, 0.1)
+    L0, _ = oracle.uniform_delta(g.n, 0.1)
+    d = np.exp(-L0)
+    S = K.Sampler(G, seed=1, epsilon=0.02, delta=0.1, epoch_size=512, omega_override=omega,
+                  alloc_mode=K.KAD_ALLOC_EXPLICIT, use_graphs=1, pools=pools, slots=40, timing=1)
+    S.set_delta(d, d)
+    L = oracle.neglog(d)
+    for seed in (1, 2):
+        S.reset(seed)
+        r, _ = _run_and_compare(S, g, oracle, omega, 0.02, 512, L, L.copy(), seed=seed)
+        assert r.pools == pools
 
 
 @pytest.mark.parametrize("pools", [1, 2, 4])
