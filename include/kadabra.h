@@ -209,6 +209,23 @@ kad_status kad_fetch_calibration(const kad_sampler *s, uint32_t *h_cprime, uint6
 kad_status kad_count_samples(kad_sampler *s, uint64_t stream, uint64_t first, uint64_t count,
                              uint32_t *h_c);
 
+/* kad_count_samples_noalloc: for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Adds the counters of samples [first, first+count) of
+ * Philox stream (seed, stream) into d_c (uint32[n], device memory owned by
+ * the caller, indexed by the caller's vertex ids); sigma_mode is
+ * KAD_SIGMA_AUTO or KAD_SIGMA_FP.  The same counts as kad_count_samples.
+ * Calls no allocator: the samplers' visited state lives in a static device
+ * scratch of KAD_NOALLOC_SCRATCH_BYTES per GPU (held until the process
+ * ends), cleared by a kernel at the start of every call.  A graph whose one
+ * sample slot (24 n + 16 min(n, 65536) + 4 bytes) does not fit returns
+ * KAD_EOVERFLOW.  Every call on one GPU shares that GPU's scratch: calls
+ * that overlap on one GPU (from several threads or streams) race.
+ * Synchronous on the context's stream. */
+#define KAD_NOALLOC_SCRATCH_BYTES (64ull << 20)
+kad_status kad_count_samples_noalloc(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint64_t stream,
+                                     uint64_t first, uint64_t count, int32_t sigma_mode, uint32_t *d_c);
+
 /* kad_sample_paths: run samples [first, first+count) of `stream` and
  * return each path s..t: h_paths int32[count][max_len] (entries past d are
  * -1), h_info int64[count][14] = {s, t, d, w, fp_mode, meet_size, steps,

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <functional>
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -39,6 +40,32 @@ double now_ms()
 }
 
 }  // namespace
+
+// Device scratch of kad_count_samples_noalloc: a file-scope array, one copy
+// per GPU, held until the process ends.  Its device address is taken once
+// per device (kad_create) with hipGetSymbolAddress; host code uses only that
+// address, never the array's name.
+namespace {
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)KAD_NOALLOC_SCRATCH_BYTES;
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[MAX_DEVICES];
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+// Called with `device` current.
+static kad_status scratch_init(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES) return fail(KAD_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return KAD_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(KAD_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = (unsigned char *)p;
+    return KAD_OK;
+}
 
 struct kad_ctx {
     int device;
@@ -138,6 +165,10 @@ extern "C" kad_status kad_create(int device, void *hip_stream, kad_ctx **out)
     HIPCHK(hipGetDeviceProperties(&prop, device));
     if (std::string(prop.gcnArchName).find("gfx950") == std::string::npos)
         return fail(KAD_EDEVICE, std::string("kernels are built for gfx950, device is ") + prop.gcnArchName);
+    {
+        const kad_status sr = scratch_init(device);
+        if (sr != KAD_OK) return sr;
+    }
     kad_ctx *c = new kad_ctx();
     c->device = device;
     c->cu_count = prop.multiProcessorCount;
@@ -1370,6 +1401,83 @@ extern "C" kad_status kad_count_samples(kad_sampler *s, uint64_t stream, uint64_
     r = copy_to_caller(s->g, s->scratch_counts, tmp.data(), st);
     if (r != KAD_OK) return r;
     for (int32_t v = 0; v < n; ++v) h_c[v] += tmp[v];
+    return KAD_OK;
+}
+
+// The no-allocation variant of kad_count_samples.  The slots' visited state
+// (records, frontier queues, meet lists, meet accumulators, stamps), the
+// sample counter and the statistics are carved out of the device scratch;
+// everything the launch uses is cleared by a kernel first, since the
+// scratch keeps the last call's contents and a record left with a stamp
+// the next call reuses would be taken for one of its own.
+extern "C" kad_status kad_count_samples_noalloc(kad_ctx *ctx, const kad_graph *g, uint64_t seed,
+                                                uint64_t stream, uint64_t first, uint64_t count,
+                                                int32_t sigma_mode, uint32_t *d_c)
+{
+    if (!ctx || !g || !d_c) return fail(KAD_EINVAL, "null argument");
+    if (sigma_mode != KAD_SIGMA_AUTO && sigma_mode != KAD_SIGMA_FP) return fail(KAD_EINVAL, "bad sigma_mode");
+    if (first + count < first) return fail(KAD_EINVAL, "sample range wraps around");
+    if (g->device != ctx->device) return fail(KAD_EINVAL, "graph and context are on different devices");
+    if (count == 0) return KAD_OK;
+    HIPCHK(hipSetDevice(ctx->device));
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = g_scratch_ptr[ctx->device];
+    }
+    if (!base) return fail(KAD_ESTATE, "device scratch not initialised for this device");
+    const size_t n = (size_t)g->n;
+    const int block = 256;
+    const int32_t macc_cap = (int32_t)std::min<size_t>(n, (size_t)1 << 16);
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t fixed = up(sizeof(SampleStats)) + up(sizeof(unsigned long long));
+    // per slot: records, queue, meet list, meet accumulators, stamp (each
+    // array 256-byte aligned per slot count below)
+    const size_t per_slot = n * (sizeof(Rec) + 2 * sizeof(int32_t)) + 16 * (size_t)macc_cap + sizeof(uint32_t);
+    size_t slots = NOALLOC_SCRATCH_BYTES > fixed + 5 * 256 ? (NOALLOC_SCRATCH_BYTES - fixed - 5 * 256) / per_slot : 0;
+    if (slots < 1)
+        return fail(KAD_EOVERFLOW, "graph too large for kad_count_samples_noalloc: one slot needs " +
+                                       std::to_string(per_slot) + " bytes, the scratch holds " +
+                                       std::to_string(NOALLOC_SCRATCH_BYTES));
+    slots = std::min<size_t>(slots, (size_t)ctx->cu_count * (size_t)sampler_blocks_per_cu(block));
+    slots = std::min<size_t>(slots, count);
+    unsigned char *p = base;
+    auto take = [&](size_t bytes) { unsigned char *q = p; p += up(bytes); return q; };
+    SampleStats *stats = (SampleStats *)take(sizeof(SampleStats));
+    unsigned long long *work = (unsigned long long *)take(sizeof(unsigned long long));
+    uint32_t *stamps = (uint32_t *)take(4 * slots);
+    Rec *recs = (Rec *)take(sizeof(Rec) * n * slots);
+    int32_t *queues = (int32_t *)take(4 * n * slots);
+    int32_t *mbufs = (int32_t *)take(4 * n * slots);
+    unsigned long long *macc = (unsigned long long *)take(16 * (size_t)macc_cap * slots);
+    const size_t used = (size_t)(p - base);
+    if (used > NOALLOC_SCRATCH_BYTES) return fail(KAD_EOVERFLOW, "scratch layout exceeds the scratch");
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_zero_words((uint32_t *)base, used / 4, st));
+    SampleLaunch a;
+    memset(&a, 0, sizeof(a));
+    a.g = g->dev();
+    a.seed = seed;
+    a.stream = stream;
+    a.first = first;
+    a.count = count;
+    a.sf[0] = a.sf[1] = d_c;
+    a.recs = recs;
+    a.queues = queues;
+    a.mbufs = mbufs;
+    a.macc = macc;
+    a.macc_cap = macc_cap;
+    a.stamps = stamps;
+    a.work_ctr = work;
+    a.stats = stats;
+    a.sigma_fp = sigma_mode == KAD_SIGMA_FP;
+    a.count_map = g->d_orig;
+    HIPCHK(launch_sampler(a, (int)slots, block, st));
+    SampleStats h;
+    HIPCHK(hipMemcpyAsync(&h, stats, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h.error == 1) return fail(KAD_ENOTCONNECTED, "a sampled pair has no path: graph not connected");
+    if (h.error != 0) return fail(KAD_EDEVICE, "internal error: a path choice found no candidate");
     return KAD_OK;
 }
 

@@ -92,6 +92,7 @@ SIGNATURES = [
     ("kad_fetch_calibration", C.c_int, [_vp, _vp, _P(_u64), _P(_dbl)]),
     ("kad_count_samples", C.c_int, [_vp, _u64, _u64, _u64, _vp]),
     ("kad_sample_paths", C.c_int, [_vp, _u64, _u64, _u32, _i32, _vp, _vp]),
+    ("kad_count_samples_noalloc", C.c_int, [_vp, _vp, _u64, _u64, _u64, _u64, _i32, _vp]),
     ("kad_philox", C.c_int, [_vp, _u64, _u64, _u64, _u32, _u32, _vp]),
     ("kad_vd_bracket", C.c_int, [_vp, _vp, _P(_i64), _P(_i64)]),
     ("kad_omega", _dbl, [_i64, _i64, _dbl, _dbl]),
@@ -258,6 +259,11 @@ def kad_count_samples(s, stream: int, first: int, count: int, n: int) -> np.ndar
     c = np.zeros(n, dtype=np.uint32)
     _check(lib().kad_count_samples(s, stream, first, count, _p(c)))
     return c
+
+
+def kad_count_samples_noalloc(ctx, g, seed: int, stream: int, first: int, count: int, sigma_mode: int,
+                              d_c: int):
+    _check(lib().kad_count_samples_noalloc(ctx, g, seed, stream, first, count, sigma_mode, C.c_void_p(d_c)))
 
 
 def kad_sample_paths(s, stream: int, first: int, count: int, max_len: int):
