@@ -112,6 +112,7 @@ struct kad_sampler {
     // device state
     uint32_t *c, *sf[4], *cprime, *scratch_counts;
     double *LL, *LU, *lo_hi, *partials, *prior;
+    double *LU_own;   // LU's buffer: LU points at LL when the allocation makes delta_L = delta_U
     Rec *recs;
     int32_t *queues, *mbufs;
     unsigned long long *macc;
@@ -376,7 +377,7 @@ static void free_sampler(kad_sampler *s)
     if (s->mlp_dev) (void)hipFree(s->mlp_dev);
     if (s->feat_ws) (void)hipFree(s->feat_ws);
     if (s->h_status) (void)hipHostFree(s->h_status);
-    void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->sf[2], s->sf[3], s->cprime, s->scratch_counts, s->LL, s->LU, s->lo_hi, s->macc,
+    void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->sf[2], s->sf[3], s->cprime, s->scratch_counts, s->LL, s->LU_own, s->lo_hi, s->macc,
                     s->partials, s->prior, s->recs, s->queues, s->mbufs, s->stamps, s->work_ctr, s->pool_epoch,
                     s->stats, s->cal_stats, s->es, s->hist};
     for (void *p : ptrs)
@@ -405,8 +406,10 @@ static kad_status reset_epochs(kad_sampler *s)
     init.range[1] = std::min<unsigned long long>(s->E, s->cap);
     init.range[2] = 0;
     HIPCHK(hipMemcpyAsync(s->es, &init, sizeof(init), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemsetAsync(s->c, 0, sizeof(uint32_t) * s->g->n, st));
-    for (int i = 0; i < s->P; ++i) HIPCHK(hipMemsetAsync(s->sf[i], 0, sizeof(uint32_t) * s->g->n, st));
+    // n-sized clears by a kernel: the runtime's fill ran at a tenth of the
+    // HBM bandwidth on these sizes
+    HIPCHK(launch_zero_words(s->c, (size_t)s->g->n, st));
+    for (int i = 0; i < s->P; ++i) HIPCHK(launch_zero_words(s->sf[i], (size_t)s->g->n, st));
     HIPCHK(hipMemsetAsync(s->work_ctr, 0, 4 * sizeof(unsigned long long), st));
     {
         // pool p starts at epoch p; the run's seed for replayed graphs
@@ -634,7 +637,7 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
               alloc((void **)&s->sf[1], 4ull * n) && alloc((void **)&s->sf[2], 4ull * n) &&
               alloc((void **)&s->sf[3], 4ull * n) && alloc((void **)&s->cprime, 4ull * n) &&
               alloc((void **)&s->scratch_counts, 4ull * n) && alloc((void **)&s->LL, 8ull * n) &&
-              alloc((void **)&s->LU, 8ull * n) && alloc((void **)&s->lo_hi, 64) &&
+              alloc((void **)&s->LU_own, 8ull * n) && alloc((void **)&s->lo_hi, 64) &&
               alloc((void **)&s->partials, 8 * alloc_partials(n)) && alloc((void **)&s->prior, 8ull * n) &&
               alloc((void **)&s->recs, sizeof(Rec) * (size_t)n * pools_alloc * s->slots) &&
               alloc((void **)&s->queues, 4ull * n * pools_alloc * s->slots) &&
@@ -652,6 +655,7 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
         free_sampler(s);
         return fail(KAD_ENOMEM, "sampler allocation failed");
     }
+    s->LU = s->LU_own;
     s->sts[0] = st;
     for (int i = 0; i < s->P; ++i) {
         if (i > 0) HIPCHK(hipStreamCreate(&s->sts[i]));
@@ -788,6 +792,7 @@ extern "C" kad_status kad_set_delta(kad_sampler *s, const double *h_delta_L, con
     }
     if (!(sum < 0.5L * (long double)s->o.delta))
         return fail(KAD_EINVAL, "sum of delta_L + delta_U must stay below delta / 2");
+    s->LU = s->LU_own;   // delta_U may differ from delta_L here
     // L = ln(1/delta) is taken once per vertex on the host in FP64 (the
     // C library's log), in the caller's numbering, then mapped in
     std::vector<double> Lh((size_t)n);
@@ -885,6 +890,9 @@ static kad_status ensure_delta(kad_sampler *s, const std::function<kad_status()>
     a.beta = 1e-3;
     a.lo_hi = s->lo_hi;
     a.partials = s->partials;
+    // the computed allocations have delta_L = delta_U: one array serves
+    // both bounds, and the merges read it once
+    s->LU = s->LL;
     a.LL = s->LL;
     a.LU = s->LU;
     bool learned = false;
@@ -916,7 +924,7 @@ static kad_status ensure_delta(kad_sampler *s, const std::function<kad_status()>
             }
             s->cal_hist_top = top;
         }
-        HIPCHK(hipMemsetAsync(s->cprime, 0, 4ull * n, cst));
+        HIPCHK(launch_zero_words(s->cprime, (size_t)n, cst));
         HIPCHK(hipMemsetAsync(s->cal_stats, 0, sizeof(SampleStats), cst));
         HIPCHK(hipMemsetAsync(s->cal_hist, 0, sizeof(uint32_t) * ((size_t)top + 1), cst));
         kad_status r = count_into(s, KAD_STREAM_CALIB, 0, s->tau0, s->cprime, nullptr, nullptr, 0, s->cal_stats, cst,

@@ -72,8 +72,10 @@ __global__ __launch_bounds__(MB) void k_merge_stop(int32_t n, uint32_t *c, uint3
         c[v] = cv;
         sf[v] = 0;
         const double bt = (double)cv / tau;
-        const double f = fval(bt, LL[v], omega, tau);
-        const double g = gval(bt, LU[v], omega, tau);
+        const double ll = LL[v];
+        const double lu = (LU == LL) ? ll : LU[v];   // one array when delta_L = delta_U
+        const double f = fval(bt, ll, omega, tau);
+        const double g = gval(bt, lu, omega, tau);
         ok &= (f < eps && g < eps) ? 1 : 0;
         mf = f > mf ? f : mf;
         mg = g > mg ? g : mg;
