@@ -128,14 +128,18 @@ def summarize(res, walls):
             "epochs_per_run": float(np.mean([r["epochs"] for r in res])),
             "phase_ms": {k: round(float(np.mean([r[k] for r in res])), 3)
                          for k in ("t_omega_ms", "t_alloc_ms", "t_ads_ms")},
-            "launch": {k: int(res[-1][k]) for k in ("epoch_size", "slots", "block_size", "pools")}}
+            "launch": {k: int(res[-1][k]) for k in ("epoch_size", "slots", "block_size", "pools",
+                                                    "visited_mode", "visited_log2")},
+            "deferred_per_run": float(np.mean([r["deferred"] for r in res]))}
 
 
 def learned_vs_plain(K, G, eps, steps, warmup, args):
     """Both arms on the same graph, seeds and clock."""
     from paper_1910_11039_amd import learned as LRN
     shape = dict(epoch_size=args.epoch_size, slots=args.slots, block_size=args.block,
-                 use_graphs=args.use_graphs, timing=1, exact_diameter=getattr(args, "exact_diameter", 0))
+                 use_graphs=args.use_graphs, timing=1, exact_diameter=getattr(args, "exact_diameter", 0),
+                 pools=getattr(args, "pools", 0), visited_mode=getattr(args, "visited", 0),
+                 visited_log2=getattr(args, "visited_log2", 0))
     S, (pres, pwalls) = run_arm(K, G, eps, steps, warmup, **shape)
     S.close()   # frees the plain arm's visited state before the learned arm sizes its own
     params, norm = LRN.load()
@@ -154,12 +158,13 @@ def learned_vs_plain(K, G, eps, steps, warmup, args):
     return out, pres, pwalls
 
 
-def roofline_leg(K, G, eps, workload, steps=3, block=0, epoch=0):
+def roofline_leg(K, G, eps, workload, steps=3, block=0, epoch=0, visited=0, visited_log2=0):
     """The sampler's roofline with one slot pool, so that a launch's
     duration is the kernel's own time (with several pools, launches of
     neighbouring epochs share the GPU).  achieved = algorithmic bytes per
     launch / average launch duration (HIP events on the launch stream)."""
-    S = K.Sampler(G, seed=1, epsilon=eps, delta=0.1, timing=1, pools=1, block_size=block, epoch_size=epoch)
+    S = K.Sampler(G, seed=1, epsilon=eps, delta=0.1, timing=1, pools=1, block_size=block, epoch_size=epoch,
+                  visited_mode=visited, visited_log2=visited_log2)
     res, _ = arm_steps(S, steps, 1)
     S.close()
     agg = {k: sum(r[k] for r in res) for k in WORK_KEYS}
@@ -175,7 +180,8 @@ def roofline_leg(K, G, eps, workload, steps=3, block=0, epoch=0):
             "kernel": "k_sample (one slot pool: launch time is the kernel's own)",
             "launch_ms": round(per_launch_s * 1e3, 4), "launches": int(launches),
             "bytes_per_launch": int(per_launch_bytes),
-            "launch_shape": {k: int(res[0][k]) for k in ("epoch_size", "slots", "block_size", "pools")}}
+            "launch_shape": {k: int(res[0][k]) for k in ("epoch_size", "slots", "block_size", "pools",
+                                                         "visited_mode", "visited_log2")}}
 
 
 def aggregate_rate(res, walls):
@@ -301,6 +307,9 @@ def main():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--pools", type=int, default=0)
+    ap.add_argument("--visited", type=int, default=0, choices=(0, 1, 2),
+                    help="per-sample visited state: 0 auto, 1 dense, 2 hashed")
+    ap.add_argument("--visited-log2", type=int, default=0, help="hashed table size (0: auto)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-allocation arm")
     ap.add_argument("--profile-leg", action="store_true",
                     help="only the one-pool roofline leg (the command the committed profiles run)")
@@ -342,12 +351,14 @@ def main():
         args.epoch_size = FIXED_EPOCH.get(args.workload, 0)
 
     if args.profile_leg:
-        roof = roofline_leg(K, G, eps, wname, steps=args.steps, block=args.block, epoch=args.epoch_size)
+        roof = roofline_leg(K, G, eps, wname, steps=args.steps, block=args.block, epoch=args.epoch_size,
+                            visited=args.visited, visited_log2=args.visited_log2)
         print(json.dumps({"roofline": roof}), flush=True)
         return
 
     shape = dict(epoch_size=args.epoch_size, slots=args.slots, block_size=args.block,
-                 use_graphs=args.use_graphs, timing=1, pools=args.pools, exact_diameter=args.exact_diameter)
+                 use_graphs=args.use_graphs, timing=1, pools=args.pools, exact_diameter=args.exact_diameter,
+                 visited_mode=args.visited, visited_log2=args.visited_log2)
     if args.no_learned:
         S, (pres, pwalls) = run_arm(K, G, eps, args.steps, args.warmup, **shape)
         S.close()
@@ -361,7 +372,8 @@ def main():
     r0 = pres[0]
     # the one-pool leg in the plain arm's launch shape (the shape the
     # committed counter profile was taken with)
-    roof = roofline_leg(K, G, eps, wname, block=r0["block_size"], epoch=r0["epoch_size"])
+    roof = roofline_leg(K, G, eps, wname, block=r0["block_size"], epoch=r0["epoch_size"],
+                        visited=r0["visited_mode"], visited_log2=r0["visited_log2"])
     roof["aggregate"] = aggregate_rate(pres, pwalls)
     roof["copy_kernel_GBps_measured"] = copy_bandwidth()
     log(f"roofline leg: {roof['achieved']} GB/s per launch; copy {roof['copy_kernel_GBps_measured']} GB/s")
@@ -409,7 +421,8 @@ def main():
                    "epsilon": eps, "delta": 0.1,
                    "value_arm": "plain (calibration samples)",
                    "epoch_size": r0["epoch_size"], "slots": r0["slots"], "block_size": r0["block_size"],
-                   "pools": r0["pools"], "omega": r0["omega"], "vd_bracket": [r0["vd_lo"], r0["vd_hi"]]},
+                   "pools": r0["pools"], "visited_mode": r0["visited_mode"], "visited_log2": r0["visited_log2"],
+                   "omega": r0["omega"], "vd_bracket": [r0["vd_lo"], r0["vd_hi"]]},
         "time_to_stop_ms": round(1e3 * float(np.mean(pwalls)), 3),
         "adaptive_samples_per_run": float(np.mean([r["tau"] for r in pres])),
         "calibration_samples_per_run": float(np.mean([r["tau0"] for r in pres])),

@@ -75,6 +75,9 @@ enum { KAD_SIGMA_AUTO = 0, KAD_SIGMA_FP = 1 };
 
 enum { KAD_STOP_NONE = 0, KAD_STOP_COND = 1, KAD_STOP_OMEGA = 2 };
 
+/* Per-sample visited state of the sampler's workgroups (kad_opts). */
+enum { KAD_VISITED_AUTO = 0, KAD_VISITED_DENSE = 1, KAD_VISITED_HASHED = 2 };
+
 enum { KAD_GRAPH_VALIDATE = 1u };
 
 /* kad_create: bind a context to HIP device `device` and stream
@@ -120,6 +123,14 @@ typedef struct {
                                   /* kad_exact_vd until its ends give one omega   */
                                   /* (at most 64 BFS runs, then its upper end);   */
                                   /* 0: from the three-sweep bracket              */
+    int32_t visited_mode;         /* per-sample visited state: 1 dense (a record  */
+                                  /* per vertex in every slot), 2 hashed (a table */
+                                  /* of 2^visited_log2 buckets per slot; samples  */
+                                  /* that would fill it over 3/4 are finished on  */
+                                  /* a few dense slots per pool); 0 = auto: dense */
+    int32_t visited_log2;         /* hashed table size; 0 = the power of two at   */
+                                  /* or above n / 32 within [2^16, 2^22];         */
+                                  /* else within [10, 26]                         */
 } kad_opts;
 
 typedef struct {
@@ -146,6 +157,10 @@ typedef struct {
                                   /* ones after the stop epoch included           */
     int32_t block_size;           /* workgroup size used by the sampler           */
     int32_t pools;                /* slot pools (epochs overlapped across them)   */
+    int32_t visited_mode;         /* 1 dense, 2 hashed                            */
+    int32_t visited_log2;         /* hashed table size used (0 when dense)        */
+    int64_t deferred;             /* samples the hashed launches handed to the    */
+                                  /* dense fallback                               */
 } kad_result;
 
 /* kad_sampler_init: allocate the sampler state for graph g and options o.

@@ -151,7 +151,33 @@ struct kad_sampler {
     bool have_graph;
     bool tune_block;
     double tune_rate[3];     // samples/s of the trial per candidate block size
+    // visited state: dense (a record per vertex in every slot) or hashed
+    // (a table of 2^vlog2 buckets per slot; a sample that would fill more
+    // than 3/4 of it is finished by a second launch on `fb` dense slots of
+    // the pool, from the pool's defer list)
+    bool sparse = false;
+    uint32_t vlog2 = 0;
+    size_t slot_n = 0;            // entries per slot in recs, queues and mbufs
+    int32_t claim_limit = 0;
+    int fb = 0;
+    Rec *fb_recs = nullptr;
+    int32_t *fb_queues = nullptr, *fb_mbufs = nullptr;
+    unsigned long long *fb_macc = nullptr;
+    uint32_t *fb_stamps = nullptr;
+    uint32_t *defer = nullptr;    // KAD_DEFER_LISTS lists of defer_cap sample indices
+    uint32_t defer_cap = 0;
 };
+
+namespace {
+// Sample counters in work_ctr: [0, 4) the pools' epochs, [4] the
+// non-adaptive launches, then per defer list i a (deferred, fallback taken)
+// pair at [8 + 2i]: lists 0..3 belong to the pools, list 4 to the
+// non-adaptive launches.
+constexpr int KAD_DEFER_LISTS = 5;
+constexpr size_t KAD_WORK_CTRS = 8 + 2 * KAD_DEFER_LISTS;
+constexpr uint32_t KAD_DEFER_CAP = 1u << 16;   // samples a hashed launch may defer: its count at most
+constexpr int KAD_FB_SLOTS = 8;                 // dense fallback slots per pool
+}  // namespace
 
 extern "C" const char *kad_last_error(void) { return g_err.c_str(); }
 
@@ -379,7 +405,8 @@ static void free_sampler(kad_sampler *s)
     if (s->h_status) (void)hipHostFree(s->h_status);
     void *ptrs[] = {s->c, s->sf[0], s->sf[1], s->sf[2], s->sf[3], s->cprime, s->scratch_counts, s->LL, s->LU_own, s->lo_hi, s->macc,
                     s->partials, s->prior, s->recs, s->queues, s->mbufs, s->stamps, s->work_ctr, s->pool_epoch,
-                    s->stats, s->cal_stats, s->es, s->hist};
+                    s->stats, s->cal_stats, s->es, s->hist, s->fb_recs, s->fb_queues, s->fb_mbufs, s->fb_macc,
+                    s->fb_stamps, s->defer};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->h_es) (void)hipHostFree(s->h_es);
@@ -466,14 +493,14 @@ static kad_status autotune(kad_sampler *s)
                 int fastest = 0;
                 for (int i = 1; i < 3; ++i)
                     if (s->tune_rate[i] > s->tune_rate[fastest]) fastest = i;
-                const int sl = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(cands[fastest]));
+                const int sl = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(cands[fastest], s->sparse));
                 if ((double)sl / s->tune_rate[fastest] > 0.010) break;
                 short_samples = true;
                 best = -1.0;
             }
             for (int i = 0; i < 3; ++i) {
                 const int b = cands[i];
-                const int sl = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(b));
+                const int sl = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(b, s->sparse));
                 const uint64_t trial = pass == 0 ? N : 16ull * (uint64_t)sl;
                 s->block = b;
                 s->slots = sl;
@@ -506,7 +533,7 @@ static kad_status autotune(kad_sampler *s)
             if (s->tune_rate[2] >= 0.95 * best) pick = 2;
         }
         best_b = cands[pick];
-        best_slots = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(cands[pick]));
+        best_slots = std::min(all_slots, s->ctx->cu_count * sampler_blocks_per_cu(cands[pick], s->sparse));
         s->block = best_b;
         s->slots = best_slots;
         HIPCHK(hipMemsetAsync(s->stats, 0, sizeof(SampleStats), st));
@@ -575,55 +602,98 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     // start once resident ones exit, so the default is one full wave of
     // them.  With block_size = 0 the pools are sized for the largest wave
     // among the candidate block sizes and the autotuner picks one below.
-    const size_t per_slot = (size_t)n * (sizeof(Rec) + 2 * sizeof(int32_t)) +
-                            16ull * (size_t)std::min<int64_t>(n, 1 << 16);
+    if (o->visited_mode < 0 || o->visited_mode > 2) {
+        delete s;
+        return fail(KAD_EINVAL, "visited_mode must be 0 (auto), 1 (dense) or 2 (hashed)");
+    }
+    if (o->visited_log2 != 0 && (o->visited_log2 < 10 || o->visited_log2 > 26)) {
+        delete s;
+        return fail(KAD_EINVAL, "visited_log2 must be 0 (auto) or within [10, 26]");
+    }
+    const size_t macc_bytes = 16ull * (size_t)std::min<int64_t>(n, 1 << 16);
+    const size_t per_dense = (size_t)n * (sizeof(Rec) + 2 * sizeof(int32_t)) + macc_bytes;
+    // hashed table: 2^vlog2 buckets, by default the power of two at or above
+    // n / 32 within [2^16, 2^22]
+    uint32_t vlog2 = (uint32_t)o->visited_log2;
+    if (vlog2 == 0) {
+        vlog2 = 16;
+        while (vlog2 < 22 && ((size_t)1 << vlog2) < (size_t)n / 32) ++vlog2;
+    }
+    const size_t per_sparse = ((size_t)1 << vlog2) * (sizeof(Rec) + 2 * sizeof(int32_t)) + macc_bytes;
     size_t free_b = 0, total_b = 0;
     HIPCHK(hipMemGetInfo(&free_b, &total_b));
     size_t budget = o->visited_budget_bytes ? (size_t)o->visited_budget_bytes : free_b / 4 * 3;
     s->tune_block = o->block_size == 0;
-    int want = 0;
-    if (o->slots > 0) {
-        want = o->slots;
-    } else if (!s->tune_block) {
-        want = ctx->cu_count * sampler_blocks_per_cu(block);
-    } else {
-        for (int b : {256, 512, 1024}) want = std::max(want, ctx->cu_count * sampler_blocks_per_cu(b));
-    }
-    const size_t fit = budget / per_slot;
-    if (fit < 1) {
-        delete s;
-        return fail(KAD_ENOMEM, "not even one sample slot fits the visited-state budget");
-    }
-    // pools: up to 4 while a full wave of slots fits each (epochs overlap
-    // across pools); when fewer than two full waves fit, two pools of half
-    // the slots (two concurrent epochs still cover every CU and fill each
-    // other's tails); a single pool only when even that does not fit
-    s->slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)want, std::min<size_t>(fit, 1 << 16)));
-    s->P = (int)std::max<size_t>(1, std::min<size_t>(4, fit / (size_t)s->slots));
-    if (s->P == 1 && o->slots <= 0 && o->pools != 1 && fit / 2 >= (size_t)std::max(1, ctx->cu_count / 2)) {
-        s->slots = (int)std::min<size_t>((size_t)s->slots, fit / 2);
-        s->P = 2;
-    }
+    auto full_wave = [&](bool sp) {
+        if (!s->tune_block) return ctx->cu_count * sampler_blocks_per_cu(block, sp);
+        int w = 0;
+        for (int b : {256, 512, 1024}) w = std::max(w, ctx->cu_count * sampler_blocks_per_cu(b, sp));
+        return w;
+    };
     if (o->pools < 0 || o->pools > 4) {
         delete s;
         return fail(KAD_EINVAL, "pools must be 0 (auto) or 1..4");
     }
-    if (o->pools > 0) {
-        if ((size_t)o->pools * (size_t)s->slots > fit) {
+    s->sparse = o->visited_mode == 2;
+    size_t pools_alloc = 0;
+    if (s->sparse) {
+        // every pool: a full wave of hashed slots, its dense fallback slots
+        // and its defer list; four pools (or the requested number), fewer
+        // when the budget does not hold them
+        const int want = o->slots > 0 ? o->slots : std::min(full_wave(true), 1 << 16);
+        const size_t pool_bytes = (size_t)want * per_sparse + (size_t)KAD_FB_SLOTS * per_dense;
+        int P = o->pools > 0 ? o->pools : 4;
+        while (o->pools == 0 && P > 1 && (size_t)P * pool_bytes > budget) --P;
+        if ((size_t)P * pool_bytes > budget) {
             delete s;
-            return fail(KAD_ENOMEM, "requested pools exceed the visited-state budget");
+            return fail(KAD_ENOMEM, "the hashed visited state of the requested pools and slots exceeds the budget");
         }
-        s->P = o->pools;
+        s->slots = want;
+        s->P = P;
+        s->cal_pool = ((size_t)(P + 1) * pool_bytes <= budget) ? P : 0;
+        s->vlog2 = vlog2;
+        s->slot_n = (size_t)1 << vlog2;
+        s->claim_limit = (int32_t)(s->slot_n / 4 * 3);
+        s->fb = KAD_FB_SLOTS;
+        s->defer_cap = KAD_DEFER_CAP;
+    } else {
+        const size_t per_slot = per_dense;
+        int want = 0;
+        if (o->slots > 0) want = o->slots;
+        else want = full_wave(false);
+        const size_t fit = budget / per_slot;
+        if (fit < 1) {
+            delete s;
+            return fail(KAD_ENOMEM, "not even one sample slot fits the visited-state budget");
+        }
+        // pools: up to 4 while a full wave of slots fits each (epochs overlap
+        // across pools); when fewer than two full waves fit, two pools of half
+        // the slots (two concurrent epochs still cover every CU and fill each
+        // other's tails); a single pool only when even that does not fit
+        s->slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)want, std::min<size_t>(fit, 1 << 16)));
+        s->P = (int)std::max<size_t>(1, std::min<size_t>(4, fit / (size_t)s->slots));
+        if (s->P == 1 && o->slots <= 0 && o->pools != 1 && fit / 2 >= (size_t)std::max(1, ctx->cu_count / 2)) {
+            s->slots = (int)std::min<size_t>((size_t)s->slots, fit / 2);
+            s->P = 2;
+        }
+        if (o->pools > 0) {
+            if ((size_t)o->pools * (size_t)s->slots > fit) {
+                delete s;
+                return fail(KAD_ENOMEM, "requested pools exceed the visited-state budget");
+            }
+            s->P = o->pools;
+        }
+        if (o->slots > 0 && s->slots < o->slots) {
+            delete s;
+            return fail(KAD_ENOMEM, "requested slots exceed the visited-state budget");
+        }
+        // the calibration (and the other non-adaptive launches) get a pool of
+        // their own when memory holds one, so that all P first epochs can run
+        // beside the calibration
+        s->cal_pool = ((size_t)(s->P + 1) * (size_t)s->slots <= fit) ? s->P : 0;
+        s->slot_n = (size_t)n;
     }
-    if (o->slots > 0 && s->slots < o->slots) {
-        delete s;
-        return fail(KAD_ENOMEM, "requested slots exceed the visited-state budget");
-    }
-    // the calibration (and the other non-adaptive launches) get a pool of
-    // their own when memory holds one, so that all P first epochs can run
-    // beside the calibration
-    s->cal_pool = ((size_t)(s->P + 1) * (size_t)s->slots <= fit) ? s->P : 0;
-    const size_t pools_alloc = (size_t)s->P + (s->cal_pool ? 1 : 0);
+    pools_alloc = (size_t)s->P + (s->cal_pool ? 1 : 0);
     s->E = o->epoch_size;
     s->inflight = o->epochs_in_flight > 0 ? o->epochs_in_flight : 4;
     s->macc_cap = (int32_t)std::min<int64_t>(n, 1 << 16);   // larger meet sets take the slow path
@@ -633,21 +703,29 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     auto alloc = [&](void **p, size_t bytes) {
         return hipMalloc(p, std::max<size_t>(bytes, 16)) == hipSuccess;
     };
+    const size_t sn = s->slot_n, nslots = pools_alloc * (size_t)s->slots, nfb = pools_alloc * (size_t)s->fb;
     bool ok = alloc((void **)&s->c, 4ull * n) && alloc((void **)&s->sf[0], 4ull * n) &&
               alloc((void **)&s->sf[1], 4ull * n) && alloc((void **)&s->sf[2], 4ull * n) &&
               alloc((void **)&s->sf[3], 4ull * n) && alloc((void **)&s->cprime, 4ull * n) &&
               alloc((void **)&s->scratch_counts, 4ull * n) && alloc((void **)&s->LL, 8ull * n) &&
               alloc((void **)&s->LU_own, 8ull * n) && alloc((void **)&s->lo_hi, 64) &&
               alloc((void **)&s->partials, 8 * alloc_partials(n)) && alloc((void **)&s->prior, 8ull * n) &&
-              alloc((void **)&s->recs, sizeof(Rec) * (size_t)n * pools_alloc * s->slots) &&
-              alloc((void **)&s->queues, 4ull * n * pools_alloc * s->slots) &&
-              alloc((void **)&s->mbufs, 4ull * n * pools_alloc * s->slots) &&
-              alloc((void **)&s->macc, 16ull * (size_t)s->macc_cap * pools_alloc * s->slots) &&
-              alloc((void **)&s->stamps, 4ull * pools_alloc * s->slots) && alloc((void **)&s->work_ctr, 64) &&
+              alloc((void **)&s->recs, sizeof(Rec) * sn * nslots) &&
+              alloc((void **)&s->queues, 4ull * sn * nslots) &&
+              alloc((void **)&s->mbufs, 4ull * sn * nslots) &&
+              alloc((void **)&s->macc, 16ull * (size_t)s->macc_cap * nslots) &&
+              alloc((void **)&s->stamps, 4ull * nslots) &&
+              alloc((void **)&s->work_ctr, sizeof(unsigned long long) * KAD_WORK_CTRS) &&
               alloc((void **)&s->pool_epoch, 64) &&
               alloc((void **)&s->stats, sizeof(SampleStats)) && alloc((void **)&s->cal_stats, sizeof(SampleStats)) &&
               alloc((void **)&s->es, sizeof(EpochState)) &&
               alloc((void **)&s->hist, epoch_hist_bytes() * s->hist_cap);
+    if (ok && s->sparse)
+        ok = alloc((void **)&s->fb_recs, sizeof(Rec) * (size_t)n * nfb) &&
+             alloc((void **)&s->fb_queues, 4ull * n * nfb) && alloc((void **)&s->fb_mbufs, 4ull * n * nfb) &&
+             alloc((void **)&s->fb_macc, 16ull * (size_t)s->macc_cap * nfb) &&
+             alloc((void **)&s->fb_stamps, 4ull * nfb) &&
+             alloc((void **)&s->defer, 4ull * s->defer_cap * KAD_DEFER_LISTS);
     if (!ok || hipHostMalloc((void **)&s->h_es, sizeof(EpochState), 0) != hipSuccess ||
         hipHostMalloc((void **)&s->h_status, sizeof(HostStatus), hipHostMallocMapped) != hipSuccess ||
         hipHostGetDevicePointer((void **)&s->d_status, s->h_status, 0) != hipSuccess ||
@@ -666,8 +744,14 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     HIPCHK(hipEventCreateWithFlags(&s->ev_cal, hipEventDisableTiming));
     HIPCHK(hipStreamCreate(&s->aux));
     HIPCHK(hipEventCreateWithFlags(&s->ev_aux, hipEventDisableTiming));
-    HIPCHK(hipMemsetAsync(s->recs, 0, sizeof(Rec) * (size_t)n * pools_alloc * s->slots, st));
-    HIPCHK(hipMemsetAsync(s->stamps, 0, 4ull * pools_alloc * s->slots, st));
+    // records start unstamped (a key of zero is nobody's): cleared by a kernel
+    HIPCHK(launch_zero_words((uint32_t *)s->recs, sizeof(Rec) / 4 * sn * nslots, st));
+    HIPCHK(launch_zero_words(s->stamps, nslots, st));
+    if (s->sparse) {
+        HIPCHK(launch_zero_words((uint32_t *)s->fb_recs, sizeof(Rec) / 4 * (size_t)n * nfb, st));
+        HIPCHK(launch_zero_words(s->fb_stamps, nfb, st));
+    }
+    HIPCHK(launch_zero_words((uint32_t *)s->work_ctr, 2 * KAD_WORK_CTRS, st));
     kad_status rs = autotune(s);
     if (rs != KAD_OK) { free_sampler(s); return rs; }
     rs = reset_epochs(s);
@@ -722,7 +806,7 @@ extern "C" kad_status kad_sampler_reset(kad_sampler *s, uint64_t seed)
 
 static SampleLaunch base_launch(kad_sampler *s, int pool = 0)
 {
-    const size_t n = (size_t)s->g->n, sl = (size_t)s->slots * pool;
+    const size_t sn = s->slot_n, sl = (size_t)s->slots * pool;
     SampleLaunch a;
     memset(&a, 0, sizeof(a));
     a.g = s->g->dev();
@@ -730,9 +814,9 @@ static SampleLaunch base_launch(kad_sampler *s, int pool = 0)
     a.stream = KAD_STREAM_ADS;
     a.sf[0] = s->sf[0];
     a.sf[1] = s->sf[1];
-    a.recs = s->recs + sl * n;
-    a.queues = s->queues + sl * n;
-    a.mbufs = s->mbufs + sl * n;
+    a.recs = s->recs + sl * sn;
+    a.queues = s->queues + sl * sn;
+    a.mbufs = s->mbufs + sl * sn;
     a.macc = s->macc + sl * 2 * (size_t)s->macc_cap;
     a.macc_cap = s->macc_cap;
     a.stamps = s->stamps + sl;
@@ -742,6 +826,44 @@ static SampleLaunch base_launch(kad_sampler *s, int pool = 0)
     return a;
 }
 
+// Launches `a` (built by base_launch for `pool`) on `slots` workgroups.
+// Hashed state: the two counters of defer list `list` are cleared by a
+// kernel, the hashed launch runs, then the pool's dense fallback slots
+// finish the samples it deferred (a launch that exits at once when there
+// are none).  Everything is enqueued on `st`, with kernels only, so that
+// the sequence may be captured in a graph.
+static hipError_t launch_pool(kad_sampler *s, SampleLaunch a, int pool, int list, int slots, hipStream_t st)
+{
+    if (!s->sparse) return launch_sampler(a, slots, s->block, st);
+    unsigned long long *dc = s->work_ctr + 8 + 2 * list;
+    hipError_t e = launch_zero_words(reinterpret_cast<uint32_t *>(dc), 4, st);
+    if (e != hipSuccess) return e;
+    a.sparse = 1;
+    a.vcap_log2 = s->vlog2;
+    a.claim_limit = s->claim_limit;
+    a.defer_list = s->defer + (size_t)list * s->defer_cap;
+    a.defer_count = dc;
+    a.defer_cap = s->defer_cap;
+    e = launch_sampler(a, slots, s->block, st);
+    if (e != hipSuccess) return e;
+    const size_t n = (size_t)s->g->n, fl = (size_t)s->fb * pool;
+    SampleLaunch f = a;
+    f.sparse = 0;
+    f.vcap_log2 = 0;
+    f.claim_limit = 0;
+    f.recs = s->fb_recs + fl * n;
+    f.queues = s->fb_queues + fl * n;
+    f.mbufs = s->fb_mbufs + fl * n;
+    f.macc = s->fb_macc + fl * 2 * (size_t)s->macc_cap;
+    f.stamps = s->fb_stamps + fl;
+    f.work_ctr = dc + 1;
+    f.defer_list = nullptr;
+    f.defer_count = nullptr;
+    f.defer_in = a.defer_list;
+    f.defer_in_count = dc;
+    return launch_sampler(f, s->fb, s->block, st);
+}
+
 // Non-adaptive samples [first, first+count) of `stream` counted into `target`.
 static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, uint64_t count,
                              uint32_t *target, int32_t *paths, int64_t *info, int32_t max_len,
@@ -749,22 +871,28 @@ static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, ui
 {
     if (count == 0) return KAD_OK;
     hipStream_t st = on ? on : s->ctx->stream;
-    SampleLaunch a = base_launch(s, s->cal_pool);
-    if (stats) a.stats = stats;
-    a.work_ctr = s->work_ctr + 4;   // a counter of its own: pool 0's stays at zero for its epochs
-    a.stream = stream;
-    a.first = first;
-    a.count = count;
-    a.sf[0] = target;
-    a.sf[1] = target;
-    a.paths = paths;
-    a.info = info;
-    a.max_len = max_len;
-    a.hist = hist;
-    a.hist_top = hist_top;
-    HIPCHK(hipMemsetAsync(a.work_ctr, 0, sizeof(unsigned long long), st));
-    const int slots = (int)std::min<uint64_t>(s->slots, count);
-    HIPCHK(launch_sampler(a, slots, s->block, st));
+    // hashed state: launches of at most defer_cap samples, so that every
+    // sample a launch defers has a place in the list
+    const uint64_t chunk = s->sparse ? (uint64_t)s->defer_cap : count;
+    for (uint64_t done = 0; done < count; done += chunk) {
+        const uint64_t cnt = std::min<uint64_t>(chunk, count - done);
+        SampleLaunch a = base_launch(s, s->cal_pool);
+        if (stats) a.stats = stats;
+        a.work_ctr = s->work_ctr + 4;   // a counter of its own: pool 0's stays at zero for its epochs
+        a.stream = stream;
+        a.first = first + done;
+        a.count = cnt;
+        a.sf[0] = target;
+        a.sf[1] = target;
+        a.paths = paths ? paths + done * (uint64_t)max_len : nullptr;
+        a.info = info ? info + done * (uint64_t)KAD_INFO_WIDTH : nullptr;
+        a.max_len = max_len;
+        a.hist = hist;
+        a.hist_top = hist_top;
+        HIPCHK(launch_zero_words(reinterpret_cast<uint32_t *>(a.work_ctr), 2, st));
+        const int slots = (int)std::min<uint64_t>(s->slots, cnt);
+        HIPCHK(launch_pool(s, a, s->cal_pool, KAD_DEFER_LISTS - 1, slots, st));
+    }
     return KAD_OK;
 }
 
@@ -777,6 +905,8 @@ static kad_status check_stats_error(kad_sampler *s, const SampleStats *src = nul
     if (h.error == 1) return fail(KAD_ENOTCONNECTED, "a sampled pair has no path: graph not connected");
     if (h.error == 2) return fail(KAD_EOVERFLOW, "a path is longer than max_len - 1");
     if (h.error == 3) return fail(KAD_EDEVICE, "internal error: a path choice found no candidate");
+    if (h.error == 4) return fail(KAD_EDEVICE, "internal error: a launch deferred more samples than its list holds");
+    if (h.error == 5) return fail(KAD_EDEVICE, "internal error: a reached vertex is missing from the hashed state");
     return KAD_OK;
 }
 
@@ -969,7 +1099,7 @@ static kad_status enqueue_sampler_k(kad_sampler *s, unsigned long long k, hipEve
     // by the merge of this stream's previous epoch
     if (ev0) HIPCHK(hipEventRecord(ev0, st));
     const int w = width > 0 ? std::min(width, s->slots) : s->slots;
-    HIPCHK(launch_sampler(a, (int)std::min<unsigned long long>((unsigned long long)w, count), s->block, st));
+    HIPCHK(launch_pool(s, a, p, p, (int)std::min<unsigned long long>((unsigned long long)w, count), st));
     if (ev1) HIPCHK(hipEventRecord(ev1, st));
     return KAD_OK;
 }
@@ -1048,6 +1178,9 @@ static kad_status fill_result(kad_sampler *s)
     r.slots = s->slots;
     r.block_size = s->block;
     r.pools = s->P;
+    r.visited_mode = s->sparse ? 2 : 1;
+    r.visited_log2 = (int32_t)s->vlog2;
+    r.deferred = (int64_t)h.deferred;
     return KAD_OK;
 }
 
@@ -1093,7 +1226,7 @@ static kad_status build_graph(kad_sampler *s)
         a.cap = s->cap;
         a.sf[0] = a.sf[1] = s->sf[p];
         a.stop_flag = &s->es->stopped;
-        chk(launch_sampler(a, s->slots, s->block, sp), "sampler");
+        chk(launch_pool(s, a, p, p, s->slots, sp), "sampler");
         if (prev_merge) chk(hipStreamWaitEvent(sp, prev_merge, 0), "merge order");
         chk(launch_merge_stop_impl(s->g->dev(), s->c, s->sf[p], s->sf[p], s->LL, s->LU, s->omega, s->o.epsilon,
                                    s->cap, s->E, s->es, s->work_ctr + p, s->hist, s->hist_cap, s->d_status, sp,
@@ -1447,7 +1580,7 @@ extern "C" kad_status kad_count_samples_noalloc(kad_ctx *ctx, const kad_graph *g
         return fail(KAD_EOVERFLOW, "graph too large for kad_count_samples_noalloc: one slot needs " +
                                        std::to_string(per_slot) + " bytes, the scratch holds " +
                                        std::to_string(NOALLOC_SCRATCH_BYTES));
-    slots = std::min<size_t>(slots, (size_t)ctx->cu_count * (size_t)sampler_blocks_per_cu(block));
+    slots = std::min<size_t>(slots, (size_t)ctx->cu_count * (size_t)sampler_blocks_per_cu(block, false));
     slots = std::min<size_t>(slots, count);
     unsigned char *p = base;
     auto take = [&](size_t bytes) { unsigned char *q = p; p += up(bytes); return q; };

@@ -40,7 +40,10 @@ struct SampleStats {
     unsigned long long fp_samples;     // samples in FP mode
     unsigned long long samples;        // samples finished
     unsigned long long edges_all;      // adjacency entries read including redone attempts and rescans
-    int error;                         // nonzero: a sample found the graph disconnected
+    unsigned long long deferred;       // samples a hashed-state launch handed to the dense fallback
+    int error;                         // nonzero: a sample found the graph disconnected (1), a path
+                                       // outgrew max_len (2), no predecessor (3), defer list full (4),
+                                       // a reached vertex missing from the hashed state (5)
     int pad[3];
 };
 
@@ -110,11 +113,26 @@ struct SampleLaunch {
     uint32_t *hist;                 // optional: histogram of the counters' values 1..hist_top,
     uint32_t hist_top;              // kept as they are counted (the calibration's)
     const int32_t *count_map;       // optional: counter index of a vertex (internal id -> caller id)
+    // Visited state.  Dense (sparse == 0): recs, queues and mbufs hold n
+    // entries per slot.  Sparse: each holds 2^vcap_log2 entries per slot and
+    // recs is a hashed table; a sample that would claim more than
+    // claim_limit vertices is appended to defer_list (at most defer_cap,
+    // counted in *defer_count; error 4 beyond that) and left for a dense
+    // launch.  A dense launch with defer_in set takes its samples from that
+    // list (defer_in_count entries) instead of [0, count).
+    int sparse;
+    uint32_t vcap_log2;
+    int32_t claim_limit;
+    uint32_t *defer_list;
+    unsigned long long *defer_count;
+    uint32_t defer_cap;
+    const uint32_t *defer_in;
+    const unsigned long long *defer_in_count;
 };
 
 hipError_t launch_sampler(const SampleLaunch &a, int slots, int block, hipStream_t st);
 int sampler_max_block();
-int sampler_blocks_per_cu(int block);   // resident workgroups per CU
+int sampler_blocks_per_cu(int block, bool sparse);   // resident workgroups per CU
 
 // Epoch merge + stop rule (FP64).
 struct EpochState {

@@ -153,7 +153,7 @@ struct Smem {
     int32_t me_a[MEDGE];         // meet edges of the current chunk: owner index in the chunk,
     int32_t me_w[MEDGE];         // and the meet vertex
     uint32_t filt[Filter<BS>::WORDS];
-    int32_t tail, mcount, ovf, err, w, wmin, mpath, nme, fold_bad, pathc;
+    int32_t tail, mcount, ovf, err, w, wmin, mpath, nme, fold_bad, pathc, vsfull;
     uint32_t stamp;
     int32_t s, t;
 };
@@ -200,18 +200,155 @@ __device__ uint64_t block_sum_u64(Smem<BS> &sm, uint64_t v)
 
 struct Ctx {
     DevGraph g;
-    Rec *R;
+    Rec *R;                     // dense: one record per vertex; sparse: the slot's table
     int32_t *Q;
     int32_t *MB;
     unsigned long long *gacc;   // the slot's meet accumulators: sigma_X, then sigma_Y
     int32_t macc_cap;           // meet positions each of the two holds
     uint32_t cur;
     int fp;
+    int32_t qn;                 // capacity of the queue and the meet list (dense: n)
+    uint32_t cur16;             // sparse: the stamp as stored in the table
+    uint32_t hshift;            // sparse: 64 - log2(table size)
+    uint32_t mask;              // sparse: table size - 1
+    int32_t claim_limit;        // sparse: vertices a sample may claim (table load <= 0.75)
+    int *err;                   // the launch's error word
 };
 
 __device__ __forceinline__ int64_t qpos(int32_t n, int side, int64_t p)
 {
     return side ? (int64_t)n - 1 - p : p;
+}
+
+// ---- visited state.  Dense: record v of the slot's array (key = stamp << 32
+// | state).  Sparse: an open-addressing table per slot with linear probing,
+// whose buckets have the record layout but a key word packed as
+//   stamp (16 bits) | side | meet | depth (15 bits) | vertex (31 bits);
+// a bucket whose stamp is not the sample's is free, so runs of the
+// sample's buckets end at a free one and a sample never clears its table
+// (only when the 16-bit stamp wraps).  The functions below return keys in
+// the dense layout (stamp << 32 | state, 0 for a vertex not reached) and a
+// record index ri (dense: the vertex; sparse: its bucket), so the search
+// code is the same for both.  A sample claims at most claim_limit vertices
+// (the table stays at most 3/4 full, so every probe run ends); a sample
+// that would claim more, or reach a depth of 2^15, is handed to the dense
+// fallback.
+constexpr uint32_t SP_DEPTH_MAX = (1u << 15) - 1;
+
+__device__ __forceinline__ uint64_t sp_pack(uint32_t cur16, uint32_t state, int32_t v)
+{
+    return ((uint64_t)cur16 << 48) | ((uint64_t)(state >> 30) << 46) | ((uint64_t)(state & 0x7fffu) << 31) |
+           (uint64_t)(uint32_t)v;
+}
+__device__ __forceinline__ uint32_t sp_state(uint64_t k)
+{
+    return (((uint32_t)(k >> 46) & 3u) << 30) | (uint32_t)((k >> 31) & 0x7fffu);
+}
+__device__ __forceinline__ bool sp_live(const Ctx &c, uint64_t k) { return (uint32_t)(k >> 48) == c.cur16; }
+__device__ __forceinline__ int32_t sp_vid(uint64_t k) { return (int32_t)(k & 0x7fffffffu); }
+__device__ __forceinline__ uint32_t sp_home(const Ctx &c, int32_t v)
+{
+    return (uint32_t)(((uint64_t)(uint32_t)v * 0x9E3779B97F4A7C15ull) >> c.hshift);
+}
+
+// Key of v (dense layout) and its record index, continuing a probe run from
+// bucket b whose key k0 has already been loaded (sparse).
+template <bool SP>
+__device__ __forceinline__ uint64_t vs_resolve(const Ctx &c, int32_t v, uint32_t b, uint64_t k0, int64_t &ri)
+{
+    uint64_t k = k0;
+    for (;;) {
+        if (!sp_live(c, k)) { ri = -1; return 0ull; }
+        if (sp_vid(k) == v) { ri = b; return ((uint64_t)c.cur << 32) | sp_state(k); }
+        b = (b + 1) & c.mask;
+        k = ld_key(c.R + b);
+    }
+}
+
+template <bool SP>
+__device__ __forceinline__ uint64_t vs_key(const Ctx &c, int32_t v, int64_t &ri)
+{
+    if (!SP) {
+        ri = v;
+        return ld_key(c.R + v);
+    }
+    const uint32_t b = sp_home(c, v);
+    return vs_resolve<SP>(c, v, b, ld_key(c.R + b), ri);
+}
+
+// Record index of a vertex the sample has reached (error 5, and bucket 0,
+// if the table does not hold it: never, short of a defect).
+template <bool SP>
+__device__ __forceinline__ int64_t vs_index(const Ctx &c, int32_t v)
+{
+    int64_t ri;
+    (void)vs_key<SP>(c, v, ri);
+    if (SP && ri < 0) {
+        *c.err = 5;
+        ri = 0;
+    }
+    return ri;
+}
+
+// Claims v with key `desired` (dense layout) unless the sample has reached
+// it; `seen` is the key the caller loaded (dense: the compare value).
+template <bool SP>
+__device__ __forceinline__ bool vs_claim(const Ctx &c, int32_t v, uint64_t seen, uint64_t desired, int64_t &ri)
+{
+    if (!SP) {
+        ri = v;
+        return cas_key(c.R + v, seen, desired);
+    }
+    const uint64_t nk = sp_pack(c.cur16, (uint32_t)desired, v);
+    uint32_t b = sp_home(c, v);
+    uint64_t k = ld_key(c.R + b);
+    for (;;) {
+        if (sp_live(c, k)) {
+            if (sp_vid(k) == v) { ri = b; return false; }
+            b = (b + 1) & c.mask;
+            k = ld_key(c.R + b);
+            continue;
+        }
+        uint64_t expect = k;
+        if (__hip_atomic_compare_exchange_strong(reinterpret_cast<uint64_t *>(c.R + b), &expect, nk,
+                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            ri = b;
+            return true;
+        }
+        k = expect;   // the bucket was taken meanwhile: look at it again
+    }
+}
+
+// Sets the meet bit; returns the previous state (dense layout).
+template <bool SP>
+__device__ __forceinline__ uint32_t vs_or_meet(const Ctx &c, int64_t ri)
+{
+    if (!SP) return or_state(c.R + ri, MEET_BIT);
+    const uint64_t old = __hip_atomic_fetch_or(reinterpret_cast<uint64_t *>(c.R + ri), 1ull << 46,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return sp_state(old);
+}
+
+// A root of the search (s or t) with key `key` (dense layout).
+template <bool SP>
+__device__ __forceinline__ int64_t vs_root(const Ctx &c, int32_t v, uint64_t key)
+{
+    if (!SP) {
+        st_key(c.R + v, key);
+        return v;
+    }
+    int64_t ri;
+    (void)vs_claim<SP>(c, v, 0ull, key, ri);
+    return ri;
+}
+
+// Vertices the sample has claimed so far (both queues), read while other
+// waves of the workgroup keep appending to X's queue.
+template <int BS>
+__device__ __forceinline__ int32_t claimed_now(Smem<BS> &sm, int X)
+{
+    return __hip_atomic_load(&sm.tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) + sm.hi[1 - X];
 }
 
 // Thread-local statistics, flushed once per workgroup.
@@ -226,7 +363,7 @@ struct LocalStats {
 // meet edges and sigma of layer k, which is all a step that meets needs
 // (its new layer is never used); a probe that finds no meet is followed
 // by the claiming scan.
-template <int BS>
+template <int BS, bool SP>
 __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t lo, int32_t hi,
                            LocalStats &ls, bool probe)
 {
@@ -235,7 +372,7 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
     // together: U column reads, then U record probes, then the U updates.
     constexpr int U = 4;
     const int tid = threadIdx.x, lane = tid & 63;
-    const int32_t n = c.g.n;
+    const int32_t n = c.qn;   // queue and meet-list capacity
     const uint32_t xbit = (uint32_t)X << X_SHIFT;
     const uint64_t newkey = ((uint64_t)c.cur << 32) | xbit | (uint32_t)(k + 1);
     unsigned long long nd = 0;
@@ -254,11 +391,12 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
     for (int32_t base = lo; base < hi; base += BS) {
         const int cnt = min(BS, hi - base);
         int32_t u = -1;
-        int64_t rs = 0, d = 0;
+        int64_t rs = 0, d = 0, riu = -1;
         if (tid < cnt) {
             u = c.Q[qpos(n, X, base + tid)];
             rs = c.g.rp[u];
             d = c.g.rp[u + 1] - rs;
+            if (k >= 1) riu = vs_index<SP>(c, u);
         }
         sm.e.u[tid] = u;
         sm.e.rs[tid] = rs;
@@ -304,8 +442,27 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
                 for (int j = 0; j < U; ++j)
                     if ((act >> j & 1) && !filt_test<BS>(sm.filt, w[j])) act &= ~(1u << j);
             }
+            int64_t ri[U];
+            if (!SP) {
 #pragma unroll
-            for (int j = 0; j < U; ++j) kk[j] = (act >> j & 1) ? ld_key(c.R + w[j]) : 0ull;
+                for (int j = 0; j < U; ++j) {
+                    ri[j] = w[j];
+                    kk[j] = (act >> j & 1) ? ld_key(c.R + w[j]) : 0ull;
+                }
+            } else {
+                // the home buckets' loads together, then the rest of each run
+                uint32_t hb[U];
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    hb[j] = sp_home(c, w[j]);
+                    kk[j] = (act >> j & 1) ? ld_key(c.R + hb[j]) : 0ull;
+                }
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    ri[j] = -1;
+                    if (act >> j & 1) kk[j] = vs_resolve<SP>(c, w[j], hb[j], kk[j], ri[j]);
+                }
+            }
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 if (!(act >> j & 1)) continue;
@@ -322,16 +479,25 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
             }
             uint64_t sv[U];
 #pragma unroll
-            for (int j = 0; j < U; ++j) sv[j] = (pred >> j & 1) ? ld_sig(c.R + w[j]) : 0ull;
+            for (int j = 0; j < U; ++j) sv[j] = (pred >> j & 1) ? ld_sig(c.R + ri[j]) : 0ull;
             uint32_t disc = 0, newmeet = 0;
+            if (SP && claim) {
+                // the table stays at most 3/4 full: a sample that would claim
+                // more vertices (or go deeper than the key holds) is handed
+                // to the dense fallback
+                if (claimed_now(sm, X) + BS * U > c.claim_limit || (uint32_t)(k + 1) > SP_DEPTH_MAX) {
+                    sm.vsfull = 1;
+                    claim = 0;
+                }
+            }
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 if (claim >> j & 1) {
-                    const bool won = cas_key(c.R + w[j], kk[j], newkey);
+                    const bool won = vs_claim<SP>(c, w[j], kk[j], newkey, ri[j]);
                     disc |= (uint32_t)won << j;
                     if (won) filt_set<BS>(sm.filt, w[j]);
                 }
-                if (meet >> j & 1) newmeet |= (uint32_t)!(or_state(c.R + w[j], MEET_BIT) & MEET_BIT) << j;
+                if (meet >> j & 1) newmeet |= (uint32_t)!(vs_or_meet<SP>(c, ri[j]) & MEET_BIT) << j;
             }
 #pragma unroll
             for (int j = 0; j < U; ++j) {
@@ -354,12 +520,12 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
                 }
                 if (meet >> j & 1) {
                     const int32_t slot = atomicAdd(&sm.nme, 1);
-                    if (slot < MEDGE) {
+                    if (slot < MEDGE) {   // the meet vertex by its record index
                         sm.me_a[slot] = a[j];
-                        sm.me_w[slot] = w[j];
+                        sm.me_w[slot] = (int32_t)ri[j];
                     } else if ((int64_t)(slot - MEDGE) < spill_cap) {
                         const int64_t q = (int64_t)n - 2 - 2 * (int64_t)(slot - MEDGE);
-                        c.MB[q + 1] = w[j];
+                        c.MB[q + 1] = (int32_t)ri[j];
                         c.MB[q] = a[j];
                     }
                 }
@@ -373,7 +539,7 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
                     if (mj) {
                         const int mp = pos + (int)mbcnt(mm);
                         c.MB[mp] = w[j];
-                        st_sig(c.R + w[j], (uint64_t)mp);   // meet vertices are never expanded:
+                        st_sig(c.R + ri[j], (uint64_t)mp);   // meet vertices are never expanded:
                                                             // their sigma field holds the list position
                         if (mp >= MCAP && mp < c.macc_cap) c.gacc[mp] = 0;
                     }
@@ -390,7 +556,7 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
             act = actn;
         }
         __syncthreads();
-        if (k >= 1 && tid < cnt) st_sig(c.R + sm.e.u[tid], sm.e.acc[tid]);
+        if (k >= 1 && tid < cnt) st_sig(c.R + riu, sm.e.acc[tid]);
         const int32_t nme = sm.nme;
         if (nme > 0) {
             // the chunk's sigmas are complete; meet positions were written
@@ -426,7 +592,7 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
     if (nd) atomicAdd(&sm.nextdeg, nd);
 }
 
-template <int BS>
+template <int BS, bool SP>
 __device__ void expand_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t lo, int32_t hi,
                           LocalStats &ls)
 {
@@ -434,7 +600,7 @@ __device__ void expand_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t 
     // row is read V entries at a time with all loads of a batch in flight.
     constexpr int V = 8;
     const int tid = threadIdx.x;
-    const int32_t n = c.g.n;
+    const int32_t n = c.qn;   // queue and meet-list capacity
     const uint32_t xbit = (uint32_t)X << X_SHIFT;
     const uint64_t newkey = ((uint64_t)c.cur << 32) | xbit | (uint32_t)(k + 1);
     unsigned long long nd = 0;
@@ -449,8 +615,12 @@ __device__ void expand_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t 
             uint64_t kk[V];
 #pragma unroll
             for (int j = 0; j < V; ++j) w[j] = j < m ? c.g.cci[e0 + j] : 0;
+            int64_t ri[V];
 #pragma unroll
-            for (int j = 0; j < V; ++j) kk[j] = j < m ? ld_key(c.R + w[j]) : 0ull;
+            for (int j = 0; j < V; ++j) {
+                ri[j] = -1;
+                kk[j] = j < m ? vs_key<SP>(c, w[j], ri[j]) : 0ull;
+            }
             uint32_t pred = 0;
 #pragma unroll
             for (int j = 0; j < V; ++j) {
@@ -460,10 +630,12 @@ __device__ void expand_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t 
                     if ((st & SIDE_BIT) == xbit) {
                         if (k >= 1 && (st & DEPTH_MASK) == (uint32_t)(k - 1)) pred |= 1u << j;
                     } else {
-                        const uint32_t old = or_state(c.R + w[j], MEET_BIT);
+                        const uint32_t old = vs_or_meet<SP>(c, ri[j]);
                         if (!(old & MEET_BIT)) c.MB[atomicAdd(&sm.mcount, 1)] = w[j];
                     }
-                } else if (cas_key(c.R + w[j], kk[j], newkey)) {
+                } else if (SP && (claimed_now(sm, X) + BS * V > c.claim_limit || (uint32_t)(k + 1) > SP_DEPTH_MAX)) {
+                    sm.vsfull = 1;   // handed to the dense fallback
+                } else if (vs_claim<SP>(c, w[j], kk[j], newkey, ri[j])) {
                     c.Q[qpos(n, X, atomicAdd(&sm.tail, 1))] = w[j];
                     nd += (unsigned long long)c.g.deg[w[j]];
                     ls.visited += 1;
@@ -471,7 +643,7 @@ __device__ void expand_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t 
             }
             double sv[V];
 #pragma unroll
-            for (int j = 0; j < V; ++j) sv[j] = (pred >> j & 1) ? as_f64(ld_sig(c.R + w[j])) : 0.0;
+            for (int j = 0; j < V; ++j) sv[j] = (pred >> j & 1) ? as_f64(ld_sig(c.R + ri[j])) : 0.0;
 #pragma unroll
             for (int j = 0; j < V; ++j)
                 if (pred >> j & 1) {       // CSR order within and across batches
@@ -480,7 +652,7 @@ __device__ void expand_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t 
                 }
         }
         if (k >= 1) {
-            st_sig(c.R + u, as_u64(acc));
+            st_sig(c.R + vs_index<SP>(c, u), as_u64(acc));
             mx = acc > mx ? acc : mx;
         }
     }
@@ -489,7 +661,7 @@ __device__ void expand_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t 
 }
 
 // sigma_X(w) * sigma_Y(w) for every meet vertex, stored in w's record.
-template <int BS>
+template <int BS, bool SP>
 __device__ void meet_weights_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t kY, int32_t m)
 {
     const int tid = threadIdx.x, lane = tid & 63;
@@ -520,8 +692,9 @@ __device__ void meet_weights_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, 
                     if (sm.e.off[mid] <= e) a = mid; else b = mid - 1;
                 }
                 const int32_t x = c.g.ci[sm.e.rs[a] + (e - sm.e.off[a])];
-                Rec *r = c.R + x;
-                const uint64_t kk = ld_key(r);
+                int64_t rx;
+                const uint64_t kk = vs_key<SP>(c, x, rx);
+                Rec *r = c.R + rx;
                 if ((uint32_t)(kk >> 32) == c.cur) {
                     const uint32_t st = (uint32_t)kk;
                     const uint32_t dep = st & DEPTH_MASK;
@@ -543,7 +716,7 @@ __device__ void meet_weights_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, 
             const uint64_t ay = (kY == 0) ? 1ull : (uint64_t)sm.e.acc2[tid];
             if (__umul64hi(ax, ay) != 0) sm.ovf = 1;
             const uint64_t a = ax * ay;
-            st_sig(c.R + w, a);
+            st_sig(c.R + vs_index<SP>(c, w), a);
             const unsigned long long old = atomicAdd(&sm.sigst, (unsigned long long)a);
             if (old + a < old) sm.ovf = 1;
         }
@@ -553,12 +726,12 @@ __device__ void meet_weights_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, 
 
 // Adds sigma(u) to acc[position of w] for every edge (u, w) with u in the
 // queue positions [lo, hi) of `side` and w a meet vertex.
-template <int BS>
+template <int BS, bool SP>
 __device__ void push_to_meet(Smem<BS> &sm, const Ctx &c, int side, int32_t lo, int32_t hi,
                              unsigned long long *acc)
 {
     const int tid = threadIdx.x, lane = tid & 63;
-    const int32_t n = c.g.n;
+    const int32_t n = c.qn;
     for (int32_t base = lo; base < hi; base += BS) {
         const int cnt = min(BS, hi - base);
         int64_t rs = 0, d = 0;
@@ -567,7 +740,7 @@ __device__ void push_to_meet(Smem<BS> &sm, const Ctx &c, int side, int32_t lo, i
             const int32_t u = c.Q[qpos(n, side, base + tid)];
             rs = c.g.rp[u];
             d = c.g.rp[u + 1] - rs;
-            su = ld_sig(c.R + u);
+            su = ld_sig(c.R + vs_index<SP>(c, u));
         }
         sm.e.rs[tid] = rs;
         sm.e.acc[tid] = su;
@@ -583,8 +756,9 @@ __device__ void push_to_meet(Smem<BS> &sm, const Ctx &c, int side, int32_t lo, i
                     int mid = (a + b + 1) >> 1;
                     if (sm.e.off[mid] <= e) a = mid; else b = mid - 1;
                 }
-                Rec *r = c.R + c.g.ci[sm.e.rs[a] + (e - sm.e.off[a])];
-                const uint64_t kk = ld_key(r);
+                int64_t rx;
+                const uint64_t kk = vs_key<SP>(c, c.g.ci[sm.e.rs[a] + (e - sm.e.off[a])], rx);
+                Rec *r = c.R + rx;
                 if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & MEET_BIT)) {
                     const uint64_t v = sm.e.acc[a];
                     const unsigned long long old = atomicAdd(acc + ld_sig(r), (unsigned long long)v);
@@ -599,7 +773,7 @@ __device__ void push_to_meet(Smem<BS> &sm, const Ctx &c, int side, int32_t lo, i
 // For every meet vertex w (list position i): accX[i] += sigma of w's
 // neighbours in layer kX of X, accY[i] += sigma of w's neighbours in layer
 // kY - 1 of Y (either accumulator may be null: that side is skipped).
-template <int BS>
+template <int BS, bool SP>
 __device__ void pull_to_meet(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t kY, int32_t m,
                              unsigned long long *accX, unsigned long long *accY)
 {
@@ -627,8 +801,9 @@ __device__ void pull_to_meet(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int3
                     int mid = (a + b + 1) >> 1;
                     if (sm.e.off[mid] <= e) a = mid; else b = mid - 1;
                 }
-                Rec *r = c.R + c.g.ci[sm.e.rs[a] + (e - sm.e.off[a])];
-                const uint64_t kk = ld_key(r);
+                int64_t rx;
+                const uint64_t kk = vs_key<SP>(c, c.g.ci[sm.e.rs[a] + (e - sm.e.off[a])], rx);
+                Rec *r = c.R + rx;
                 if ((uint32_t)(kk >> 32) == c.cur) {
                     const uint32_t st = (uint32_t)kk & ~MEET_BIT;
                     unsigned long long *acc = nullptr;
@@ -653,14 +828,14 @@ __device__ void pull_to_meet(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int3
 // order, so both give the same value.  Weights end in sm.m.w (m <= MCAP),
 // in the slot's global buffer (m <= MACC) or, beyond that, in the meet
 // vertices' sigma fields; sm.mpath says which.
-template <int BS>
+template <int BS, bool SP>
 __device__ void meet_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t kY, int32_t m,
                          unsigned long long *gacc, int32_t macc_cap)
 {
     const int tid = threadIdx.x;
     const int path = (m <= MCAP) ? 0 : (m <= macc_cap ? 1 : 2);
     if (path == 2) {
-        meet_weights_int<BS>(sm, c, X, kX, kY, m);
+        meet_weights_int<BS, SP>(sm, c, X, kX, kY, m);
         if (tid == 0) sm.mpath = 2;
         __syncthreads();
         return;
@@ -686,10 +861,10 @@ __device__ void meet_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t 
     const bool pullX = !foldX && !pushX;
     const bool pushY = kY >= 1 && (uint64_t)sm.psdeg[Y] <= dM;
     const bool pullY = kY >= 1 && !pushY;
-    if (pushX) push_to_meet<BS>(sm, c, X, sm.lo[X], sm.hi[X], accX);
-    if (pushY) push_to_meet<BS>(sm, c, Y, sm.plo[Y], sm.phi[Y], accY);
+    if (pushX) push_to_meet<BS, SP>(sm, c, X, sm.lo[X], sm.hi[X], accX);
+    if (pushY) push_to_meet<BS, SP>(sm, c, Y, sm.plo[Y], sm.phi[Y], accY);
     if (pullX || pullY)
-        pull_to_meet<BS>(sm, c, X, kX, kY, m, pullX ? accX : nullptr, pullY ? accY : nullptr);
+        pull_to_meet<BS, SP>(sm, c, X, kX, kY, m, pullX ? accX : nullptr, pullY ? accY : nullptr);
     __syncthreads();
     for (int32_t i = tid; i < m; i += BS) {
         const uint64_t ax = accX[i];
@@ -704,7 +879,7 @@ __device__ void meet_int(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t 
     __syncthreads();
 }
 
-template <int BS>
+template <int BS, bool SP>
 __device__ void meet_weights_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, int32_t kY, int32_t m)
 {
     const uint32_t xstate = ((uint32_t)X << X_SHIFT) | (uint32_t)kX;
@@ -714,15 +889,16 @@ __device__ void meet_weights_fp(Smem<BS> &sm, const Ctx &c, int X, int32_t kX, i
         double ax = 0.0, ay = 0.0;
         for (int64_t e = c.g.rp[w]; e < c.g.rp[w + 1]; ++e) {
             const int32_t x = c.g.cci[e];
-            Rec *r = c.R + x;
-            const uint64_t kk = ld_key(r);
+            int64_t rx;
+            const uint64_t kk = vs_key<SP>(c, x, rx);
+            Rec *r = c.R + rx;
             if ((uint32_t)(kk >> 32) != c.cur) continue;
             const uint32_t st = (uint32_t)kk & ~MEET_BIT;
             if (st == xstate) ax = ax + as_f64(ld_sig(r));
             else if (kY >= 1 && st == ystate) ay = ay + as_f64(ld_sig(r));
         }
         if (kY == 0) ay = 1.0;
-        st_sig(c.R + w, as_u64(ax * ay));
+        st_sig(c.R + vs_index<SP>(c, w), as_u64(ax * ay));
     }
     (void)sm;
 }
@@ -747,7 +923,7 @@ __device__ int32_t next_min(Smem<BS> &sm, const Ctx &c, int32_t m, int32_t last)
 }
 
 // Chooses the meet vertex; result in sm.w (all threads call).
-template <int BS>
+template <int BS, bool SP>
 __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
                             const unsigned long long *gacc)
 {
@@ -758,7 +934,7 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
             for (int32_t i = tid; i < m; i += BS) {
                 const int32_t w = c.MB[i];
                 sm.m.id[i] = c.g.orig[w];
-                sm.m.w[i] = ld_sig(c.R + w);
+                sm.m.w[i] = ld_sig(c.R + vs_index<SP>(c, w));
             }
         }
         __syncthreads();
@@ -837,7 +1013,7 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
             uint64_t part = 0;
             for (int32_t i = tid; i < m; i += BS) {
                 const int32_t w = c.MB[i];
-                if (c.g.orig[w] <= mid) part += global_w ? (uint64_t)gacc[i] : ld_sig(c.R + w);
+                if (c.g.orig[w] <= mid) part += global_w ? (uint64_t)gacc[i] : ld_sig(c.R + vs_index<SP>(c, w));
             }
             const uint64_t tot = block_sum_u64<BS>(sm, part);
             if (tot > r) hi = mid; else lo = mid + 1;
@@ -876,7 +1052,8 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
                 __syncthreads();
             }
         }
-        for (int32_t i = tid; i < m; i += BS) wsorted[i] = as_f64(ld_sig(c.R + c.MB[(uint32_t)key[i]]));
+        for (int32_t i = tid; i < m; i += BS)
+            wsorted[i] = as_f64(ld_sig(c.R + vs_index<SP>(c, c.MB[(uint32_t)key[i]])));
         __syncthreads();
         if (tid < 64) {
             const int lane = tid;
@@ -912,7 +1089,7 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
     double tot = 0.0;
     for (int32_t step = 0, last = -1; step < m; ++step) {
         const int32_t id = next_min<BS>(sm, c, m, last);
-        tot = tot + as_f64(ld_sig(c.R + c.g.newid[id]));
+        tot = tot + as_f64(ld_sig(c.R + vs_index<SP>(c, c.g.newid[id])));
         last = id;
     }
     const double r = unit53(u2) * tot;
@@ -920,7 +1097,7 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
     int32_t pick = -1;
     for (int32_t step = 0, last = -1; step < m; ++step) {
         const int32_t id = next_min<BS>(sm, c, m, last);
-        const double a = as_f64(ld_sig(c.R + c.g.newid[id]));
+        const double a = as_f64(ld_sig(c.R + vs_index<SP>(c, c.g.newid[id])));
         pre = pre + a;
         if (a != 0.0) pick = id;
         if (pre > r) { pick = id; break; }
@@ -931,6 +1108,7 @@ __device__ void choose_meet(Smem<BS> &sm, const Ctx &c, int32_t m, uint64_t u2,
 }
 
 // One predecessor pick walking back on `side` from v at depth l (>= 2).
+template <bool SP>
 __device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint64_t u, int lane)
 {
     const uint32_t want = ((uint32_t)side << X_SHIFT) | (uint32_t)(l - 1);
@@ -943,8 +1121,9 @@ __device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint6
         bool cand = false;
         if (e < end) {
             x = c.g.cci[e];
-            Rec *r = c.R + x;
-            const uint64_t kk = ld_key(r);
+            int64_t rx;
+            const uint64_t kk = vs_key<SP>(c, x, rx);
+            Rec *r = c.R + rx;
             if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) {
                 cand = true;
                 bits = ld_sig(r);
@@ -981,8 +1160,9 @@ __device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint6
             const int64_t e = c0 + lane;
             uint64_t wt = 0;
             if (e < end) {
-                Rec *r = c.R + c.g.cci[e];
-                const uint64_t kk = ld_key(r);
+                int64_t rx;
+                const uint64_t kk = vs_key<SP>(c, c.g.cci[e], rx);
+                Rec *r = c.R + rx;
                 if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) wt = ld_sig(r);
             }
             tot += wave_sum_u64(wt);
@@ -995,8 +1175,9 @@ __device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint6
             int32_t x = -1;
             if (e < end) {
                 x = c.g.cci[e];
-                Rec *rc = c.R + x;
-                const uint64_t kk = ld_key(rc);
+                int64_t rx;
+                const uint64_t kk = vs_key<SP>(c, x, rx);
+                Rec *rc = c.R + rx;
                 if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) wt = ld_sig(rc);
             }
             const uint64_t incl = wave_incl_scan_u64(wt, lane);
@@ -1012,8 +1193,9 @@ __device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint6
         double wt = 0.0;
         bool cand = false;
         if (e < end) {
-            Rec *r = c.R + c.g.cci[e];
-            const uint64_t kk = ld_key(r);
+            int64_t rx;
+            const uint64_t kk = vs_key<SP>(c, c.g.cci[e], rx);
+            Rec *r = c.R + rx;
             if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) {
                 cand = true;
                 wt = as_f64(ld_sig(r));
@@ -1036,8 +1218,9 @@ __device__ int32_t pick_pred(const Ctx &c, int side, int32_t v, int32_t l, uint6
         int32_t x = -1;
         if (e < end) {
             x = c.g.cci[e];
-            Rec *rc = c.R + x;
-            const uint64_t kk = ld_key(rc);
+            int64_t rx;
+            const uint64_t kk = vs_key<SP>(c, x, rx);
+            Rec *rc = c.R + rx;
             if ((uint32_t)(kk >> 32) == c.cur && ((uint32_t)kk & ~MEET_BIT) == want) {
                 cand = true;
                 wt = as_f64(ld_sig(rc));
@@ -1075,11 +1258,11 @@ __device__ __forceinline__ bool row_contains(const DevGraph &g, int32_t row, int
 // One wave; candidates go to its part [base, base + cap) of the (idle)
 // expansion LDS area.  Returns -2 when there are more candidates than fit
 // (the caller scans v's row).
-template <int BS>
+template <int BS, bool SP>
 __device__ int32_t pick_pred_layer(Smem<BS> &sm, const Ctx &c, int side, int32_t v, int32_t lo,
                                    int32_t hi, uint64_t u, int lane, int32_t base, int32_t cap)
 {
-    const int32_t n = c.g.n;
+    const int32_t n = c.qn;
     const int64_t dv = c.g.rp[v + 1] - c.g.rp[v];
     uint64_t tot = 0;
     int32_t ncand = 0;
@@ -1092,7 +1275,7 @@ __device__ int32_t pick_pred_layer(Smem<BS> &sm, const Ctx &c, int side, int32_t
             x = c.Q[qpos(n, side, p)];
             const int64_t dx = c.g.rp[x + 1] - c.g.rp[x];
             cand = dx <= dv ? row_contains(c.g, x, v) : row_contains(c.g, v, x);
-            if (cand) wt = ld_sig(c.R + x);
+            if (cand) wt = ld_sig(c.R + vs_index<SP>(c, x));
         }
         const uint64_t cm = __ballot(cand);
         const int32_t k = __popcll(cm);
@@ -1146,7 +1329,7 @@ __device__ __forceinline__ void count_vertex(const SampleLaunch &a, uint32_t *sf
 // shape is held to three (three workgroups per CU): the high-diameter
 // graphs depend on that many samples in flight; the 512-thread shape to
 // four (two workgroups per CU).
-template <int BS>
+template <int BS, bool SP>
 __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_sample(SampleLaunch a)
 {
     __shared__ Smem<BS> sm;
@@ -1166,9 +1349,17 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
     const size_t slot = blockIdx.x;
     Ctx c;
     c.g = a.g;
-    c.R = a.recs + slot * (size_t)n;
-    c.Q = a.queues + slot * (size_t)n;
-    c.MB = a.mbufs + slot * (size_t)n;
+    // dense: a record per vertex, queue and meet list of n; sparse: a table
+    // of 2^vcap_log2 buckets, queue and meet list of as many entries
+    const int32_t qn = SP ? (int32_t)(1u << a.vcap_log2) : n;
+    c.qn = qn;
+    c.R = a.recs + slot * (size_t)qn;
+    c.Q = a.queues + slot * (size_t)qn;
+    c.MB = a.mbufs + slot * (size_t)qn;
+    c.mask = SP ? (uint32_t)qn - 1u : 0u;
+    c.hshift = SP ? 64u - a.vcap_log2 : 0u;
+    c.claim_limit = a.claim_limit;
+    c.err = &a.stats->error;
     unsigned long long *gacc = a.macc + slot * 2 * (size_t)a.macc_cap;
     c.gacc = gacc;
     c.macc_cap = a.macc_cap;
@@ -1180,7 +1371,14 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
             // a later epoch that became speculative (the run stopped) quits early
             const bool stop = a.stop_flag &&
                               __hip_atomic_load(a.stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sm.sid = stop ? count : atomicAdd(a.work_ctr, 1ull);
+            if (a.defer_in) {   // the dense fallback: the samples a sparse launch handed over
+                const unsigned long long q = stop ? ~0ull : atomicAdd(a.work_ctr, 1ull);
+                const unsigned long long nd =
+                    __hip_atomic_load(a.defer_in_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sm.sid = (q < nd && q < (unsigned long long)a.defer_cap) ? (unsigned long long)a.defer_in[q] : count;
+            } else {
+                sm.sid = stop ? count : atomicAdd(a.work_ctr, 1ull);
+            }
         }
         __syncthreads();
         const unsigned long long sid = sm.sid;
@@ -1204,7 +1402,8 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
         int32_t kX = 0, kY = 0, m = 0;
         unsigned long long edges = 0;
         int steps = 0;
-        bool failed = false;
+        bool failed = false, deferred = false;
+        const unsigned long long vis0 = ls.visited, pred0 = ls.pred, exp0 = st_exp;
         for (;;) {  // attempt (integer mode, then FP mode if it overflowed)
             attempts += 1;
             for (int i = tid; i < Filter<BS>::WORDS; i += BS) sm.filt[i] = 0;
@@ -1213,13 +1412,22 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                 const uint32_t cur = a.stamps[slot] + 1;
                 a.stamps[slot] = cur;
                 sm.stamp = cur;
+            }
+            __syncthreads();
+            c.cur = sm.stamp;
+            c.cur16 = ((c.cur - 1u) % 65535u) + 1u;
+            if (SP && c.cur16 == 1u && c.cur > 1u) {
+                // the 16-bit stamp wrapped: every bucket is made free again
+                for (int32_t i = tid; i < qn; i += BS) st_key(c.R + i, 0ull);
+                __syncthreads();
+            }
+            if (tid == 0) {
+                const uint32_t cur = c.cur;
                 const int32_t s = sm.s, t = sm.t;
-                st_key(c.R + s, ((uint64_t)cur << 32) | 0u);
-                st_sig(c.R + s, fp ? as_u64(1.0) : 1ull);
-                st_key(c.R + t, ((uint64_t)cur << 32) | SIDE_BIT);
-                st_sig(c.R + t, fp ? as_u64(1.0) : 1ull);
+                st_sig(c.R + vs_root<SP>(c, s, ((uint64_t)cur << 32) | 0u), fp ? as_u64(1.0) : 1ull);
+                st_sig(c.R + vs_root<SP>(c, t, ((uint64_t)cur << 32) | SIDE_BIT), fp ? as_u64(1.0) : 1ull);
                 c.Q[0] = s;
-                c.Q[n - 1] = t;
+                c.Q[qn - 1] = t;
                 filt_set<BS>(sm.filt, s);
                 filt_set<BS>(sm.filt, t);
                 sm.lo[0] = sm.lo[1] = 0;
@@ -1239,9 +1447,9 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                 sm.mcount = 0;
                 sm.nextdeg = 0;
                 sm.fmax_bits = 0;
+                sm.vsfull = 0;
             }
             __syncthreads();
-            c.cur = sm.stamp;
             c.fp = fp;
             edges = 0;
             steps = 0;
@@ -1258,21 +1466,22 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                 // of their degree sums reaches the number of adjacency
                 // entries) is scanned without claiming first.
                 const bool probe = !fp && (double)sm.sdeg[X] * (double)sm.sdeg[1 - X] >= (double)c.g.nnz;
-                if (!fp) expand_int<BS>(sm, c, X, k, lo, hi, ls, probe);
-                else expand_fp<BS>(sm, c, X, k, lo, hi, ls);
+                if (!fp) expand_int<BS, SP>(sm, c, X, k, lo, hi, ls, probe);
+                else expand_fp<BS, SP>(sm, c, X, k, lo, hi, ls);
                 __syncthreads();
                 if (probe && !sm.ovf && sm.mcount == 0) {
                     __syncthreads();
                     const unsigned long long pred_before = ls.pred;   // the rescan meets the
-                    expand_int<BS>(sm, c, X, k, lo, hi, ls, false);  // same predecessor edges
+                    expand_int<BS, SP>(sm, c, X, k, lo, hi, ls, false);  // same predecessor edges
                     ls.pred = pred_before;
                     __syncthreads();
                     st_all += (unsigned long long)sm.sdeg[X];
                 }
                 t_exp += wall_clock64() - t_mark;
+                if (SP && sm.vsfull) { deferred = true; break; }
                 if (fp && k >= 1 && as_f64(sm.fmax_bits) > BIG) {
                     for (int32_t p = lo + tid; p < hi; p += BS) {
-                        Rec *r = c.R + c.Q[qpos(n, X, p)];
+                        Rec *r = c.R + vs_index<SP>(c, c.Q[qpos(qn, X, p)]);
                         st_sig(r, as_u64(as_f64(ld_sig(r)) * SHRINK));
                     }
                     __syncthreads();
@@ -1300,15 +1509,15 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                 __syncthreads();
             }
             st_all += edges;
-            if (failed) break;
+            if (failed || deferred) break;
             if (!fp && sm.ovf) { __syncthreads(); fp = 1; continue; }
             kX = sm.dep[X];
             kY = sm.dep[1 - X];
             m = sm.mcount;
             __syncthreads();
             t_mark = wall_clock64();
-            if (!fp) meet_int<BS>(sm, c, X, kX, kY, m, gacc, a.macc_cap);
-            else meet_weights_fp<BS>(sm, c, X, kX, kY, m);
+            if (!fp) meet_int<BS, SP>(sm, c, X, kX, kY, m, gacc, a.macc_cap);
+            else meet_weights_fp<BS, SP>(sm, c, X, kX, kY, m);
             __syncthreads();
             t_mw += wall_clock64() - t_mark;
             if (!fp && sm.ovf) { __syncthreads(); fp = 1; continue; }
@@ -1316,6 +1525,19 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
         }
         if (failed) {
             if (tid == 0) a.stats->error = 1;
+            __syncthreads();
+            continue;
+        }
+        if (deferred) {   // to the dense fallback launch that follows this one, which
+            ls.visited = vis0;   // counts the sample's statistics
+            ls.pred = pred0;
+            st_exp = exp0;
+            if (tid == 0) {
+                const unsigned long long q = atomicAdd(a.defer_count, 1ull);
+                if (q < (unsigned long long)a.defer_cap) a.defer_list[q] = (uint32_t)sid;
+                else a.stats->error = 4;
+                atomicAdd(&a.stats->deferred, 1ull);
+            }
             __syncthreads();
             continue;
         }
@@ -1327,7 +1549,7 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
             SampleDraws dr;
             dr.init(seed, a.stream, idx);
             const uint64_t u2 = dr.get(2);
-            choose_meet<BS>(sm, c, m, u2, gacc);
+            choose_meet<BS, SP>(sm, c, m, u2, gacc);
         }
         t_ch = wall_clock64() - t_mark;
         t_mark = wall_clock64();
@@ -1379,9 +1601,9 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                         const int32_t llo = sm.loff[side][l - 1], lhi = sm.loff[side][l];
                         const int64_t dv = a.g.rp[v + 1] - a.g.rp[v];
                         if (2 * (int64_t)(lhi - llo) < dv)
-                            p = pick_pred_layer<BS>(sm, c, side, v, llo, lhi, u, lane, wid * cap, cap);
+                            p = pick_pred_layer<BS, SP>(sm, c, side, v, llo, lhi, u, lane, wid * cap, cap);
                     }
-                    if (p == -2) p = pick_pred(c, side, v, l, u, lane);
+                    if (p == -2) p = pick_pred<SP>(c, side, v, l, u, lane);
                     if (p < 0) {   // no predecessor found: report, stop this walk
                         if (lane == 0) a.stats->error = 3;
                         break;
@@ -1448,31 +1670,43 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
 
 int sampler_max_block() { return 1024; }
 
-int sampler_blocks_per_cu(int block)
+int sampler_blocks_per_cu(int block, bool sparse)
 {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
+#define KAD_OCC(B)                                                                                          \
+    case B:                                                                                                 \
+        e = sparse ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<B, true>, B, 0)           \
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<B, false>, B, 0);         \
+        break;
     switch (block) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<64>, 64, 0); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<128>, 128, 0); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<256>, 256, 0); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<512>, 512, 0); break;
-    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<1024>, 1024, 0); break;
+        KAD_OCC(64)
+        KAD_OCC(128)
+        KAD_OCC(256)
+        KAD_OCC(512)
+        KAD_OCC(1024)
     default: break;
     }
+#undef KAD_OCC
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 hipError_t launch_sampler(const SampleLaunch &a, int slots, int block, hipStream_t st)
 {
+#define KAD_LAUNCH(B)                                                                                       \
+    case B:                                                                                                 \
+        if (a.sparse) hipLaunchKernelGGL((k_sample<B, true>), dim3(slots), dim3(B), 0, st, a);             \
+        else hipLaunchKernelGGL((k_sample<B, false>), dim3(slots), dim3(B), 0, st, a);                     \
+        break;
     switch (block) {
-    case 64: hipLaunchKernelGGL(k_sample<64>, dim3(slots), dim3(64), 0, st, a); break;
-    case 128: hipLaunchKernelGGL(k_sample<128>, dim3(slots), dim3(128), 0, st, a); break;
-    case 256: hipLaunchKernelGGL(k_sample<256>, dim3(slots), dim3(256), 0, st, a); break;
-    case 512: hipLaunchKernelGGL(k_sample<512>, dim3(slots), dim3(512), 0, st, a); break;
-    case 1024: hipLaunchKernelGGL(k_sample<1024>, dim3(slots), dim3(1024), 0, st, a); break;
+        KAD_LAUNCH(64)
+        KAD_LAUNCH(128)
+        KAD_LAUNCH(256)
+        KAD_LAUNCH(512)
+        KAD_LAUNCH(1024)
     default: return hipErrorInvalidValue;
     }
+#undef KAD_LAUNCH
     return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ KAD_STREAM_ADS, KAD_STREAM_CALIB, KAD_STREAM_TUNE = 0, 1, 5
 KAD_ALLOC_PLAIN, KAD_ALLOC_EXPLICIT, KAD_ALLOC_LEARNED = 0, 1, 2
 KAD_SIGMA_AUTO, KAD_SIGMA_FP = 0, 1
 KAD_STOP_NONE, KAD_STOP_COND, KAD_STOP_OMEGA = 0, 1, 2
+KAD_VISITED_AUTO, KAD_VISITED_DENSE, KAD_VISITED_HASHED = 0, 1, 2
 KAD_GRAPH_VALIDATE = 1
 MLP_PARAMS = 4481
 INFO_WIDTH = 14
@@ -40,7 +41,8 @@ class kad_opts(C.Structure):
                 ("omega_override", C.c_double), ("sigma_mode", C.c_int32), ("slots", C.c_int32),
                 ("visited_budget_bytes", C.c_uint64), ("epochs_in_flight", C.c_int32),
                 ("use_graphs", C.c_int32), ("block_size", C.c_int32), ("timing", C.c_int32),
-                ("pools", C.c_int32), ("exact_diameter", C.c_int32)]
+                ("pools", C.c_int32), ("exact_diameter", C.c_int32), ("visited_mode", C.c_int32),
+                ("visited_log2", C.c_int32)]
 
 
 class kad_result(C.Structure):
@@ -54,7 +56,8 @@ class kad_result(C.Structure):
                 ("path_vertices", C.c_int64), ("fp_samples", C.c_int64), ("max_f", C.c_double),
                 ("max_g", C.c_double), ("min_margin", C.c_double), ("epoch_size", C.c_uint32),
                 ("slots", C.c_int32), ("samples_run", C.c_int64), ("block_size", C.c_int32),
-                ("pools", C.c_int32)]
+                ("pools", C.c_int32), ("visited_mode", C.c_int32), ("visited_log2", C.c_int32),
+                ("deferred", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -165,9 +168,11 @@ def kad_graph_free(g):
 
 def make_opts(seed=1, epsilon=0.01, delta=0.1, epoch_size=0, alloc_mode=KAD_ALLOC_PLAIN,
               omega_override=0.0, sigma_mode=KAD_SIGMA_AUTO, slots=0, visited_budget_bytes=0,
-              epochs_in_flight=0, use_graphs=0, block_size=0, timing=0, pools=0, exact_diameter=0) -> kad_opts:
+              epochs_in_flight=0, use_graphs=0, block_size=0, timing=0, pools=0, exact_diameter=0,
+              visited_mode=0, visited_log2=0) -> kad_opts:
     return kad_opts(seed, epsilon, delta, epoch_size, alloc_mode, omega_override, sigma_mode, slots,
-                    visited_budget_bytes, epochs_in_flight, use_graphs, block_size, timing, pools, exact_diameter)
+                    visited_budget_bytes, epochs_in_flight, use_graphs, block_size, timing, pools, exact_diameter,
+                    visited_mode, visited_log2)
 
 
 def kad_sampler_init(ctx, g, opts: kad_opts):
