@@ -123,6 +123,7 @@ struct kad_sampler {
     SampleStats *stats;
     SampleStats *cal_stats;   // the calibration's samples (they may run beside adaptive epochs)
     uint32_t *cal_hist = nullptr;   // histogram of the calibration counts, kept by its sampler
+    double *cal_ltab = nullptr;     // L of each count value 0..tau0
     uint32_t cal_hist_top = 0;      // its last bin: tau0
     EpochState *es;
     void *hist;
@@ -166,6 +167,12 @@ struct kad_sampler {
     uint32_t *fb_stamps = nullptr;
     uint32_t *defer = nullptr;    // KAD_DEFER_LISTS lists of defer_cap sample indices
     uint32_t defer_cap = 0;
+    // plain allocation: the merges read L by calibration count (cprime,
+    // cal_ltab), and the L arrays are filled only when fetched
+    bool L_lazy = false;
+    mutable bool L_pending = false;
+    AllocArgs lazy_args{};
+    double lazy_C = 0.0;
 };
 
 namespace {
@@ -176,7 +183,12 @@ namespace {
 constexpr int KAD_DEFER_LISTS = 5;
 constexpr size_t KAD_WORK_CTRS = 8 + 2 * KAD_DEFER_LISTS;
 constexpr uint32_t KAD_DEFER_CAP = 1u << 16;   // samples a hashed launch may defer: its count at most
-constexpr int KAD_FB_SLOTS = 8;                 // dense fallback slots per pool
+// Dense fallback slots per pool: one.  The fallback launch sits between an
+// epoch's sampler and its merge and usually has nothing to do, but each of
+// its workgroups must still find a CU among those the other pools' samplers
+// hold (the XCDs take a launch's workgroups in turn, so eight workgroups
+// wait for a free CU in eight XCDs); a single workgroup waits least.
+constexpr int KAD_FB_SLOTS = 1;
 }  // namespace
 
 extern "C" const char *kad_last_error(void) { return g_err.c_str(); }
@@ -398,6 +410,7 @@ static void free_sampler(kad_sampler *s)
     if (s->ev_aux) (void)hipEventDestroy(s->ev_aux);
     if (s->ev_cal) (void)hipEventDestroy(s->ev_cal);
     if (s->cal_hist) (void)hipFree(s->cal_hist);
+    if (s->cal_ltab) (void)hipFree(s->cal_ltab);
     if (s->yhat) (void)hipFree(s->yhat);
     if (s->feat_buf) (void)hipFree(s->feat_buf);
     if (s->mlp_dev) (void)hipFree(s->mlp_dev);
@@ -437,7 +450,7 @@ static kad_status reset_epochs(kad_sampler *s)
     // HBM bandwidth on these sizes
     HIPCHK(launch_zero_words(s->c, (size_t)s->g->n, st));
     for (int i = 0; i < s->P; ++i) HIPCHK(launch_zero_words(s->sf[i], (size_t)s->g->n, st));
-    HIPCHK(hipMemsetAsync(s->work_ctr, 0, 4 * sizeof(unsigned long long), st));
+    HIPCHK(hipMemsetAsync(s->work_ctr, 0, KAD_WORK_CTRS * sizeof(unsigned long long), st));
     {
         // pool p starts at epoch p; the run's seed for replayed graphs
         const unsigned long long pe[5] = {0, 1, 2, 3, (unsigned long long)s->o.seed};
@@ -570,7 +583,7 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     if (!(o->delta > 0.0 && o->delta < 1.0)) return fail(KAD_EINVAL, "delta must lie in (0, 1)");
     if (o->alloc_mode < 0 || o->alloc_mode > 2) return fail(KAD_EINVAL, "bad alloc_mode");
     if (o->sigma_mode < 0 || o->sigma_mode > 1) return fail(KAD_EINVAL, "bad sigma_mode");
-    const int block = o->block_size ? o->block_size : 256;
+    int block = o->block_size ? o->block_size : 256;
     if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
         return fail(KAD_EINVAL, "block_size must be 64, 128, 256, 512 or 1024");
     HIPCHK(hipSetDevice(ctx->device));
@@ -634,7 +647,24 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
         delete s;
         return fail(KAD_EINVAL, "pools must be 0 (auto) or 1..4");
     }
-    s->sparse = o->visited_mode == 2;
+    // Auto: hashed when the dense state cannot hold four pools of a full
+    // wave, the table is at most an eighth of a dense slot, and the graph is
+    // small-world (vertex diameter at most 32 by the bracket), so that a
+    // search claims a small share of the vertices and deferrals stay rare;
+    // otherwise (and when omega was given, with no bracket) dense.
+    s->sparse = o->visited_mode == KAD_VISITED_HASHED;
+    if (o->visited_mode == KAD_VISITED_AUTO && o->slots <= 0)
+        s->sparse = budget / per_dense < 4 * (size_t)full_wave(false) && per_sparse * 8 <= per_dense &&
+                    s->vd_hi > 0 && s->vd_hi <= 32;
+    // Hashed state without a given shape: 1024-thread workgroups, not the
+    // trial's pick.  A trial times one launch; with four overlapped pools
+    // the 512-thread shape it favoured ran R-MAT 26 to the stop in 69 ms
+    // against 48 ms for 1024 threads.
+    if (s->sparse && o->block_size == 0) {
+        s->tune_block = false;
+        block = 1024;
+        s->block = block;
+    }
     size_t pools_alloc = 0;
     if (s->sparse) {
         // every pool: a full wave of hashed slots, its dense fallback slots
@@ -827,17 +857,23 @@ static SampleLaunch base_launch(kad_sampler *s, int pool = 0)
 }
 
 // Launches `a` (built by base_launch for `pool`) on `slots` workgroups.
-// Hashed state: the two counters of defer list `list` are cleared by a
-// kernel, the hashed launch runs, then the pool's dense fallback slots
-// finish the samples it deferred (a launch that exits at once when there
-// are none).  Everything is enqueued on `st`, with kernels only, so that
-// the sequence may be captured in a graph.
-static hipError_t launch_pool(kad_sampler *s, SampleLaunch a, int pool, int list, int slots, hipStream_t st)
+// Hashed state: the hashed launch runs, then the pool's dense fallback
+// slots finish the samples it deferred (a launch that exits at once when
+// there are none).  The two counters of defer list `list` must be zero:
+// with `clear` a kernel clears them first (the epochs' lists are cleared
+// by the reset and then by each merge, so that no extra launch waits for
+// a CU between an epoch's sampler and the previous merge).  Everything is
+// enqueued on `st`, with kernels only, so that the sequence may be
+// captured in a graph.
+static unsigned long long *defer_counters(kad_sampler *s, int list) { return s->work_ctr + 8 + 2 * list; }
+
+static hipError_t launch_pool(kad_sampler *s, SampleLaunch a, int pool, int list, int slots, hipStream_t st,
+                              bool clear)
 {
     if (!s->sparse) return launch_sampler(a, slots, s->block, st);
-    unsigned long long *dc = s->work_ctr + 8 + 2 * list;
-    hipError_t e = launch_zero_words(reinterpret_cast<uint32_t *>(dc), 4, st);
-    if (e != hipSuccess) return e;
+    unsigned long long *dc = defer_counters(s, list);
+    hipError_t e = hipSuccess;
+    if (clear && (e = launch_zero_words(reinterpret_cast<uint32_t *>(dc), 4, st)) != hipSuccess) return e;
     a.sparse = 1;
     a.vcap_log2 = s->vlog2;
     a.claim_limit = s->claim_limit;
@@ -891,7 +927,7 @@ static kad_status count_into(kad_sampler *s, uint64_t stream, uint64_t first, ui
         a.hist_top = hist_top;
         HIPCHK(launch_zero_words(reinterpret_cast<uint32_t *>(a.work_ctr), 2, st));
         const int slots = (int)std::min<uint64_t>(s->slots, cnt);
-        HIPCHK(launch_pool(s, a, s->cal_pool, KAD_DEFER_LISTS - 1, slots, st));
+        HIPCHK(launch_pool(s, a, s->cal_pool, KAD_DEFER_LISTS - 1, slots, st, true));
     }
     return KAD_OK;
 }
@@ -923,6 +959,8 @@ extern "C" kad_status kad_set_delta(kad_sampler *s, const double *h_delta_L, con
     if (!(sum < 0.5L * (long double)s->o.delta))
         return fail(KAD_EINVAL, "sum of delta_L + delta_U must stay below delta / 2");
     s->LU = s->LU_own;   // delta_U may differ from delta_L here
+    s->L_lazy = false;
+    s->L_pending = false;
     // L = ln(1/delta) is taken once per vertex on the host in FP64 (the
     // C library's log), in the caller's numbering, then mapped in
     std::vector<double> Lh((size_t)n);
@@ -1032,6 +1070,8 @@ static kad_status ensure_delta(kad_sampler *s, const std::function<kad_status()>
         kad_status r = learned_prior(s);
         if (r != KAD_OK) return r;
         a.dense_prior = s->prior;
+        s->L_lazy = false;
+        s->L_pending = false;
         double C = 0.0;
         HIPCHK(run_alloc(a, st, &C));
         HIPCHK(hipStreamSynchronize(st));
@@ -1045,11 +1085,16 @@ static kad_status ensure_delta(kad_sampler *s, const std::function<kad_status()>
         const uint32_t top = (uint32_t)std::max<uint64_t>(1, s->tau0);
         if (s->cal_hist && s->cal_hist_top != top) {
             (void)hipFree(s->cal_hist);
+            (void)hipFree(s->cal_ltab);
             s->cal_hist = nullptr;
+            s->cal_ltab = nullptr;
         }
         if (!s->cal_hist) {
-            if (hipMalloc((void **)&s->cal_hist, sizeof(uint32_t) * ((size_t)top + 1)) != hipSuccess) {
+            if (hipMalloc((void **)&s->cal_hist, sizeof(uint32_t) * ((size_t)top + 1)) != hipSuccess ||
+                hipMalloc((void **)&s->cal_ltab, sizeof(double) * ((size_t)top + 1)) != hipSuccess) {
+                if (s->cal_hist) (void)hipFree(s->cal_hist);
                 s->cal_hist = nullptr;
+                s->cal_ltab = nullptr;
                 return fail(KAD_ENOMEM, "calibration histogram allocation failed");
             }
             s->cal_hist_top = top;
@@ -1064,10 +1109,18 @@ static kad_status ensure_delta(kad_sampler *s, const std::function<kad_status()>
         a.counts = s->cprime;
         a.tau0 = (double)s->tau0;
         a.hist = s->cal_hist;
+        a.ltab = s->cal_ltab;
+        // plain mode: the merges read L by count value; a learned run that
+        // fell back builds the arrays (its merges read them)
+        a.lazy = s->o.alloc_mode == KAD_ALLOC_PLAIN ? 1 : 0;
         double C = 0.0;
         HIPCHK(run_alloc(a, cst, &C));
         HIPCHK(hipStreamSynchronize(cst));
         s->C = C;
+        s->L_lazy = a.lazy != 0;
+        s->L_pending = s->L_lazy;
+        s->lazy_args = a;
+        s->lazy_C = C;
         r = check_stats_error(s, s->cal_stats, cst);
         if (r != KAD_OK) return r;
     }
@@ -1099,7 +1152,7 @@ static kad_status enqueue_sampler_k(kad_sampler *s, unsigned long long k, hipEve
     // by the merge of this stream's previous epoch
     if (ev0) HIPCHK(hipEventRecord(ev0, st));
     const int w = width > 0 ? std::min(width, s->slots) : s->slots;
-    HIPCHK(launch_pool(s, a, p, p, (int)std::min<unsigned long long>((unsigned long long)w, count), st));
+    HIPCHK(launch_pool(s, a, p, p, (int)std::min<unsigned long long>((unsigned long long)w, count), st, false));
     if (ev1) HIPCHK(hipEventRecord(ev1, st));
     return KAD_OK;
 }
@@ -1113,7 +1166,8 @@ static kad_status enqueue_merge_k(kad_sampler *s, unsigned long long k)
     if (k > 0) HIPCHK(hipStreamWaitEvent(st, s->ev_merge[(p + s->P - 1) % s->P], 0));
     HIPCHK(launch_merge_stop_impl(s->g->dev(), s->c, s->sf[p], s->sf[p], s->LL, s->LU, s->omega,
                                   s->o.epsilon, s->cap, s->E, s->es, s->work_ctr + p, s->hist, s->hist_cap,
-                                  s->d_status, st));
+                                  s->d_status, st, nullptr, 0, s->sparse ? defer_counters(s, p) : nullptr,
+                                  s->L_lazy ? s->cprime : nullptr, s->L_lazy ? s->cal_ltab : nullptr));
     HIPCHK(hipEventRecord(s->ev_merge[p], st));
     HIPCHK(hipEventRecord(s->ev_ring[k % s->ev_ring.size()], st));
     return KAD_OK;
@@ -1226,11 +1280,12 @@ static kad_status build_graph(kad_sampler *s)
         a.cap = s->cap;
         a.sf[0] = a.sf[1] = s->sf[p];
         a.stop_flag = &s->es->stopped;
-        chk(launch_pool(s, a, p, p, s->slots, sp), "sampler");
+        chk(launch_pool(s, a, p, p, s->slots, sp, false), "sampler");
         if (prev_merge) chk(hipStreamWaitEvent(sp, prev_merge, 0), "merge order");
         chk(launch_merge_stop_impl(s->g->dev(), s->c, s->sf[p], s->sf[p], s->LL, s->LU, s->omega, s->o.epsilon,
                                    s->cap, s->E, s->es, s->work_ctr + p, s->hist, s->hist_cap, s->d_status, sp,
-                                   s->pool_epoch + p, s->P),
+                                   s->pool_epoch + p, s->P, s->sparse ? defer_counters(s, p) : nullptr,
+                                   s->L_lazy ? s->cprime : nullptr, s->L_lazy ? s->cal_ltab : nullptr),
             "merge");
         chk(hipEventRecord(evs[ev], sp), "merge event");
         prev_merge = evs[ev++];
@@ -1407,6 +1462,17 @@ static kad_status copy_to_caller(const kad_graph *g, const double *d_in, double 
     return KAD_OK;
 }
 
+// The L arrays of a plain allocation, built from the count table when
+// first needed (the merges read the table).
+static kad_status ensure_L(const kad_sampler *s)
+{
+    if (!s->L_pending) return KAD_OK;
+    HIPCHK(run_alloc_L(s->lazy_args, s->lazy_C, s->ctx->stream));
+    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    s->L_pending = false;
+    return KAD_OK;
+}
+
 extern "C" kad_status kad_fetch_result(const kad_sampler *s, kad_result *out)
 {
     if (!s || !out) return fail(KAD_EINVAL, "null argument");
@@ -1464,6 +1530,8 @@ extern "C" kad_status kad_fetch_fg(const kad_sampler *s, double *h_f, double *h_
     if (r != KAD_OK) return r;
     hipStream_t st = s->ctx->stream;
     double *f = nullptr, *g = nullptr;
+    r = ensure_L(s);
+    if (r != KAD_OK) return r;
     HIPCHK(hipMallocAsync((void **)&f, 8ull * s->g->n, st));
     HIPCHK(hipMallocAsync((void **)&g, 8ull * s->g->n, st));
     HIPCHK(launch_fg(s->g->n, s->c, tau, s->LL, s->LU, s->omega, f, g, st));
@@ -1480,7 +1548,8 @@ extern "C" kad_status kad_fetch_delta(const kad_sampler *s, double *h_lnInvDL, d
     if (!s || !h_lnInvDL || !h_lnInvDU) return fail(KAD_EINVAL, "null argument");
     if (!s->delta_ready) return fail(KAD_ESTATE, "delta allocation not done");
     HIPCHK(hipSetDevice(s->ctx->device));
-    kad_status r = copy_to_caller(s->g, s->LL, h_lnInvDL, s->ctx->stream);
+    kad_status r = ensure_L(s);
+    if (r == KAD_OK) r = copy_to_caller(s->g, s->LL, h_lnInvDL, s->ctx->stream);
     if (r == KAD_OK) r = copy_to_caller(s->g, s->LU, h_lnInvDU, s->ctx->stream);
     return r;
 }

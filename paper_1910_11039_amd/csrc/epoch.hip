@@ -58,7 +58,9 @@ __global__ __launch_bounds__(MB) void k_merge_stop(int32_t n, uint32_t *c, uint3
                                                    unsigned long long E, EpochState *es,
                                                    unsigned long long *work_ctr, EpochHist *hist,
                                                    int32_t hist_cap, HostStatus *hs,
-                                                   unsigned long long *pool_epoch, int pools)
+                                                   unsigned long long *pool_epoch, int pools,
+                                                   unsigned long long *defer_ctr, const uint32_t *lcnt,
+                                                   const double *ltab)
 {
     if (__hip_atomic_load(&es->stopped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const unsigned long long first = es->range[0], count = es->range[1];
@@ -67,21 +69,61 @@ __global__ __launch_bounds__(MB) void k_merge_stop(int32_t n, uint32_t *c, uint3
     const double tau = (double)tau_u;
     int ok = 1;
     double mf = 0.0, mg = 0.0, mm = INFINITY;
-    for (int32_t v = blockIdx.x * MB + threadIdx.x; v < n; v += gridDim.x * MB) {
-        const uint32_t cv = c[v] + sf[v];
-        c[v] = cv;
-        sf[v] = 0;
-        const double bt = (double)cv / tau;
-        const double ll = LL[v];
-        const double lu = (LU == LL) ? ll : LU[v];   // one array when delta_L = delta_U
-        const double f = fval(bt, ll, omega, tau);
-        const double g = gval(bt, lu, omega, tau);
-        ok &= (f < eps && g < eps) ? 1 : 0;
-        mf = f > mf ? f : mf;
-        mg = g > mg ? g : mg;
-        double mar = eps - (f > g ? f : g);
-        mar = mar < 0 ? -mar : mar;
-        mm = mar < mm ? mar : mm;
+    // f and g of the thread's previous vertex, reused when the next has the
+    // same count and the same L bits (the same inputs give the same FP64
+    // results): nearly every vertex of a large graph is never counted, and
+    // with the calibrated allocation all uncounted vertices of one
+    // calibration count share L, so the divisions and square roots run for
+    // a small share of the vertices.  Four vertices a thread per round keep
+    // their loads in flight together.
+    uint32_t m_cv = 0xFFFFFFFFu;
+    uint64_t m_ll = 0, m_lu = 0;
+    double m_f = 0.0, m_g = 0.0;
+    constexpr int R = 4;
+    const int64_t stride = (int64_t)gridDim.x * MB;
+    for (int64_t v0 = (int64_t)blockIdx.x * MB + threadIdx.x; v0 < n; v0 += R * stride) {
+        uint32_t cv[R];
+        double ll[R], lu[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int64_t v = v0 + j * stride;
+            cv[j] = 0;
+            ll[j] = lu[j] = 0.0;
+            if (v < n) {
+                cv[j] = c[v] + sf[v];
+                // the calibrated allocation by count value (delta_L =
+                // delta_U), or the L arrays
+                ll[j] = ltab ? ltab[lcnt[v]] : LL[v];
+                lu[j] = (ltab || LU == LL) ? ll[j] : LU[v];   // one array when delta_L = delta_U
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int64_t v = v0 + j * stride;
+            if (v >= n) continue;
+            c[v] = cv[j];
+            sf[v] = 0;
+            double f, g;
+            if (cv[j] == m_cv && bits(ll[j]) == m_ll && bits(lu[j]) == m_lu) {
+                f = m_f;
+                g = m_g;
+            } else {
+                const double bt = (double)cv[j] / tau;
+                f = fval(bt, ll[j], omega, tau);
+                g = gval(bt, lu[j], omega, tau);
+                m_cv = cv[j];
+                m_ll = bits(ll[j]);
+                m_lu = bits(lu[j]);
+                m_f = f;
+                m_g = g;
+            }
+            ok &= (f < eps && g < eps) ? 1 : 0;
+            mf = f > mf ? f : mf;
+            mg = g > mg ? g : mg;
+            double mar = eps - (f > g ? f : g);
+            mar = mar < 0 ? -mar : mar;
+            mm = mar < mm ? mar : mm;
+        }
     }
     // block reduction
     __shared__ int s_ok;
@@ -138,6 +180,10 @@ __global__ __launch_bounds__(MB) void k_merge_stop(int32_t n, uint32_t *c, uint3
     es->range[1] = stop ? 0 : ((cap - nfirst) < E ? (cap - nfirst) : E);
     es->range[2] = ep + 1;
     if (work_ctr) *work_ctr = 0;
+    if (defer_ctr) {   // the pool's deferred-sample counters, for its next epoch
+        defer_ctr[0] = 0;
+        defer_ctr[1] = 0;
+    }
     if (pool_epoch) *pool_epoch += (unsigned long long)pools;   // this pool's next epoch
     __threadfence();
     __hip_atomic_store(&es->stopped, stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -295,16 +341,52 @@ __global__ __launch_bounds__(HB) void k_alloc_bisect_hist(AllocArgs a, const uin
     }
 }
 
-__global__ void k_alloc_delta(AllocArgs a, double C)
+__device__ __forceinline__ double alloc_L(const AllocArgs &a, double p, double C)
 {
     const double floor_d = a.beta * a.delta / (4.0 * (double)a.n);
+    double dv = floor_d;
+    if (p > 0.0) dv = (1.0 - a.beta) * exp(-C / p) + floor_d;
+    return -log(dv);
+}
+
+__global__ void k_alloc_delta(AllocArgs a, double C)
+{
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
-        const double p = prior_of(a, v);
-        double dv = floor_d;
-        if (p > 0.0) dv = (1.0 - a.beta) * exp(-C / p) + floor_d;
-        const double L = -log(dv);
+        const double L = alloc_L(a, prior_of(a, v), C);
         a.LL[v] = L;
-        a.LU[v] = L;
+        if (a.LU != a.LL) a.LU[v] = L;
+    }
+}
+
+// Calibration priors take the tau0 + 1 values c / tau0: L is computed once
+// per count value (the same expression as for a dense prior) ...
+__global__ void k_alloc_ltab(AllocArgs a, double C, uint32_t top, double *ltab)
+{
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c <= top; c += gridDim.x * blockDim.x)
+        ltab[c] = alloc_L(a, (double)c / a.tau0, C);
+}
+
+// ... and every vertex takes its count's value: a pass of 4 bytes read and
+// 8 written per vertex instead of an exponential and a logarithm in FP64
+// each, on the few CUs the samplers beside the calibration leave free.
+__global__ void k_alloc_delta_counts(AllocArgs a, double C, uint32_t top, const double *ltab)
+{
+    constexpr int R = 8;   // vertices a thread per round, their loads in flight together
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v0 < a.n; v0 += R * stride) {
+        uint32_t c[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) c[j] = v0 + j * stride < a.n ? a.counts[v0 + j * stride] : 0u;
+        double L[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) L[j] = c[j] <= top ? ltab[c[j]] : alloc_L(a, (double)c[j] / a.tau0, C);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int64_t v = v0 + j * stride;
+            if (v >= a.n) continue;
+            a.LL[v] = L[j];
+            if (a.LU != a.LL) a.LU[v] = L[j];
+        }
     }
 }
 
@@ -803,14 +885,15 @@ hipError_t launch_merge_stop_impl(const DevGraph &g, uint32_t *c, uint32_t *sf0,
                                   const double *LL, const double *LU, double omega, double eps,
                                   unsigned long long cap, unsigned long long E, EpochState *es,
                                   unsigned long long *work_ctr, void *hist, int32_t hist_cap,
-                                  HostStatus *hs, hipStream_t st, unsigned long long *pool_epoch, int pools)
+                                  HostStatus *hs, hipStream_t st, unsigned long long *pool_epoch, int pools,
+                                  unsigned long long *defer_ctr, const uint32_t *lcnt, const double *ltab)
 {
     // At most 256 workgroups: the merge runs while sampler workgroups hold
     // the CUs, and each of its workgroups waits for a slot that one of them
     // gives up; fewer, longer workgroups finish the merge sooner there.
     hipLaunchKernelGGL(k_merge_stop, dim3(grid_for(g.n, MB, 256)), dim3(MB), 0, st, g.n, c, sf0, sf1,
                        LL, LU, omega, eps, cap, E, es, work_ctr, (EpochHist *)hist, hist_cap, hs, pool_epoch,
-                       pools);
+                       pools, defer_ctr, lcnt, ltab);
     return hipGetLastError();
 }
 
@@ -851,7 +934,15 @@ hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host)
         CK(hipMemcpyAsync(fin, a.lo_hi, sizeof(fin), hipMemcpyDeviceToHost, st));
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
         const double C = fin[1];
-        hipLaunchKernelGGL(k_alloc_delta, dim3(grid_for(a.n, 256, 256)), dim3(256), 0, st, a, C);
+        if (a.ltab) {
+            hipLaunchKernelGGL(k_alloc_ltab, dim3(grid_for((int64_t)top + 1, 256, 64)), dim3(256), 0, st, a, C, top,
+                               a.ltab);
+            if (!a.lazy)
+                hipLaunchKernelGGL(k_alloc_delta_counts, dim3(grid_for(a.n, 256, 256)), dim3(256), 0, st, a, C, top,
+                                   a.ltab);
+        } else {
+            hipLaunchKernelGGL(k_alloc_delta, dim3(grid_for(a.n, 256, 256)), dim3(256), 0, st, a, C);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         *C_host = C;
         return hipSuccess;
@@ -893,6 +984,13 @@ hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host)
 }
 
 size_t alloc_partials(int32_t n) { return (size_t)((n + 4095) / 4096); }
+
+hipError_t run_alloc_L(const AllocArgs &a, double C, hipStream_t st)
+{
+    const uint32_t top = (uint32_t)std::max(1.0, a.tau0);
+    hipLaunchKernelGGL(k_alloc_delta_counts, dim3(grid_for(a.n, 256)), dim3(256), 0, st, a, C, top, a.ltab);
+    return hipGetLastError();
+}
 
 namespace {
 // Budget check of an allocation: per workgroup, the sum of delta_L + delta_U

@@ -160,7 +160,8 @@ hipError_t launch_merge_stop_impl(const DevGraph &g, uint32_t *c, uint32_t *sf0,
                                   unsigned long long cap, unsigned long long E, EpochState *es,
                                   unsigned long long *work_ctr, void *hist, int32_t hist_cap,
                                   HostStatus *hs, hipStream_t st, unsigned long long *pool_epoch = nullptr,
-                                  int pools = 0);
+                                  int pools = 0, unsigned long long *defer_ctr = nullptr,
+                                  const uint32_t *lcnt = nullptr, const double *ltab = nullptr);
 size_t epoch_hist_bytes();   // per-epoch record: max_f, max_g, min_margin (f64), ok (i32), pad
 size_t alloc_partials(int32_t n);
 hipError_t launch_fg(int32_t n, const uint32_t *c, double tau, const double *LL, const double *LU,
@@ -181,8 +182,12 @@ struct AllocArgs {
     double *partials;    // device scratch, one per block
     double *LL, *LU;     // out
     uint32_t *hist;      // optional: histogram of the counts already built (bins 1..tau0)
+    double *ltab;        // optional: room for tau0 + 1 doubles (L by count value)
+    int lazy;            // with ltab: fill only the table (LL is built later by run_alloc_L)
 };
 hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host);
+// LL (= LU) from the count table that a lazy run_alloc filled.
+hipError_t run_alloc_L(const AllocArgs &a, double C, hipStream_t st);
 // Sum over v of delta_L(v) + delta_U(v) = e^-LL + e^-LU on the device
 // (compensated per thread, pairwise across threads), and whether every L is
 // finite and positive.

@@ -30,13 +30,28 @@ constexpr int PSTRIDE = NP + 1; // per-block partial: gradient then loss
 constexpr int OFF_W1 = 0, OFF_B1 = 192, OFF_W2 = 256, OFF_B2 = 4352, OFF_W3 = 4416, OFF_B3 = 4480;
 
 // ln(1 + deg u) and deg u (FP64) of a neighbour u: the 4-byte degree is
-// gathered and the logarithm taken here.  (A precomputed 16-byte table
-// per vertex stops fitting the caches on large graphs, where the gathers
-// then dominate; the logarithm is cheap next to a missed line.)
-__device__ __forceinline__ double2 logdeg(const DevGraph &g, int32_t u)
+// gathered and the logarithm read from a table indexed by degree, lt[d] =
+// ln(1 + d) for d = 0 .. max degree, filled once per pass.  The FP64
+// logarithm is about 120 FP64 instructions, which over the 2 nnz entries
+// of a large graph cost more than the whole gather; the table's hot part
+// (the small degrees, and the few hubs' entries) stays in cache, and a
+// 16-byte table per vertex would not.
+__device__ __forceinline__ double2 logdeg(const DevGraph &g, const double *lt, int32_t u)
 {
-    const double d = (double)g.deg[u];
-    return make_double2(log1p(d), d);
+    const uint32_t d = g.deg[u];
+    // (a degree of n or more, possible only with repeated entries, is
+    // beyond the table)
+    return make_double2(d < (uint32_t)g.n ? lt[d] : log1p((double)d), (double)d);
+}
+
+// lt[d] = ln(1 + d) for d = 0 .. min(deg[0], n - 1) (vertex 0 has the
+// largest degree in the internal numbering).
+__global__ void k_logtab(DevGraph g, double *lt)
+{
+    const int64_t top = min((int64_t)g.deg[0], (int64_t)g.n - 1);
+    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d <= top;
+         d += (int64_t)gridDim.x * blockDim.x)
+        lt[d] = log1p((double)d);
 }
 
 constexpr int64_t FPIECE = 8192;   // rows longer than this are summed in pieces
@@ -54,7 +69,7 @@ constexpr int64_t FSHORT = 32;     // rows up to this long: a thread per vertex
 // entries eight at a time.
 // (Vertices are numbered by descending degree: the short rows are those of
 // vertices bnd[1] .. n-1.)
-__global__ void k_features_short(DevGraph g, const int32_t *bnd, float *out)
+__global__ void k_features_short(DevGraph g, const int32_t *bnd, const double *lt, float *out)
 {
     const int64_t first = bnd[1];
     for (int64_t v = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
@@ -68,7 +83,7 @@ __global__ void k_features_short(DevGraph g, const int32_t *bnd, float *out)
             for (int j = 0; j < B; ++j) u[j] = (e0 + j < end) ? g.ci[e0 + j] : -1;
             double2 p[B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? logdeg(g, u[j]) : make_double2(0.0, 0.0);
+            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? logdeg(g, lt, u[j]) : make_double2(0.0, 0.0);
 #pragma unroll
             for (int j = 0; j < B; ++j) {
                 if (u[j] < 0) continue;
@@ -80,27 +95,38 @@ __global__ void k_features_short(DevGraph g, const int32_t *bnd, float *out)
     }
 }
 
-// Rows of FSHORT + 1 .. FPIECE entries: a wave per vertex, vertices
-// bnd[0] .. bnd[1]-1 (the longer rows, vertices 0 .. bnd[0]-1, go in pieces).
-__global__ void k_features(DevGraph g, const int32_t *bnd, float *out)
+constexpr int64_t FMID = 256;      // rows up to this long: eight lanes per vertex
+
+// Rows of medium length: a group of G lanes per vertex (G = 8 for rows of
+// FSHORT + 1 .. FMID entries, vertices bnd[2] .. bnd[1]-1; G = 64 for rows
+// of FMID + 1 .. FPIECE, vertices bnd[0] .. bnd[2]-1; the longer rows,
+// vertices 0 .. bnd[0]-1, go in pieces).  A lane keeps eight entries in
+// flight; G is matched to the row length so that most lanes have loads
+// to issue (a wave per vertex left seven of eight batches empty on rows
+// of a few dozen entries).
+template <int G>
+__global__ void k_features_group(DevGraph g, const int32_t *bnd, const double *lt, float *out)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t lo = bnd[0], hi = bnd[1];
-    for (int64_t v = lo + wave; v < hi; v += waves) {
-        const int64_t beg = g.rp[v], end = g.rp[v + 1];
+    const int sub = threadIdx.x & (G - 1);
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t grps = ((int64_t)gridDim.x * blockDim.x) / G;
+    const int64_t lo = G == 64 ? bnd[0] : bnd[2], hi = G == 64 ? bnd[2] : bnd[1];
+    // every lane of a wave runs the same number of iterations (the row's
+    // sum needs all G lanes of its group at the shuffles)
+    const int64_t span = hi - lo, iters = (span + grps - 1) / grps;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t v = lo + grp + it * grps;
+        const bool own = v < hi;
+        const int64_t beg = own ? g.rp[v] : 0, end = own ? g.rp[v + 1] : 0;
         double acc = 0.0, sd = 0.0;
-        // eight entries per lane in flight: a hub's row is a long serial
-        // loop for its one wave, and the loads dominate it
         constexpr int B = 8;
-        for (int64_t e0 = beg + lane; e0 < end; e0 += 64 * B) {
+        for (int64_t e0 = beg + sub; e0 < end; e0 += G * B) {
             int32_t u[B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) u[j] = (e0 + 64 * j < end) ? g.ci[e0 + 64 * j] : -1;
+            for (int j = 0; j < B; ++j) u[j] = (e0 + G * j < end) ? g.ci[e0 + G * j] : -1;
             double2 p[B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? logdeg(g, u[j]) : make_double2(0.0, 0.0);
+            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? logdeg(g, lt, u[j]) : make_double2(0.0, 0.0);
 #pragma unroll
             for (int j = 0; j < B; ++j) {
                 if (u[j] < 0) continue;
@@ -108,11 +134,11 @@ __global__ void k_features(DevGraph g, const int32_t *bnd, float *out)
                 sd += p[j].y;
             }
         }
-        for (int o = 32; o > 0; o >>= 1) {
+        for (int o = G / 2; o > 0; o >>= 1) {
             acc += __shfl_xor(acc, o);
             sd += __shfl_xor(sd, o);
         }
-        if (lane == 0) write_features(out, v, (double)(end - beg), acc, sd);
+        if (own && sub == 0) write_features(out, v, (double)(end - beg), acc, sd);
     }
 }
 
@@ -135,6 +161,12 @@ __global__ __launch_bounds__(1024) void k_feat_pieces(DevGraph g, int64_t *pref,
         sH = lo;
         s_run = 0;
         H_out[0] = lo;
+        hi = g.n;                      // first vertex with at most FMID entries
+        while (lo < hi) {
+            const int32_t mid = lo + ((hi - lo) >> 1);
+            if ((int64_t)g.deg[mid] > FMID) lo = mid + 1; else hi = mid;
+        }
+        H_out[2] = lo;
         hi = g.n;                      // first vertex with at most FSHORT entries
         while (lo < hi) {
             const int32_t mid = lo + ((hi - lo) >> 1);
@@ -163,7 +195,7 @@ __global__ __launch_bounds__(1024) void k_feat_pieces(DevGraph g, int64_t *pref,
     if (tid == 0) pref[0] = 0;
 }
 
-__global__ void k_feat_sum(DevGraph g, const int64_t *pref, const int32_t *H_in,
+__global__ void k_feat_sum(DevGraph g, const int64_t *pref, const int32_t *H_in, const double *lt,
                            double2 *part)
 {
     const int lane = threadIdx.x & 63;
@@ -188,7 +220,7 @@ __global__ void k_feat_sum(DevGraph g, const int64_t *pref, const int32_t *H_in,
             for (int j = 0; j < B; ++j) u[j] = (e0 + 64 * j < e) ? g.ci[e0 + 64 * j] : -1;
             double2 p[B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? logdeg(g, u[j]) : make_double2(0.0, 0.0);
+            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? logdeg(g, lt, u[j]) : make_double2(0.0, 0.0);
 #pragma unroll
             for (int j = 0; j < B; ++j) {
                 if (u[j] < 0) continue;
@@ -543,29 +575,37 @@ int blocks_for_rows(int64_t rows)
 size_t mlp_scratch_floats(int64_t rows) { return (size_t)blocks_for_rows(rows) * PSTRIDE; }
 
 // Workspace of the feature pass: the prefix of the long rows' pieces, the
-// tier boundaries and the pieces' partial sums.  Long rows have more than
-// FPIECE entries each, so there are at most nnz / FPIECE of them and at
-// most 2 nnz / FPIECE + 1 pieces.
+// tier boundaries, the pieces' partial sums and the logarithm table (n
+// entries at most: no degree reaches n).  Long rows have more than FPIECE
+// entries each, so there are at most nnz / FPIECE of them and at most
+// 2 nnz / FPIECE + 1 pieces.
 size_t features_workspace_bytes(const DevGraph &g)
 {
     const int64_t hmax = g.nnz / FPIECE + 1, pmax = 2 * (g.nnz / FPIECE) + 1;
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
-    return up(sizeof(int64_t) * (size_t)(hmax + 1)) + 256 + up(sizeof(double2) * (size_t)pmax);
+    return up(sizeof(int64_t) * (size_t)(hmax + 1)) + 256 + up(sizeof(double2) * (size_t)pmax) +
+           up(sizeof(double) * (size_t)g.n);
 }
 
 hipError_t launch_features_ws(const DevGraph &g, float *out, void *ws, hipStream_t st)
 {
-    const int64_t hmax = g.nnz / FPIECE + 1;
+    const int64_t hmax = g.nnz / FPIECE + 1, pmax = 2 * (g.nnz / FPIECE) + 1;
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     int64_t *pref = (int64_t *)ws;
     int32_t *H = (int32_t *)((char *)ws + up(sizeof(int64_t) * (size_t)(hmax + 1)));  // tier boundaries
     double2 *part = (double2 *)((char *)H + 256);
+    double *lt = (double *)((char *)part + up(sizeof(double2) * (size_t)pmax));
+    const int64_t tblocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_logtab, dim3((unsigned)tblocks), dim3(256), 0, st, g, lt);
     hipLaunchKernelGGL(k_feat_pieces, dim3(1), dim3(1024), 0, st, g, pref, H);
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_features_short, dim3((unsigned)blocks), dim3(256), 0, st, g, H, out);
+    hipLaunchKernelGGL(k_features_short, dim3((unsigned)blocks), dim3(256), 0, st, g, H, lt, out);
     const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(g.n, 1 << 16));
-    hipLaunchKernelGGL(k_features, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, H, out);
-    hipLaunchKernelGGL(k_feat_sum, dim3(2048), dim3(256), 0, st, g, pref, H, part);
+    hipLaunchKernelGGL(k_features_group<8>, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, H,
+                       lt, out);
+    hipLaunchKernelGGL(k_features_group<64>, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, H,
+                       lt, out);
+    hipLaunchKernelGGL(k_feat_sum, dim3(2048), dim3(256), 0, st, g, pref, H, lt, part);
     hipLaunchKernelGGL(k_feat_combine, dim3(64), dim3(256), 0, st, g, pref, H, part, out);
     return hipGetLastError();
 }

@@ -153,7 +153,7 @@ struct Smem {
     int32_t me_a[MEDGE];         // meet edges of the current chunk: owner index in the chunk,
     int32_t me_w[MEDGE];         // and the meet vertex
     uint32_t filt[Filter<BS>::WORDS];
-    int32_t tail, mcount, ovf, err, w, wmin, mpath, nme, fold_bad, pathc, vsfull;
+    int32_t tail, mcount, ovf, err, w, wmin, mpath, nme, fold_bad, pathc, vsfull, quit;
     uint32_t stamp;
     int32_t s, t;
 };
@@ -1402,7 +1402,7 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
         int32_t kX = 0, kY = 0, m = 0;
         unsigned long long edges = 0;
         int steps = 0;
-        bool failed = false, deferred = false;
+        bool failed = false, deferred = false, quit = false;
         const unsigned long long vis0 = ls.visited, pred0 = ls.pred, exp0 = st_exp;
         for (;;) {  // attempt (integer mode, then FP mode if it overflowed)
             attempts += 1;
@@ -1448,6 +1448,7 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                 sm.nextdeg = 0;
                 sm.fmax_bits = 0;
                 sm.vsfull = 0;
+                sm.quit = 0;
             }
             __syncthreads();
             c.fp = fp;
@@ -1505,11 +1506,20 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                     sm.mcount = 0;
                     sm.nextdeg = 0;
                     sm.fmax_bits = 0;
+                    // the run stopped while this (speculative) sample was
+                    // searching: its counts would never be merged
+                    sm.quit = a.stop_flag ? __hip_atomic_load(a.stop_flag, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT)
+                                          : 0;
                 }
                 __syncthreads();
+                if (sm.quit) {
+                    quit = true;
+                    break;
+                }
             }
             st_all += edges;
-            if (failed || deferred) break;
+            if (failed || deferred || quit) break;
             if (!fp && sm.ovf) { __syncthreads(); fp = 1; continue; }
             kX = sm.dep[X];
             kY = sm.dep[1 - X];
@@ -1525,6 +1535,13 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
         }
         if (failed) {
             if (tid == 0) a.stats->error = 1;
+            __syncthreads();
+            continue;
+        }
+        if (quit) {   // abandoned: the sample loop sees the stop and ends
+            ls.visited = vis0;
+            ls.pred = pred0;
+            st_exp = exp0;
             __syncthreads();
             continue;
         }
