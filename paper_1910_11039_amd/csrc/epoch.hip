@@ -234,62 +234,99 @@ __device__ __forceinline__ double prior_of(const AllocArgs &a, int32_t v)
     return a.counts ? (double)a.counts[v] / a.tau0 : a.dense_prior[v];
 }
 
-__global__ __launch_bounds__(AB) void k_alloc_count(AllocArgs a, unsigned long long *K)
-{
-    unsigned long long k = 0;
-    for (int32_t v = blockIdx.x * AB + threadIdx.x; v < a.n; v += gridDim.x * AB)
-        k += prior_of(a, v) > 0.0 ? 1 : 0;
-    for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o);
-    if ((threadIdx.x & 63) == 0 && k) atomicAdd(K, k);
-}
+// A dense prior's constant C: the root of S(C) = T for S(C) = sum over
+// p > 0 of exp(-C / p) and T = delta / 4 (1 - 1e-9).  ln S is convex and
+// decreasing in C, so Newton's method on ln S - ln T started at C = 0
+// rises monotonically to the root; once a step no longer moves C, C is
+// raised by relative steps of 2^-40 until S(C) <= T holds.  (The same C as
+// the bisection of the calibrated prior up to about 1e-12 relative, in
+// about a tenth of the passes over the vertices.)  One launch per step:
+// each workgroup sums its fixed vertex range (S, and M = sum exp(-C/p)/p),
+// the last to finish adds the partial sums in a fixed order and takes the
+// step.
+struct NewtonState {
+    double C;
+    int32_t phase;   // 0: Newton steps, 1: checking S(C) <= T
+    int32_t done;
+    unsigned int blocks_done;
+    int32_t steps;
+};
 
-// Partial sums of exp(-mid / prior) over fixed vertex ranges, reduced in a
-// fixed order (run-to-run deterministic).
-__global__ __launch_bounds__(AB) void k_alloc_sum(AllocArgs a, int32_t chunk)
+__global__ __launch_bounds__(AB) void k_alloc_newton(AllocArgs a, int32_t chunk, double target)
 {
-    const double lo = a.lo_hi[0], hi = a.lo_hi[1];
-    if (a.lo_hi[2] != 0.0) return;
-    const double mid = 0.5 * (lo + hi);
+    NewtonState *ns = reinterpret_cast<NewtonState *>(a.lo_hi);
+    if (__hip_atomic_load(&ns->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const double C = ns->C;
     const int32_t beg = blockIdx.x * chunk;
     const int32_t end = min(a.n, beg + chunk);
-    double s = 0.0;
+    double sS = 0.0, sM = 0.0;
     for (int32_t v = beg + threadIdx.x; v < end; v += AB) {
-        const double p = prior_of(a, v);
-        if (p > 0.0) s = s + exp(-mid / p);
+        const double p = a.dense_prior[v];
+        if (p > 0.0) {
+            const double e = exp(-C / p);
+            sS = sS + e;
+            sM = sM + e / p;
+        }
     }
-    __shared__ double red[AB];
-    red[threadIdx.x] = s;
+    __shared__ double rs[AB], rm[AB];
+    __shared__ int last;
+    rs[threadIdx.x] = sS;
+    rm[threadIdx.x] = sM;
     __syncthreads();
     for (int o = AB / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + o];
+        if ((int)threadIdx.x < o) {
+            rs[threadIdx.x] = rs[threadIdx.x] + rs[threadIdx.x + o];
+            rm[threadIdx.x] = rm[threadIdx.x] + rm[threadIdx.x + o];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
-}
-
-// One bisection step: the partial sums added in a fixed order (thread t
-// takes partials t, t + AB, ... in turn, then a pairwise tree).
-__global__ __launch_bounds__(AB) void k_alloc_update(double *lo_hi, const double *partials, int32_t nb,
-                                                     double target)
-{
-    __shared__ double red[AB];
-    if (lo_hi[2] != 0.0) return;
-    const double lo = lo_hi[0], hi = lo_hi[1];
-    const double mid = 0.5 * (lo + hi);
-    double s = 0.0;
-    for (int32_t b = threadIdx.x; b < nb; b += AB) s = s + partials[b];
-    red[threadIdx.x] = s;
+    if (threadIdx.x == 0) {
+        a.partials[2 * blockIdx.x] = rs[0];
+        a.partials[2 * blockIdx.x + 1] = rm[0];
+        __threadfence();
+        last = atomicAdd(&ns->blocks_done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // the last workgroup: the partial sums in a fixed order (thread t takes
+    // blocks t, t + AB, ... in turn, then a pairwise tree)
+    const int32_t nb = (int32_t)gridDim.x;
+    sS = 0.0;
+    sM = 0.0;
+    for (int32_t b = threadIdx.x; b < nb; b += AB) {
+        sS = sS + __hip_atomic_load(&a.partials[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sM = sM + __hip_atomic_load(&a.partials[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    rs[threadIdx.x] = sS;
+    rm[threadIdx.x] = sM;
     __syncthreads();
     for (int o = AB / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + o];
+        if ((int)threadIdx.x < o) {
+            rs[threadIdx.x] = rs[threadIdx.x] + rs[threadIdx.x + o];
+            rm[threadIdx.x] = rm[threadIdx.x] + rm[threadIdx.x + o];
+        }
         __syncthreads();
     }
     if (threadIdx.x != 0) return;
-    if (mid <= lo || mid >= hi) {
-        lo_hi[2] = 1.0;
-        return;
+    const double S = rs[0], M = rm[0];
+    ns->blocks_done = 0;
+    ns->steps += 1;
+    if (!(S == S) || !(M == M) || ns->steps > 400) {
+        ns->done = 1;   // a prior that is not finite: the allocation fails its check
+    } else if (ns->phase == 0) {
+        if (S <= target) {
+            ns->done = 1;   // also C = 0 when the sum starts at or below T
+        } else {
+            const double Cn = C + (log(S) - log(target)) * (S / M);
+            if (Cn > C) ns->C = Cn;
+            else ns->phase = 1;   // converged from below: check, then raise
+        }
+    } else {
+        if (S <= target) ns->done = 1;
+        else ns->C = C > 0.0 ? C * (1.0 + 0x1p-40) : 0x1p-1000;
     }
-    if (red[0] <= target) lo_hi[1] = mid; else lo_hi[0] = mid;
+    __threadfence();
 }
 
 // Calibration priors are counts over tau0, so the sum over vertices is a
@@ -947,43 +984,29 @@ hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host)
         *C_host = C;
         return hipSuccess;
     }
-    unsigned long long *dK = nullptr;
-    if ((e = hipMallocAsync((void **)&dK, sizeof(unsigned long long), st)) != hipSuccess) return e;
-    CK(hipMemsetAsync(dK, 0, sizeof(unsigned long long), st));
-    hipLaunchKernelGGL(k_alloc_count, dim3(grid_for(a.n, AB, 1024)), dim3(AB), 0, st, a, dK);
-    unsigned long long K = 0;
-    CK(hipMemcpyAsync(&K, dK, sizeof(K), hipMemcpyDeviceToHost, st));
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    CK(hipFreeAsync(dK, st));
-    double C = 0.0;
-    if (K > 0) {
-        double init[3] = {0.0, log((double)K / target), 0.0};
-        if (init[1] < 0.0) init[1] = 0.0;
-        CK(hipMemcpyAsync(a.lo_hi, init, sizeof(init), hipMemcpyHostToDevice, st));
-        const int32_t chunk = 4096;
-        const int32_t nb = (a.n + chunk - 1) / chunk;
-        for (int it = 0; it < 200; ++it) {
-            hipLaunchKernelGGL(k_alloc_sum, dim3(nb), dim3(AB), 0, st, a, chunk);
-            hipLaunchKernelGGL(k_alloc_update, dim3(1), dim3(AB), 0, st, a.lo_hi, a.partials, nb, target);
-            if ((it & 31) == 31) {
-                double fin[3];
-                CK(hipMemcpyAsync(fin, a.lo_hi, sizeof(fin), hipMemcpyDeviceToHost, st));
-                if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-                if (fin[2] != 0.0) break;
-            }
+    // dense prior: Newton's method on ln S (k_alloc_newton), a launch per
+    // step, the state read back after 12 steps and then every 8
+    NewtonState init{};
+    CK(hipMemcpyAsync(a.lo_hi, &init, sizeof(init), hipMemcpyHostToDevice, st));
+    const int32_t chunk = 8192;
+    const int32_t nb = (a.n + chunk - 1) / chunk;
+    NewtonState fin{};
+    for (int it = 0; it < 400 && !fin.done; ++it) {
+        hipLaunchKernelGGL(k_alloc_newton, dim3(nb), dim3(AB), 0, st, a, chunk, target);
+        if (it == 11 || (it > 11 && (it - 11) % 8 == 0)) {
+            CK(hipMemcpyAsync(&fin, a.lo_hi, sizeof(fin), hipMemcpyDeviceToHost, st));
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
         }
-        double fin[3];
-        CK(hipMemcpyAsync(fin, a.lo_hi, sizeof(fin), hipMemcpyDeviceToHost, st));
-        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-        C = fin[1];
     }
+    if (!fin.done) return hipErrorUnknown;
+    const double C = fin.C;
     hipLaunchKernelGGL(k_alloc_delta, dim3(grid_for(a.n, 256)), dim3(256), 0, st, a, C);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     *C_host = C;
     return hipSuccess;
 }
 
-size_t alloc_partials(int32_t n) { return (size_t)((n + 4095) / 4096); }
+size_t alloc_partials(int32_t n) { return 2 * (size_t)((n + 8191) / 8192) + 2; }   // S and M per workgroup
 
 hipError_t run_alloc_L(const AllocArgs &a, double C, hipStream_t st)
 {
