@@ -127,12 +127,13 @@ typedef struct {
                                   /* per vertex in every slot), 2 hashed (a table */
                                   /* of 2^visited_log2 buckets per slot; samples  */
                                   /* that would fill it over 3/4 are finished on  */
-                                  /* a few dense slots per pool); 0 = auto:       */
-                                  /* hashed when dense slots do not fit four      */
-                                  /* pools of a full wave, the table is at most   */
-                                  /* 1/8 of a dense slot and the bracket's vertex */
-                                  /* diameter is at most 32; else dense.  Hashed  */
-                                  /* with block_size 0 uses 1024 threads          */
+                                  /* a dense slot per pool); 0 = auto: hashed     */
+                                  /* when the dense state holds fewer than 1.25   */
+                                  /* full waves of 1024-thread slots, the table   */
+                                  /* is at most 1/8 of a dense slot and the       */
+                                  /* bracket's vertex diameter is at most 32;     */
+                                  /* else dense.  Hashed with block_size 0 uses   */
+                                  /* 1024 threads                                 */
     int32_t visited_log2;         /* hashed table size; 0 = the power of two at   */
                                   /* or above n / 32 within [2^16, 2^22];         */
                                   /* else within [10, 26]                         */

@@ -647,15 +647,21 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
         delete s;
         return fail(KAD_EINVAL, "pools must be 0 (auto) or 1..4");
     }
-    // Auto: hashed when the dense state cannot hold four pools of a full
-    // wave, the table is at most an eighth of a dense slot, and the graph is
+    // Auto: hashed when the dense state holds fewer than 1.25 full waves of
+    // 1024-thread slots (so that two dense pools would leave CUs idle), the
+    // table is at most an eighth of a dense slot, and the graph is
     // small-world (vertex diameter at most 32 by the bracket), so that a
     // search claims a small share of the vertices and deferrals stay rare;
-    // otherwise (and when omega was given, with no bracket) dense.
+    // otherwise (and when omega was given, with no bracket) dense.  (On the
+    // R-MAT and hyperbolic sweep, 2^23..2^26 vertices, hashed won where the
+    // dense state held 1-1.1 waves: 15% and 34% at 2^26; where it held two
+    // or more, dense was 6-25% faster.)
     s->sparse = o->visited_mode == KAD_VISITED_HASHED;
-    if (o->visited_mode == KAD_VISITED_AUTO && o->slots <= 0)
-        s->sparse = budget / per_dense < 4 * (size_t)full_wave(false) && per_sparse * 8 <= per_dense &&
-                    s->vd_hi > 0 && s->vd_hi <= 32;
+    if (o->visited_mode == KAD_VISITED_AUTO && o->slots <= 0) {
+        const size_t wave1024 = (size_t)ctx->cu_count * (size_t)sampler_blocks_per_cu(1024, false);
+        s->sparse = budget / per_dense * 4 < 5 * wave1024 && per_sparse * 8 <= per_dense && s->vd_hi > 0 &&
+                    s->vd_hi <= 32;
+    }
     // Hashed state without a given shape: 1024-thread workgroups, not the
     // trial's pick.  A trial times one launch; with four overlapped pools
     // the 512-thread shape it favoured ran R-MAT 26 to the stop in 69 ms

@@ -271,3 +271,38 @@ def test_mlp_train_entry_point_matches_oracle_loop(ctx, oracle):
         scale = max(np.abs(po[sl]).max(), 1e-3)
         assert np.abs(params[sl] - po[sl]).max() <= 2e-3 * scale, name
     assert losses[-1] < losses[0]
+
+
+def test_learned_arm_on_held_out_rmat22(ctx, oracle):
+    """The learned-vs-plain configuration as benchmarked: R-MAT scale 22,
+    edge factor 16 (held out from training), eps = 0.01, delta = 0.1, the
+    autotuned launch shape.  For three seeds the learned allocation spends
+    no calibration samples, stops on the condition after fewer samples in
+    total than the plain arm, and certifies max(f, g) < eps at its stop.
+    (Sample counts are deterministic; the times, printed, are not asserted.)"""
+    import time
+    params, norm = L.load()
+    g = gg.workload("rmat22")
+    G = K.Graph(ctx, g)
+    res = {}
+    for arm, mode in (("plain", K.KAD_ALLOC_PLAIN), ("learned", K.KAD_ALLOC_LEARNED)):
+        S = K.Sampler(G, seed=1, epsilon=0.01, delta=0.1, alloc_mode=mode)
+        if mode == K.KAD_ALLOC_LEARNED:
+            S.set_mlp_weights(params, norm)
+        S.reset(1000)
+        S.run_to_stop()
+        out = []
+        for seed in (1, 2, 3):
+            t0 = time.perf_counter()
+            S.reset(seed)
+            r = S.run_to_stop()
+            ms = 1e3 * (time.perf_counter() - t0)
+            assert r.stop_reason == K.KAD_STOP_COND
+            assert max(r.max_f, r.max_g) < 0.01
+            assert (r.tau0 == 0) == (mode == K.KAD_ALLOC_LEARNED)
+            out.append((r.tau0 + r.tau, ms))
+        res[arm] = out
+        S.close()
+    print(f"rmat22 samples and ms per run: {res}", flush=True)
+    for (sp, _), (sl, _) in zip(res["plain"], res["learned"]):
+        assert sl < sp
