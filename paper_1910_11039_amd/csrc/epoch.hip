@@ -235,18 +235,20 @@ __device__ __forceinline__ double prior_of(const AllocArgs &a, int32_t v)
 }
 
 // A dense prior's constant C: the root of S(C) = T for S(C) = sum over
-// p > 0 of exp(-C / p) and T = delta / 4 (1 - 1e-9).  ln S is convex and
-// decreasing in C, so Newton's method on ln S - ln T started at C = 0
-// rises monotonically to the root; once a step no longer moves C, C is
-// raised by relative steps of 2^-40 until S(C) <= T holds.  (The same C as
-// the bisection of the calibrated prior up to about 1e-12 relative, in
-// about a tenth of the passes over the vertices.)  One launch per step:
-// each workgroup sums its fixed vertex range (S, and M = sum exp(-C/p)/p),
-// the last to finish adds the partial sums in a fixed order and takes the
-// step.
+// p > 0 of exp(-C / p) and T = delta / 4 (1 - 1e-9), i.e. the bisection's
+// answer (the smallest C with S(C) <= T) to within 2^-39 relative.  ln S is
+// convex and decreasing in C, so Newton's method on ln S - ln T rises
+// monotonically from the left; the step is kept inside the bracket
+// [lo, hi] of evaluated points (S(lo) > T >= S(hi); hi starts at
+// ln(K/T), K = S(0), where S <= T holds), and bisection takes over after
+// 60 Newton steps or when a step would leave the bracket.  When Newton
+// stalls just left of the root, C is raised by 2^-40 relative until
+// S(C) <= T.  One launch per evaluation: each workgroup sums its fixed
+// vertex range (S, and M = sum exp(-C/p)/p), the last to finish adds the
+// partial sums in a fixed order and picks the next point.
 struct NewtonState {
-    double C;
-    int32_t phase;   // 0: Newton steps, 1: checking S(C) <= T
+    double C, lo, hi;
+    int32_t phase;   // 0: Newton, 1: raised just right of a stalled Newton iterate, 2: bisection
     int32_t done;
     unsigned int blocks_done;
     int32_t steps;
@@ -314,17 +316,39 @@ __global__ __launch_bounds__(AB) void k_alloc_newton(AllocArgs a, int32_t chunk,
     ns->steps += 1;
     if (!(S == S) || !(M == M) || ns->steps > 400) {
         ns->done = 1;   // a prior that is not finite: the allocation fails its check
-    } else if (ns->phase == 0) {
+    } else if (ns->steps == 1) {   // C = 0: S is the number of vertices with p > 0
         if (S <= target) {
-            ns->done = 1;   // also C = 0 when the sum starts at or below T
+            ns->done = 1;   // C = 0
         } else {
-            const double Cn = C + (log(S) - log(target)) * (S / M);
-            if (Cn > C) ns->C = Cn;
-            else ns->phase = 1;   // converged from below: check, then raise
+            ns->lo = 0.0;
+            ns->hi = fmax(0.0, log(S / target));
+            ns->C = fmin(ns->hi, (log(S) - log(target)) * (S / M));
         }
     } else {
-        if (S <= target) ns->done = 1;
-        else ns->C = C > 0.0 ? C * (1.0 + 0x1p-40) : 0x1p-1000;
+        double lo = ns->lo, hi = ns->hi;
+        if (S > target) lo = C; else hi = C;
+        ns->lo = lo;
+        ns->hi = hi;
+        const double mid = 0.5 * (lo + hi);
+        if (hi - lo <= hi * 0x1p-39 || mid <= lo || mid >= hi) {
+            ns->done = 1;
+            ns->C = hi;
+        } else if (S > target && ns->phase != 2) {
+            const double Cn = C + (log(S) - log(target)) * (S / M);
+            if (ns->steps > 60 || Cn >= hi) {
+                ns->phase = 2;
+                ns->C = mid;
+            } else if (Cn > C) {
+                ns->phase = 0;
+                ns->C = Cn;
+            } else {   // stalled left of the root
+                ns->phase = 1;
+                ns->C = C > 0.0 ? fmin(hi, C * (1.0 + 0x1p-40)) : fmin(hi, 0x1p-1000);
+            }
+        } else {
+            ns->phase = 2;
+            ns->C = mid;
+        }
     }
     __threadfence();
 }
