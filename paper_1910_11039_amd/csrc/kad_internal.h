@@ -195,7 +195,12 @@ hipError_t alloc_budget(int32_t n, const double *LL, const double *LU, hipStream
                         bool *finite_out);
 
 // Vertex-diameter bracket by BFS sweeps on the device.
-hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, int64_t *vd_hi);
+// cache (optional): BFS arrays kept between calls on the same graph.
+struct BfsCache;
+BfsCache *bfs_cache_create();
+void bfs_cache_free(BfsCache *c, hipStream_t st);
+hipError_t device_vd_bracket(const DevGraph &g, hipStream_t st, int64_t *vd_lo, int64_t *vd_hi,
+                             BfsCache *cache = nullptr);
 // Exact vertex diameter (eccentricity-bound refinement); with omega_only it
 // stops once both ends of [vd_lo, vd_hi] give the same omega; after
 // max_bfs BFS runs it stops with the bracket it has.  witness: a vertex
