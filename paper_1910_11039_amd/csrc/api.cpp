@@ -72,6 +72,13 @@ struct kad_ctx {
     hipStream_t stream;
     bool own_stream;
     int cu_count;
+    // Streams of slot pools 1..3 (pool 0 runs on `stream`), shared by every
+    // sampler of the context and created right after `stream`: HIP deals its
+    // hardware queues (four by default) to streams in creation order, and
+    // streams created per sampler could leave two pools on one queue, where
+    // they run one after the other.  side[2] also carries the learned
+    // prior's network beside the bracket's BFS.
+    hipStream_t side[3];
 };
 
 struct kad_graph {
@@ -85,7 +92,12 @@ struct kad_graph {
     int32_t *d_newid;    // caller id -> internal id
     int32_t *d_cci;      // rows in the caller's order
     uint32_t *d_deg;
+    int32_t nruns;                      // runs of equal degree (descending)
+    int32_t *d_run_start;               // nruns + 1 entries
+    uint32_t *d_run_deg;                // nruns entries
+    std::vector<int32_t> h_run_start;
     DevGraph dev() const { return DevGraph{n, nnz, d_rp, d_ci, d_orig, d_newid, d_cci, d_deg}; }
+    DegreeRuns runs() const { return DegreeRuns{nruns, d_run_start, d_run_deg, h_run_start.data()}; }
 };
 
 struct kad_sampler {
@@ -235,6 +247,15 @@ extern "C" kad_status kad_create(int device, void *hip_stream, kad_ctx **out)
         if (e != hipSuccess) { delete c; return fail(KAD_EDEVICE, hipGetErrorString(e)); }
         c->own_stream = true;
     }
+    for (int i = 0; i < 3; ++i) {
+        hipError_t e = hipStreamCreate(&c->side[i]);
+        if (e != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipStreamDestroy(c->side[j]);
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            return fail(KAD_EDEVICE, hipGetErrorString(e));
+        }
+    }
     *out = c;
     return KAD_OK;
 }
@@ -243,6 +264,10 @@ extern "C" void kad_destroy(kad_ctx *ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
+    for (int i = 0; i < 3; ++i) {
+        (void)hipStreamSynchronize(ctx->side[i]);
+        (void)hipStreamDestroy(ctx->side[i]);
+    }
     if (ctx->own_stream) {
         (void)hipStreamSynchronize(ctx->stream);
         (void)hipStreamDestroy(ctx->stream);
@@ -291,7 +316,8 @@ extern "C" kad_status kad_graph_upload(kad_ctx *ctx, int32_t n, int64_t nnz, con
     }
     HIPCHK(hipSetDevice(ctx->device));
     // hub-first numbering: a stable counting sort by descending degree
-    std::vector<int32_t> orig(n), newid(n);
+    std::vector<int32_t> orig(n), newid(n), run_start;
+    std::vector<uint32_t> run_deg;
     std::vector<int64_t> rp2((size_t)n + 1);
     {
         int64_t maxdeg = 0;
@@ -306,6 +332,15 @@ extern "C" kad_status kad_graph_upload(kad_ctx *ctx, int32_t n, int64_t nnz, con
         }
         rp2[0] = 0;
         for (int32_t i = 0; i < n; ++i) rp2[i + 1] = rp2[i] + (h_row_ptr[orig[i] + 1] - h_row_ptr[orig[i]]);
+        // runs of equal degree: pos[j] now ends the vertices of degree maxdeg - j
+        for (size_t j = 0; j + 1 < pos.size(); ++j) {
+            const int64_t b = j == 0 ? 0 : pos[j - 1];
+            if (pos[j] > b) {
+                run_start.push_back((int32_t)b);
+                run_deg.push_back((uint32_t)(maxdeg - (int64_t)j));
+            }
+        }
+        run_start.push_back(n);
     }
     kad_graph *g = new kad_graph();
     g->ctx = ctx;
@@ -321,6 +356,8 @@ extern "C" kad_status kad_graph_upload(kad_ctx *ctx, int32_t n, int64_t nnz, con
         hipMalloc((void **)&g->d_newid, sizeof(int32_t) * (size_t)n) != hipSuccess ||
         hipMalloc((void **)&g->d_cci, ci_bytes) != hipSuccess ||
         hipMalloc((void **)&g->d_deg, sizeof(uint32_t) * (size_t)n) != hipSuccess ||
+        hipMalloc((void **)&g->d_run_start, sizeof(int32_t) * run_start.size()) != hipSuccess ||
+        hipMalloc((void **)&g->d_run_deg, sizeof(uint32_t) * run_deg.size()) != hipSuccess ||
         hipMalloc((void **)&t_rp, sizeof(int64_t) * ((size_t)n + 1)) != hipSuccess ||
         hipMalloc((void **)&t_ci, ci_bytes) != hipSuccess) {
         (void)hipFree(g->d_rp);
@@ -329,6 +366,8 @@ extern "C" kad_status kad_graph_upload(kad_ctx *ctx, int32_t n, int64_t nnz, con
         (void)hipFree(g->d_newid);
         (void)hipFree(g->d_cci);
         (void)hipFree(g->d_deg);
+        (void)hipFree(g->d_run_start);
+        (void)hipFree(g->d_run_deg);
         (void)hipFree(t_rp);
         (void)hipFree(t_ci);
         delete g;
@@ -340,6 +379,12 @@ extern "C" kad_status kad_graph_upload(kad_ctx *ctx, int32_t n, int64_t nnz, con
     HIPCHK(hipMemcpyAsync(g->d_rp, rp2.data(), sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(g->d_orig, orig.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(g->d_newid, newid.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(g->d_run_start, run_start.data(), sizeof(int32_t) * run_start.size(),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(g->d_run_deg, run_deg.data(), sizeof(uint32_t) * run_deg.size(), hipMemcpyHostToDevice,
+                          st));
+    g->nruns = (int32_t)run_deg.size();
+    g->h_run_start = std::move(run_start);
     HIPCHK(launch_relabel_rows(n, t_rp, t_ci, g->d_orig, g->d_newid, g->d_rp, g->d_cci, st));
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipFree(t_rp));
@@ -361,6 +406,8 @@ extern "C" void kad_graph_free(kad_graph *g)
     (void)hipFree(g->d_newid);
     (void)hipFree(g->d_cci);
     (void)hipFree(g->d_deg);
+    (void)hipFree(g->d_run_start);
+    (void)hipFree(g->d_run_deg);
     delete g;
 }
 
@@ -418,11 +465,9 @@ static void free_sampler(kad_sampler *s)
     if (s->have_graph) (void)hipGraphExecDestroy(s->gexec);
     for (hipEvent_t e : s->ev_ring) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->ev_merge) if (e) (void)hipEventDestroy(e);
-    for (int i = 1; i < 4; ++i) if (s->sts[i]) (void)hipStreamDestroy(s->sts[i]);
-    if (s->aux) {
-        (void)hipStreamSynchronize(s->aux);
-        (void)hipStreamDestroy(s->aux);
-    }
+    // the streams are the context's: wait for this sampler's work on them
+    for (int i = 0; i < 4; ++i) if (s->sts[i]) (void)hipStreamSynchronize(s->sts[i]);
+    if (s->aux) (void)hipStreamSynchronize(s->aux);
     if (s->ev_aux) (void)hipEventDestroy(s->ev_aux);
     if (s->ev_cal) (void)hipEventDestroy(s->ev_cal);
     if (s->cal_hist) (void)hipFree(s->cal_hist);
@@ -789,13 +834,13 @@ extern "C" kad_status kad_sampler_init(kad_ctx *ctx, const kad_graph *g, const k
     s->LU = s->LU_own;
     s->sts[0] = st;
     for (int i = 0; i < s->P; ++i) {
-        if (i > 0) HIPCHK(hipStreamCreate(&s->sts[i]));
+        if (i > 0) s->sts[i] = s->ctx->side[i - 1];
         HIPCHK(hipEventCreateWithFlags(&s->ev_merge[i], hipEventDisableTiming));
     }
     s->ev_ring.resize(std::max(s->inflight, s->P) + 1);
     for (auto &e : s->ev_ring) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&s->ev_cal, hipEventDisableTiming));
-    HIPCHK(hipStreamCreate(&s->aux));
+    s->aux = s->ctx->side[2];
     HIPCHK(hipEventCreateWithFlags(&s->ev_aux, hipEventDisableTiming));
     // records start unstamped (a key of zero is nobody's): cleared by a kernel
     HIPCHK(launch_zero_words((uint32_t *)s->recs, sizeof(Rec) / 4 * sn * nslots, st));
@@ -1031,9 +1076,8 @@ extern "C" kad_status kad_set_mlp_weights(kad_sampler *s, const float *h_params,
 static kad_status enqueue_network(kad_sampler *s, hipStream_t st)
 {
     const int32_t n = s->g->n;
-    HIPCHK(launch_features_ws(s->g->dev(), s->feat_buf, s->feat_ws, st));
-    HIPCHK(launch_normalize(n, s->feat_buf, s->mlp_dev + 4544, st));
-    HIPCHK(launch_mlp_forward(s->mlp_dev, s->feat_buf, n, s->yhat, st));
+    HIPCHK(launch_features_ws(s->g->dev(), s->g->runs(), s->feat_buf, s->feat_ws, st));
+    HIPCHK(launch_mlp_forward(s->mlp_dev, s->feat_buf, s->mlp_dev + 4544, n, s->yhat, st));
     return KAD_OK;
 }
 
@@ -1787,7 +1831,7 @@ extern "C" kad_status kad_features(kad_ctx *ctx, const kad_graph *g, float *d_ou
     float *t = nullptr, *d = d_out;
     HIPCHK(hipMallocAsync((void **)&t, bytes, st));
     if (!d) HIPCHK(hipMallocAsync((void **)&d, bytes, st));
-    HIPCHK(launch_features(g->dev(), t, st));
+    HIPCHK(launch_features(g->dev(), g->runs(), t, st));
     HIPCHK(launch_to_caller_f32x3(g->n, g->d_orig, t, d, st));
     HIPCHK(hipFreeAsync(t, st));
     if (!d_out) {
@@ -1894,7 +1938,7 @@ extern "C" kad_status kad_mlp_forward(kad_mlp *m, const float *d_x, int64_t rows
     hipStream_t st = m->ctx->stream;
     float *y = d_y;
     if (!y) HIPCHK(hipMallocAsync((void **)&y, sizeof(float) * (size_t)rows, st));
-    HIPCHK(launch_mlp_forward(m->params, d_x, rows, y, st));
+    HIPCHK(launch_mlp_forward(m->params, d_x, nullptr, rows, y, st));
     if (!d_y) {
         HIPCHK(hipMemcpyAsync(h_y, y, sizeof(float) * (size_t)rows, hipMemcpyDeviceToHost, st));
         HIPCHK(hipFreeAsync(y, st));
@@ -1958,7 +2002,7 @@ extern "C" kad_status kad_mlp_train(kad_ctx *ctx, const kad_graph *const *graphs
     int64_t off = 0;
     for (int32_t i = 0; i < ngraphs; ++i) {
         const kad_graph *g = graphs[i];
-        TRAIN_CHK(launch_features(g->dev(), feat, st));
+        TRAIN_CHK(launch_features(g->dev(), g->runs(), feat, st));
         TRAIN_CHK(launch_to_caller_f32x3(g->n, g->d_orig, feat, X + 3 * off, st));
         TRAIN_CHK(hipMemcpyAsync(bt, h_btilde[i], 8ull * g->n, hipMemcpyHostToDevice, st));
         TRAIN_CHK(launch_target(g->n, bt, h_omega[i], Y + off, st));

@@ -262,12 +262,20 @@ __global__ __launch_bounds__(AB) void k_alloc_newton(AllocArgs a, int32_t chunk,
     const int32_t beg = blockIdx.x * chunk;
     const int32_t end = min(a.n, beg + chunk);
     double sS = 0.0, sM = 0.0;
-    for (int32_t v = beg + threadIdx.x; v < end; v += AB) {
-        const double p = a.dense_prior[v];
-        if (p > 0.0) {
-            const double e = exp(-C / p);
-            sS = sS + e;
-            sM = sM + e / p;
+    // thread t sums beg + t, beg + t + AB, ... in that order, eight loads in
+    // flight at a time
+    constexpr int R = 8;
+    for (int32_t v0 = beg + threadIdx.x; v0 < end; v0 += R * AB) {
+        double p[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) p[j] = v0 + j * AB < end ? a.dense_prior[v0 + j * AB] : 0.0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (p[j] > 0.0) {
+                const double e = exp(-C / p[j]);
+                sS = sS + e;
+                sM = sM + e / p[j];
+            }
         }
     }
     __shared__ double rs[AB], rm[AB];
@@ -351,6 +359,112 @@ __global__ __launch_bounds__(AB) void k_alloc_newton(AllocArgs a, int32_t chunk,
         }
     }
     __threadfence();
+}
+
+// A bracket of the root before the first Newton step, from a histogram of
+// the priors.  Bin 0 holds the priors below 2^-64; bin 1 + 64 (e + 64) + j
+// (e = -64 .. -1, j = 0 .. 63) holds [2^e (1 + j/64), 2^e (1 + (j+1)/64)),
+// read off the exponent and the top six mantissa bits, so the edges are
+// exact; a prior of 1 goes to the last bin, whose upper edge is 1.
+// Replacing every prior by its bin's lower edge can only shrink S (each term
+// exp(-C/p) grows with p), by the upper edge only raise it; the roots of the
+// two bounding sums, found by bisection over the 4 097 bins in one
+// workgroup, therefore enclose the root of S, and lie within a factor
+// 1 + 1/64 of it.  Newton's method then starts at the lower one (S > T
+// there) with the upper one as the right end of its bracket, a few steps
+// from the root instead of about twenty from C = 0.
+constexpr int PHB = 4097;
+
+__device__ __forceinline__ int prior_bin(double p)
+{
+    const uint64_t b = bits(p);
+    const int e = (int)((b >> 52) & 0x7ff) - 1023;
+    if (e < -64) return 0;
+    if (e >= 0) return PHB - 1;
+    return 1 + (e + 64) * 64 + (int)((b >> 46) & 63);
+}
+
+__device__ __forceinline__ void prior_bin_edges(int bin, double *lo, double *up)
+{
+    if (bin == 0) {
+        *lo = 0.0;
+        *up = 0x1p-64;
+        return;
+    }
+    const int e = (bin - 1) / 64 - 64, j = (bin - 1) % 64;
+    *lo = ldexp(1.0 + j / 64.0, e);
+    *up = ldexp(1.0 + (j + 1) / 64.0, e);
+}
+
+__global__ __launch_bounds__(256) void k_prior_hist(AllocArgs a, uint32_t *ph)
+{
+    __shared__ uint32_t sh[PHB];
+    for (int i = threadIdx.x; i < PHB; i += blockDim.x) sh[i] = 0;
+    __syncthreads();
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
+        const double p = a.dense_prior[v];
+        if (p > 0.0) atomicAdd(&sh[prior_bin(p)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < PHB; i += blockDim.x)
+        if (sh[i]) atomicAdd(&ph[i], sh[i]);
+}
+
+__global__ __launch_bounds__(AB) void k_prior_bracket(AllocArgs a, const uint32_t *ph, double target)
+{
+    NewtonState *ns = reinterpret_cast<NewtonState *>(a.lo_hi);
+    __shared__ double r0[AB], r1[AB];
+    const int tid = threadIdx.x;
+    double k = 0.0;
+    for (int b = tid; b < PHB; b += AB) k += (double)ph[b];
+    r0[tid] = k;
+    __syncthreads();
+    for (int o = AB / 2; o > 0; o >>= 1) {
+        if (tid < o) r0[tid] += r0[tid + o];
+        __syncthreads();
+    }
+    const double K = r0[0];   // vertices with a positive prior (exact below 2^53)
+    __syncthreads();
+    NewtonState st{};
+    if (K <= target) {
+        st.done = 1;   // S(0) = K <= T: C = 0
+        st.C = 0.0;
+    } else {
+        // every prior is at most 1, so S and both bounds are at most
+        // K e^-C, which reaches T at ln(K/T)
+        double alo = 0.0, ahi = log(K / target), blo = 0.0, bhi = ahi;
+        for (int it = 0; it < 48; ++it) {
+            const double am = 0.5 * (alo + ahi), bm = 0.5 * (blo + bhi);
+            double sa = 0.0, sb = 0.0;
+            for (int b = tid; b < PHB; b += AB) {
+                const uint32_t c = ph[b];
+                if (!c) continue;
+                double lo, up;
+                prior_bin_edges(b, &lo, &up);
+                if (lo > 0.0) sa += (double)c * exp(-am / lo);
+                sb += (double)c * exp(-bm / up);
+            }
+            r0[tid] = sa;
+            r1[tid] = sb;
+            __syncthreads();
+            for (int o = AB / 2; o > 0; o >>= 1) {
+                if (tid < o) {
+                    r0[tid] += r0[tid + o];
+                    r1[tid] += r1[tid + o];
+                }
+                __syncthreads();
+            }
+            if (r0[0] > target) alo = am; else ahi = am;
+            if (r1[0] > target) blo = bm; else bhi = bm;
+            __syncthreads();
+        }
+        // S(alo) >= lower sum at alo > T, and S(bhi) <= upper sum at bhi <= T
+        st.C = alo;
+        st.lo = alo;
+        st.hi = bhi;
+        st.steps = 1;   // the count at C = 0 is done
+    }
+    if (tid == 0) *ns = st;
 }
 
 // Calibration priors are counts over tau0, so the sum over vertices is a
@@ -1008,16 +1122,19 @@ hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host)
         *C_host = C;
         return hipSuccess;
     }
-    // dense prior: Newton's method on ln S (k_alloc_newton), a launch per
-    // step, the state read back after 12 steps and then every 8
-    NewtonState init{};
-    CK(hipMemcpyAsync(a.lo_hi, &init, sizeof(init), hipMemcpyHostToDevice, st));
+    // dense prior: the histogram bracket, then Newton's method on ln S
+    // (k_alloc_newton), a launch per step, the state read back after 5
+    // steps and then every 3
     const int32_t chunk = 8192;
     const int32_t nb = (a.n + chunk - 1) / chunk;
+    uint32_t *ph = reinterpret_cast<uint32_t *>(a.partials + 2 * (size_t)nb + 2);
+    CK(launch_zero_words(ph, PHB, st));
+    hipLaunchKernelGGL(k_prior_hist, dim3(grid_for(a.n, 256, 2048)), dim3(256), 0, st, a, ph);
+    hipLaunchKernelGGL(k_prior_bracket, dim3(1), dim3(AB), 0, st, a, (const uint32_t *)ph, target);
     NewtonState fin{};
     for (int it = 0; it < 400 && !fin.done; ++it) {
         hipLaunchKernelGGL(k_alloc_newton, dim3(nb), dim3(AB), 0, st, a, chunk, target);
-        if (it == 11 || (it > 11 && (it - 11) % 8 == 0)) {
+        if (it == 4 || (it > 4 && (it - 4) % 3 == 0)) {
             CK(hipMemcpyAsync(&fin, a.lo_hi, sizeof(fin), hipMemcpyDeviceToHost, st));
             if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
         }
@@ -1030,7 +1147,8 @@ hipError_t run_alloc(const AllocArgs &a, hipStream_t st, double *C_host)
     return hipSuccess;
 }
 
-size_t alloc_partials(int32_t n) { return 2 * (size_t)((n + 8191) / 8192) + 2; }   // S and M per workgroup
+// S and M per workgroup, then the prior histogram (PHB 4-byte bins)
+size_t alloc_partials(int32_t n) { return 2 * (size_t)((n + 8191) / 8192) + 2 + (PHB + 1) / 2; }
 
 hipError_t run_alloc_L(const AllocArgs &a, double C, hipStream_t st)
 {

@@ -209,11 +209,24 @@ hipError_t device_exact_vd(const DevGraph &g, hipStream_t st, bool omega_only, d
                            int64_t max_bfs, int64_t *vd_lo, int64_t *vd_hi, int32_t *witness, int64_t *bfs_runs);
 
 // Learned prior.
-hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st);
+// Runs of equal degree in the internal numbering: vertices are numbered by
+// descending degree, so run k holds the vertices start[k] .. start[k+1]-1,
+// all of degree deg[k], and deg[] descends.  A graph has at most a few
+// thousand distinct degrees, so the feature pass finds a neighbour's degree
+// by a search in a table held in LDS instead of a gather.
+struct DegreeRuns {
+    int32_t count;            // number of runs (distinct degrees)
+    const int32_t *start;     // device, count + 1 entries, start[count] = n
+    const uint32_t *deg;      // device, count entries
+    const int32_t *h_start;   // host copy of start
+};
+hipError_t launch_features(const DevGraph &g, const DegreeRuns &runs, float *out, hipStream_t st);
 size_t features_workspace_bytes(const DevGraph &g);
-hipError_t launch_features_ws(const DevGraph &g, float *out, void *ws, hipStream_t st);
+hipError_t launch_features_ws(const DevGraph &g, const DegreeRuns &runs, float *out, void *ws, hipStream_t st);
 hipError_t launch_normalize(int32_t n, float *x, const float *norm, hipStream_t st);
-hipError_t launch_mlp_forward(const float *params, const float *x, int64_t rows, float *y,
+// y = MLP(x) over rows of 3 features; with norm (mean[3], std[3]) the
+// features are standardised on load.
+hipError_t launch_mlp_forward(const float *params, const float *x, const float *norm, int64_t rows, float *y,
                               hipStream_t st);
 hipError_t launch_mlp_loss_grad(const float *params, const float *x, const float *y, int64_t rows,
                                 float *grad, float *loss, float *scratch, hipStream_t st);

@@ -44,6 +44,84 @@ __device__ __forceinline__ double2 logdeg(const DevGraph &g, const double *lt, i
     return make_double2(d < (uint32_t)g.n ? lt[d] : log1p((double)d), (double)d);
 }
 
+// The degree-run table in LDS.  Vertices are numbered by descending degree,
+// so a vertex's degree is a step function of its id with one step per
+// distinct degree (3 139 steps on R-MAT 26 against 32.8 M vertices).  The
+// feature kernels hold the last `cnt` runs (the smallest degrees) in LDS:
+// key[] the first vertex of each run (padded with INT32_MAX to a power of
+// two, `half` is half of that), lg[] = ln(1 + d) and dg[] = d.  A neighbour
+// u at or above key[0] is resolved by a binary search, which needs no global
+// load; a neighbour below key[0] (a hub, only when the graph has more
+// distinct degrees than the table holds) is gathered as above.  On R-MAT 26
+// 28 % of the adjacency entries point at the 31.8 M vertices of degree
+// under 256, scattered over a 131 MB degree array that misses L2; the
+// search turns those into LDS reads.
+constexpr int RUNCAP = 4096;      // runs held in LDS (16 B each)
+
+struct RunArgs {
+    const int32_t *start;   // run starts (global)
+    const uint32_t *deg;    // run degrees (global)
+    int32_t first;          // first run held in LDS
+    int32_t cnt;            // runs held
+    int32_t pow2;           // cnt rounded up to a power of two
+};
+
+struct RunLds {
+    const double *lg;
+    const int32_t *key;
+    const uint32_t *dg;
+    int32_t half;
+};
+
+size_t run_lds_bytes(int32_t cnt, int32_t pow2) { return 8 * (size_t)cnt + 4 * (size_t)pow2 + 4 * (size_t)cnt; }
+
+// Fills the block's LDS table (every thread of the block must call this
+// before any lookup; it ends with a barrier).  lt must hold ln(1 + d) for
+// the degrees below n.
+__device__ RunLds load_runs(const DevGraph &g, const double *lt, const RunArgs &r)
+{
+    extern __shared__ double s_runs[];
+    double *lg = s_runs;
+    int32_t *key = (int32_t *)(lg + r.cnt);
+    uint32_t *dg = (uint32_t *)(key + r.pow2);
+    for (int i = threadIdx.x; i < r.pow2; i += blockDim.x) {
+        key[i] = i < r.cnt ? r.start[r.first + i] : INT32_MAX;
+        if (i < r.cnt) {
+            const uint32_t d = r.deg[r.first + i];
+            dg[i] = d;
+            lg[i] = d < (uint32_t)g.n ? lt[d] : log1p((double)d);
+        }
+    }
+    __syncthreads();
+    return RunLds{lg, key, dg, r.pow2 >> 1};
+}
+
+// (ln(1 + deg u), deg u) of B neighbours (u < 0: an empty position, 0).
+// The B searches are interleaved step by step so that their LDS reads
+// overlap.
+template <int B>
+__device__ __forceinline__ void run_lookup(const DevGraph &g, const double *lt, const RunLds &L,
+                                           const int32_t (&u)[B], double2 (&p)[B])
+{
+    int k[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) k[j] = 0;
+    for (int h = L.half; h > 0; h >>= 1) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int c = k[j] + h;
+            if (L.key[c] <= u[j]) k[j] = c;
+        }
+    }
+    const int32_t lo = L.key[0];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+        if (u[j] < 0) p[j] = make_double2(0.0, 0.0);
+        else if (u[j] < lo) p[j] = logdeg(g, lt, u[j]);
+        else p[j] = make_double2(L.lg[k[j]], (double)L.dg[k[j]]);
+    }
+}
+
 // lt[d] = ln(1 + d) for d = 0 .. min(deg[0], n - 1) (vertex 0 has the
 // largest degree in the internal numbering).
 __global__ void k_logtab(DevGraph g, double *lt)
@@ -69,8 +147,10 @@ constexpr int64_t FSHORT = 32;     // rows up to this long: a thread per vertex
 // entries eight at a time.
 // (Vertices are numbered by descending degree: the short rows are those of
 // vertices bnd[1] .. n-1.)
-__global__ void k_features_short(DevGraph g, const int32_t *bnd, const double *lt, float *out)
+__global__ __launch_bounds__(512) void k_features_short(DevGraph g, const int32_t *bnd, const double *lt,
+                                                        RunArgs ra, float *out)
 {
+    const RunLds L = load_runs(g, lt, ra);
     const int64_t first = bnd[1];
     for (int64_t v = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
          v += (int64_t)gridDim.x * blockDim.x) {
@@ -82,8 +162,7 @@ __global__ void k_features_short(DevGraph g, const int32_t *bnd, const double *l
 #pragma unroll
             for (int j = 0; j < B; ++j) u[j] = (e0 + j < end) ? g.ci[e0 + j] : -1;
             double2 p[B];
-#pragma unroll
-            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? logdeg(g, lt, u[j]) : make_double2(0.0, 0.0);
+            run_lookup<B>(g, lt, L, u, p);
 #pragma unroll
             for (int j = 0; j < B; ++j) {
                 if (u[j] < 0) continue;
@@ -105,8 +184,10 @@ constexpr int64_t FMID = 256;      // rows up to this long: eight lanes per vert
 // to issue (a wave per vertex left seven of eight batches empty on rows
 // of a few dozen entries).
 template <int G>
-__global__ void k_features_group(DevGraph g, const int32_t *bnd, const double *lt, float *out)
+__global__ __launch_bounds__(512) void k_features_group(DevGraph g, const int32_t *bnd, const double *lt,
+                                                        RunArgs ra, float *out)
 {
+    const RunLds L = load_runs(g, lt, ra);
     const int sub = threadIdx.x & (G - 1);
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int64_t grps = ((int64_t)gridDim.x * blockDim.x) / G;
@@ -125,8 +206,7 @@ __global__ void k_features_group(DevGraph g, const int32_t *bnd, const double *l
 #pragma unroll
             for (int j = 0; j < B; ++j) u[j] = (e0 + G * j < end) ? g.ci[e0 + G * j] : -1;
             double2 p[B];
-#pragma unroll
-            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? logdeg(g, lt, u[j]) : make_double2(0.0, 0.0);
+            run_lookup<B>(g, lt, L, u, p);
 #pragma unroll
             for (int j = 0; j < B; ++j) {
                 if (u[j] < 0) continue;
@@ -195,9 +275,10 @@ __global__ __launch_bounds__(1024) void k_feat_pieces(DevGraph g, int64_t *pref,
     if (tid == 0) pref[0] = 0;
 }
 
-__global__ void k_feat_sum(DevGraph g, const int64_t *pref, const int32_t *H_in, const double *lt,
-                           double2 *part)
+__global__ __launch_bounds__(512) void k_feat_sum(DevGraph g, const int64_t *pref, const int32_t *H_in,
+                                                  const double *lt, RunArgs ra, double2 *part)
 {
+    const RunLds L = load_runs(g, lt, ra);
     const int lane = threadIdx.x & 63;
     const int32_t H = *H_in;
     if (H == 0) return;
@@ -219,8 +300,7 @@ __global__ void k_feat_sum(DevGraph g, const int64_t *pref, const int32_t *H_in,
 #pragma unroll
             for (int j = 0; j < B; ++j) u[j] = (e0 + 64 * j < e) ? g.ci[e0 + 64 * j] : -1;
             double2 p[B];
-#pragma unroll
-            for (int j = 0; j < B; ++j) p[j] = u[j] >= 0 ? logdeg(g, lt, u[j]) : make_double2(0.0, 0.0);
+            run_lookup<B>(g, lt, L, u, p);
 #pragma unroll
             for (int j = 0; j < B; ++j) {
                 if (u[j] < 0) continue;
@@ -421,6 +501,81 @@ __global__ __launch_bounds__(256) void k_mlp(const float *P, const float *X, con
     }
 }
 
+// Forward pass alone (the learned prior's inference over every vertex).
+// Each wave takes 16-row strips on its own, with no LDS and no barrier, and
+// works on transposed activations so that one layer's MFMA output is laid
+// out as the next layer's B operand.  With v_mfma_f32_16x16x4f32, lane
+// l = 16 g + r (g = 0..3, r = 0..15) supplies A[r][g] and B[g][r] and gets
+// C[4 g + i][r], i = 0..3.
+//  * layer 1: Z1^T (16 hidden x 16 rows, four tiles) = W1' X'^T, where W1'
+//    is W1 with the bias as a fourth column and X' the rows with a fourth
+//    input fixed at 1, so lane (g, r) gives input g of row r (the bias's 1
+//    for g = 3) and weight W1'[16 t + r][g];
+//  * layer 2: Z2^T = W2 H1^T summed over the 64 hidden inputs k in the
+//    order k = 16 t + 4 g + i of step q = 4 t + i: at that step lane (g, r)
+//    holds exactly H1^T[16 t + 4 g + i][r] (its layer-1 output), and gives
+//    W2[16 u + r][16 t + 4 g + i] as A for output tile u;
+//  * layer 3: each lane's 16 outputs times W3, then a sum over the four
+//    lanes of a row (shuffles by 16 and 32).
+// With norm (the training mean and standard deviation of each feature) the
+// inputs are standardised on load.
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float *P, const float *X, const float *norm, int64_t rows,
+                                                 float *Y)
+{
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    float a1[4], a2[4][16], b2[4][4], w3[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a1[t] = g < 3 ? P[OFF_W1 + (16 * t + r) * 3 + g] : P[OFF_B1 + 16 * t + r];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a2[u][q] = P[OFF_W2 + (16 * u + r) * 64 + 16 * (q >> 2) + 4 * g + (q & 3)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            b2[u][i] = P[OFF_B2 + 16 * u + 4 * g + i];
+            w3[u][i] = P[OFF_W3 + 16 * u + 4 * g + i];
+        }
+    }
+    const float b3 = P[OFF_B3];
+    const float mu = (norm && g < 3) ? norm[g] : 0.f, sd = (norm && g < 3) ? norm[3 + g] : 1.f;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t s0 = wave * 16; s0 < rows; s0 += waves * 16) {
+        const int64_t row = s0 + r;
+        float x = 1.f;
+        if (g < 3) {
+            x = row < rows ? X[row * 3 + g] : 0.f;
+            if (norm) x = (x - mu) / sd;
+        }
+        floatx4 h1[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            h1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[t], x, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h1[t][i] = h1[t][i] > 0.f ? h1[t][i] : 0.f;
+        }
+        floatx4 z2[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) z2[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                z2[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[u][q], h1[q >> 2][q & 3], z2[u], 0, 0, 0);
+        float y = 0.f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float z = z2[u][i] + b2[u][i];
+                y = fmaf(w3[u][i], z > 0.f ? z : 0.f, y);
+            }
+        y += __shfl_xor(y, 16);
+        y += __shfl_xor(y, 32);
+        if (g == 0 && row < rows) Y[row] = y + b3;
+    }
+}
+
 __global__ void k_reduce_partials(const float *partial, int nb, float *grad, float *loss, float inv_rows)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -587,8 +742,17 @@ size_t features_workspace_bytes(const DevGraph &g)
            up(sizeof(double) * (size_t)g.n);
 }
 
-hipError_t launch_features_ws(const DevGraph &g, float *out, void *ws, hipStream_t st)
+hipError_t launch_features_ws(const DevGraph &g, const DegreeRuns &runs, float *out, void *ws, hipStream_t st)
 {
+    if (runs.count < 1) return hipErrorInvalidValue;
+    RunArgs ra;
+    ra.start = runs.start;
+    ra.deg = runs.deg;
+    ra.first = std::max(0, runs.count - RUNCAP);
+    ra.cnt = runs.count - ra.first;
+    ra.pow2 = 1;
+    while (ra.pow2 < ra.cnt) ra.pow2 <<= 1;
+    const size_t lds = run_lds_bytes(ra.cnt, ra.pow2);
     const int64_t hmax = g.nnz / FPIECE + 1, pmax = 2 * (g.nnz / FPIECE) + 1;
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     int64_t *pref = (int64_t *)ws;
@@ -598,24 +762,22 @@ hipError_t launch_features_ws(const DevGraph &g, float *out, void *ws, hipStream
     const int64_t tblocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + 255) / 256, 2048));
     hipLaunchKernelGGL(k_logtab, dim3((unsigned)tblocks), dim3(256), 0, st, g, lt);
     hipLaunchKernelGGL(k_feat_pieces, dim3(1), dim3(1024), 0, st, g, pref, H);
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_features_short, dim3((unsigned)blocks), dim3(256), 0, st, g, H, lt, out);
-    const int64_t waves = std::max<int64_t>(1, std::min<int64_t>(g.n, 1 << 16));
-    hipLaunchKernelGGL(k_features_group<8>, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, H,
-                       lt, out);
-    hipLaunchKernelGGL(k_features_group<64>, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, st, g, H,
-                       lt, out);
-    hipLaunchKernelGGL(k_feat_sum, dim3(2048), dim3(256), 0, st, g, pref, H, lt, part);
+    // each workgroup fills its LDS table once, then strides over its tier
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)g.n + 511) / 512, 2048));
+    hipLaunchKernelGGL(k_features_short, dim3((unsigned)blocks), dim3(512), lds, st, g, H, lt, ra, out);
+    hipLaunchKernelGGL(k_features_group<8>, dim3((unsigned)blocks), dim3(512), lds, st, g, H, lt, ra, out);
+    hipLaunchKernelGGL(k_features_group<64>, dim3((unsigned)blocks), dim3(512), lds, st, g, H, lt, ra, out);
+    hipLaunchKernelGGL(k_feat_sum, dim3(1024), dim3(512), lds, st, g, pref, H, lt, ra, part);
     hipLaunchKernelGGL(k_feat_combine, dim3(64), dim3(256), 0, st, g, pref, H, part, out);
     return hipGetLastError();
 }
 
-hipError_t launch_features(const DevGraph &g, float *out, hipStream_t st)
+hipError_t launch_features(const DevGraph &g, const DegreeRuns &runs, float *out, hipStream_t st)
 {
     void *ws = nullptr;
     hipError_t e = hipMallocAsync(&ws, features_workspace_bytes(g), st);
     if (e != hipSuccess) return e;
-    e = launch_features_ws(g, out, ws, st);
+    e = launch_features_ws(g, runs, out, ws, st);
     const hipError_t f = hipFreeAsync(ws, st);
     return e != hipSuccess ? e : f;
 }
@@ -627,10 +789,12 @@ hipError_t launch_normalize(int32_t n, float *x, const float *norm, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_forward(const float *params, const float *x, int64_t rows, float *y, hipStream_t st)
+hipError_t launch_mlp_forward(const float *params, const float *x, const float *norm, int64_t rows, float *y,
+                              hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mlp, dim3(blocks_for_rows(rows)), dim3(256), 0, st, params, x, (const float *)nullptr,
-                       rows, y, (float *)nullptr, 0);
+    const int64_t strips = (rows + 15) / 16;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((strips + 3) / 4, 2048));
+    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)blocks), dim3(256), 0, st, params, x, norm, rows, y);
     return hipGetLastError();
 }
 

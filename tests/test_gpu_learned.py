@@ -73,6 +73,36 @@ def test_features_of_long_rows_match_oracle(ctx, oracle):
     assert np.allclose(x, xo, rtol=1e-6, atol=1e-7)
 
 
+def threshold_graph(n):
+    """i ~ j (i != j) iff i + j >= n - 1: degrees 1 .. n - 1, nearly all
+    distinct."""
+    i, j = np.triu_indices(n, 1)
+    keep = i + j >= n - 1
+    return gg.from_edges(n, i[keep].astype(np.int64), j[keep].astype(np.int64))
+
+
+@pytest.mark.parametrize("case", ["threshold4600", "threshold300", "cycle_and_isolated", "rmat20"])
+def test_features_by_degree_runs_match_oracle(ctx, oracle, case):
+    """The feature pass reads a neighbour's degree from the table of runs of
+    equal degree in LDS.  threshold4600 has more distinct degrees (4 599)
+    than the table holds (4 096): its hubs are gathered from the degree
+    array, the rest searched.  A cycle with isolated vertices has two runs
+    (degrees 2 and 0); R-MAT 20 at full size has every tier."""
+    if case == "threshold4600":
+        g = threshold_graph(4600)
+    elif case == "threshold300":
+        g = threshold_graph(300)
+    elif case == "cycle_and_isolated":
+        u = np.arange(100, dtype=np.int64)
+        g = gg.from_edges(120, u, (u + 1) % 100)
+    else:
+        g = gg.workload("rmat20")
+    G = K.Graph(ctx, g)
+    x = K.kad_features(ctx.h, G.h, g.n)
+    xo = oracle.features(g)
+    assert np.allclose(x, xo, rtol=1e-6, atol=1e-7)
+
+
 @pytest.mark.parametrize("rows", [1, 63, 64, 1000, 70000])
 def test_mlp_forward_matches_oracle(ctx, oracle, rows):
     p = L.init_params(3)
