@@ -319,6 +319,8 @@ def main():
     ap.add_argument("--exact-diameter", type=int, default=0, help="omega from the exact vertex diameter")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain device copy of known size (counter calibration) and exit")
+    ap.add_argument("--feature-pass", action="store_true",
+                    help="only the learned prior's feature pass, three times on an idle GPU (profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -349,6 +351,15 @@ def main():
     log("graph resident in HBM")
     if args.epoch_size == 0:
         args.epoch_size = FIXED_EPOCH.get(args.workload, 0)
+
+    if args.feature_pass:
+        ms = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            K.kad_features(ctx.h, G.h, gn)
+            ms.append(round((time.perf_counter() - t1) * 1e3, 2))
+        print(json.dumps({"feature_pass_ms_host_incl_copy_out": ms}), flush=True)
+        return
 
     if args.profile_leg:
         roof = roofline_leg(K, G, eps, wname, steps=args.steps, block=args.block, epoch=args.epoch_size,

@@ -229,6 +229,28 @@ def test_learned_prior_above_one_is_clamped(ctx, oracle):
     assert np.allclose(LLg, LLo, rtol=1e-4, atol=0)
 
 
+def test_learned_prior_all_zero_gives_the_floor(ctx, oracle):
+    """A network that predicts nothing (y = -50, prior max(0, e^y - 1/omega)
+    = 0 everywhere): no prior is positive, the bracket's count K = 0 is
+    already within the budget, C = 0 and every delta sits at the floor
+    beta delta / (4n), as in the oracle's allocation."""
+    g = gg.rmat(11, 16, 4)
+    G = K.Graph(ctx, g)
+    params = L.init_params(3)
+    params[4480] = -50.0
+    params[4416:4480] = 0.0
+    unit = np.array([0, 0, 0, 1, 1, 1], dtype=np.float32)
+    S = K.Sampler(G, seed=1, epsilon=0.05, delta=0.1, alloc_mode=K.KAD_ALLOC_LEARNED)
+    S.set_mlp_weights(params, unit)
+    r = S.run_to_stop()
+    assert r.tau0 == 0
+    LLg, LUg = S.delta_logs()
+    LLo, _ = _oracle_learned_delta(oracle, g, params, unit, r.omega)
+    assert np.allclose(LLg, LLo, rtol=1e-12, atol=0)
+    assert np.allclose(LLg, -np.log(1e-3 * 0.1 / (4 * g.n)), rtol=1e-12)
+    assert r.stop_reason in (K.KAD_STOP_COND, K.KAD_STOP_OMEGA)
+
+
 def test_learned_allocation_falls_back_to_plain(ctx, oracle):
     g = gg.rmat(10, 8, 2)
     G = K.Graph(ctx, g)
