@@ -30,8 +30,12 @@
  *   - Graphs: undirected, unweighted (Sec. III), CSR with row_ptr int64[n+1]
  *     and col_idx int32[nnz]; each row sorted ascending, no self loops, no
  *     duplicate edges, symmetric, connected.  Vertex ids are 0..n-1.
- *   - All work runs on the HIP stream given to kad_create (or the default
- *     stream), with kernels built for gfx950 only.
+ *   - Work runs on the context's stream (the HIP stream given to
+ *     kad_create, or one the context creates) and, for samplers, on three
+ *     more streams that the context creates and owns: slot pools 1..3, the
+ *     third also carrying the learned prior's network, which
+ *     kad_sampler_reset leaves running and kad_run_to_stop waits for.
+ *     Kernels are built for gfx950 only.
  */
 #ifndef KADABRA_H
 #define KADABRA_H
@@ -81,8 +85,12 @@ enum { KAD_VISITED_AUTO = 0, KAD_VISITED_DENSE = 1, KAD_VISITED_HASHED = 2 };
 enum { KAD_GRAPH_VALIDATE = 1u };
 
 /* kad_create: bind a context to HIP device `device` and stream
- * `hip_stream` (a hipStream_t; NULL = the device's default stream; a
- * torch.cuda stream handle works).  The stream is borrowed, not owned. */
+ * `hip_stream` (a hipStream_t, borrowed, not owned; a torch.cuda stream
+ * handle works; NULL: the context creates a stream of its own).  The
+ * context also creates the three streams of the samplers' slot pools 1..3
+ * right after its own, so that HIP, which deals its hardware queues (four
+ * by default) to streams in creation order, gives every pool a queue;
+ * samplers of one context share them.  kad_destroy releases them. */
 kad_status kad_create(int device, void *hip_stream, kad_ctx **out);
 void kad_destroy(kad_ctx *ctx);
 const char *kad_last_error(void);
