@@ -154,6 +154,7 @@ struct Smem {
     int32_t me_w[MEDGE];         // and the meet vertex
     uint32_t filt[Filter<BS>::WORDS];
     int32_t tail, mcount, ovf, err, w, wmin, mpath, nme, fold_bad, pathc, vsfull, quit;
+    const int32_t *stopp;   // the run's stop flag (null: none); kept here, not in registers
     uint32_t stamp;
     int32_t s, t;
 };
@@ -389,6 +390,7 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
         sm.fold_bad = 0;
     }
     for (int32_t base = lo; base < hi; base += BS) {
+        if (SP && sm.quit) break;   // set in a previous chunk's scan (read after its barrier)
         const int cnt = min(BS, hi - base);
         int32_t u = -1;
         int64_t rs = 0, d = 0, riu = -1;
@@ -431,6 +433,17 @@ __device__ void expand_int(Smem<BS> &sm, const Ctx &c, int X, int32_t k, int32_t
         uint32_t act;
         fetch((int64_t)(tid >> 6) * 64 * U, a, w, act);
         for (int64_t e0 = (int64_t)(tid >> 6) * 64 * U; e0 < total; e0 += (int64_t)BS * U) {
+            // A scan of a hub's row can last milliseconds: every 16 rounds
+            // (16 BS U entries a workgroup) a wave looks at the stop flag,
+            // and once the run has stopped the sample is abandoned (its
+            // epoch is past the stop and never merged).
+            if (SP && ((e0 / ((int64_t)BS * U)) & 15) == 15) {
+                const int32_t *sp = sm.stopp;
+                if (sp && __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    sm.quit = 1;
+                    break;
+                }
+            }
             int an[U];
             int32_t wn[U];
             uint32_t actn = 0;
@@ -1449,6 +1462,7 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                 sm.fmax_bits = 0;
                 sm.vsfull = 0;
                 sm.quit = 0;
+                sm.stopp = a.stop_flag;
             }
             __syncthreads();
             c.fp = fp;
@@ -1470,6 +1484,10 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                 if (!fp) expand_int<BS, SP>(sm, c, X, k, lo, hi, ls, probe);
                 else expand_fp<BS, SP>(sm, c, X, k, lo, hi, ls);
                 __syncthreads();
+                if (SP && sm.quit) {   // cut short by the stop: its meets and σ are partial
+                    quit = true;
+                    break;
+                }
                 if (probe && !sm.ovf && sm.mcount == 0) {
                     __syncthreads();
                     const unsigned long long pred_before = ls.pred;   // the rescan meets the
@@ -1489,7 +1507,7 @@ __global__ __launch_bounds__(BS, (BS == 256 ? 3 : (BS == 512 ? 4 : 1))) void k_s
                 }
                 if (!fp && sm.ovf) break;
                 if (sm.mcount > 0) break;
-                if (sm.tail == hi) { failed = true; break; }
+                if (sm.tail == hi && !(SP && sm.quit)) { failed = true; break; }
                 __syncthreads();
                 if (tid == 0) {
                     sm.plo[X] = lo;
