@@ -25,6 +25,7 @@ def big():
     print(f"n={g.n} nnz={g.nnz}", flush=True)
     ctx = K.Context(0)
     G = K.Graph(ctx, g)
+    print("graph uploaded", flush=True)
     yield K, ctx, G, g
     ctx.close()
 
@@ -37,6 +38,7 @@ def test_rmat26_sampled_paths_at_full_size(big, oracle):
                   alloc_mode=K.KAD_ALLOC_EXPLICIT, epoch_size=2048)
     S.set_delta(d, d)
     O = oracle.Sampler(g, seed=1, stream=0)
+    print("oracle sampler ready", flush=True)
     for first in (0, 123_456_789):
         paths, info = S.sample_paths(0, first, 16, 64)
         for i in range(16):
@@ -44,7 +46,7 @@ def test_rmat26_sampled_paths_at_full_size(big, oracle):
             assert np.array_equal(paths[i, : inf.d + 1], p), (first + i, paths[i], p)
             want = [inf.s, inf.t, inf.d, inf.w, inf.fp_mode, inf.meet_size, inf.steps, inf.edges]
             assert list(info[i, :8]) == want, (first + i, list(info[i, :8]), want)
-        print(f"samples {first}..{first + 15} equal", flush=True)
+            print(f"sample {first + i} equal", flush=True)
     S.close()
 
 
@@ -62,6 +64,7 @@ def test_rmat26_first_epochs_match_oracle(big, oracle):
           f"stopped={stops}", flush=True)
     threads = oracle.host_threads()
     og = oracle.Graph(g)
+    print("oracle graph ready", flush=True)
     omega = oracle.omega_bracket(*oracle.vd_bracket(og), 0.01, 0.1)
     assert r.omega == omega
     print(f"oracle bracket done, omega={omega}", flush=True)
