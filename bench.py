@@ -141,11 +141,13 @@ def learned_vs_plain(K, G, eps, steps, warmup, args):
                  pools=getattr(args, "pools", 0), visited_mode=getattr(args, "visited", 0),
                  visited_log2=getattr(args, "visited_log2", 0))
     S, (pres, pwalls) = run_arm(K, G, eps, steps, warmup, **shape)
+    bt_plain = S.btilde()   # the last timed run's estimates
     S.close()   # frees the plain arm's visited state before the learned arm sizes its own
     params, norm = LRN.load()
     SL = K.Sampler(G, seed=1, epsilon=eps, delta=0.1, alloc_mode=K.KAD_ALLOC_LEARNED, **shape)
     SL.set_mlp_weights(params, norm)
     lres, lwalls = arm_steps(SL, steps, warmup)
+    bt_learned = SL.btilde()
     SL.close()
     plain, learned = summarize(pres, pwalls), summarize(lres, lwalls)
     learned["fell_back_to_plain"] = int(sum(r["tau0"] > 0 for r in lres))
@@ -154,8 +156,25 @@ def learned_vs_plain(K, G, eps, steps, warmup, args):
            "sample_ratio_learned_over_plain": round(learned["samples_per_run"] / plain["samples_per_run"], 4),
            "certified_max_f_g_at_stop": {
                "plain": float(max(max(r["max_f"], r["max_g"]) for r in pres)),
-               "learned": float(max(max(r["max_f"], r["max_g"]) for r in lres))}}
+               "learned": float(max(max(r["max_f"], r["max_g"]) for r in lres))},
+           "max_abs_err_vs_reference": reference_error(K, G, eps, bt_plain, bt_learned)}
     return out, pres, pwalls
+
+
+def reference_error(K, G, eps, bt_plain, bt_learned, ref_eps=0.002):
+    """Each arm's largest |b~(v) - b~_ref(v)| against one plain run at a
+    five times tighter epsilon on the same graph (another seed; not timed):
+    where exact betweenness is out of reach, the arms' errors are at most
+    this plus ref_eps, with probability 1 - delta each."""
+    if eps <= ref_eps:
+        return None
+    R = K.Sampler(G, seed=7, epsilon=ref_eps, delta=0.1)
+    R.reset(7)
+    r = R.run_to_stop().as_dict()
+    ref = R.btilde()
+    R.close()
+    return {"reference_eps": ref_eps, "reference_samples": int(r["tau0"] + r["tau"]),
+            "plain": float(np.max(np.abs(bt_plain - ref))), "learned": float(np.max(np.abs(bt_learned - ref)))}
 
 
 def roofline_leg(K, G, eps, workload, steps=3, block=0, epoch=0, visited=0, visited_log2=0):
