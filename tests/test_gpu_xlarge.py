@@ -17,20 +17,28 @@ import graphgen as gg
 pytestmark = pytest.mark.gpu
 
 
+def say(request, msg):
+    """A progress line that reaches the log even while pytest captures the
+    tests' output: these tests take minutes (graph build, oracle passes)."""
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+    with capman.global_and_fixture_disabled():
+        print(msg, flush=True)
+
+
 @pytest.fixture(scope="module")
-def big():
+def big(request):
     from paper_1910_11039_amd import kadabra as K
-    print("building R-MAT 26", flush=True)
+    say(request, "building R-MAT 26")
     g = gg.workload("rmat26")
-    print(f"n={g.n} nnz={g.nnz}", flush=True)
+    say(request, f"n={g.n} nnz={g.nnz}")
     ctx = K.Context(0)
     G = K.Graph(ctx, g)
-    print("graph uploaded", flush=True)
+    say(request, "graph uploaded")
     yield K, ctx, G, g
     ctx.close()
 
 
-def test_rmat26_sampled_paths_at_full_size(big, oracle):
+def test_rmat26_sampled_paths_at_full_size(big, oracle, request):
     K, ctx, G, g = big
     L, _ = oracle.uniform_delta(g.n, 0.1)
     d = np.exp(-L)
@@ -38,7 +46,7 @@ def test_rmat26_sampled_paths_at_full_size(big, oracle):
                   alloc_mode=K.KAD_ALLOC_EXPLICIT, epoch_size=2048)
     S.set_delta(d, d)
     O = oracle.Sampler(g, seed=1, stream=0)
-    print("oracle sampler ready", flush=True)
+    say(request, "oracle sampler ready")
     for first in (0, 123_456_789):
         paths, info = S.sample_paths(0, first, 16, 64)
         for i in range(16):
@@ -46,11 +54,11 @@ def test_rmat26_sampled_paths_at_full_size(big, oracle):
             assert np.array_equal(paths[i, : inf.d + 1], p), (first + i, paths[i], p)
             want = [inf.s, inf.t, inf.d, inf.w, inf.fp_mode, inf.meet_size, inf.steps, inf.edges]
             assert list(info[i, :8]) == want, (first + i, list(info[i, :8]), want)
-            print(f"sample {first + i} equal", flush=True)
+            say(request, f"sample {first + i} equal")
     S.close()
 
 
-def test_rmat26_first_epochs_match_oracle(big, oracle):
+def test_rmat26_first_epochs_match_oracle(big, oracle, request):
     """The plain arm in the benchmark's launch shape (autotuned epoch size
     and workgroups, every slot pool, timing on): omega, the calibration and
     the allocation, then the first four epochs' counters, tau and per-epoch
@@ -60,14 +68,14 @@ def test_rmat26_first_epochs_match_oracle(big, oracle):
     stops = [S.step_epoch() for _ in range(4)]
     r = S.result()
     c, tau = S.counts()
-    print(f"device: E={r.epoch_size} block={r.block_size} slots={r.slots} pools={r.pools} tau={tau} "
-          f"stopped={stops}", flush=True)
+    say(request, f"device: E={r.epoch_size} block={r.block_size} slots={r.slots} pools={r.pools} tau={tau} "
+                f"stopped={stops}")
     threads = oracle.host_threads()
     og = oracle.Graph(g)
-    print("oracle graph ready", flush=True)
+    say(request, "oracle graph ready")
     omega = oracle.omega_bracket(*oracle.vd_bracket(og), 0.01, 0.1)
     assert r.omega == omega
-    print(f"oracle bracket done, omega={omega}", flush=True)
+    say(request, f"oracle bracket done, omega={omega}")
     cal = oracle.calibrate(og, seed=1, omega_=omega, threads=threads)
     cp, tau0, Cc = S.calibration()
     assert tau0 == cal["tau0"]
@@ -76,7 +84,7 @@ def test_rmat26_first_epochs_match_oracle(big, oracle):
     dLL, dLU = S.delta_logs()
     assert np.allclose(dLL, cal["LL"], rtol=1e-12, atol=0)
     assert np.allclose(dLU, cal["LU"], rtol=1e-12, atol=0)
-    print(f"calibration equal (tau0={tau0}); oracle epochs on {threads} threads", flush=True)
+    say(request, f"calibration equal (tau0={tau0}); oracle epochs on {threads} threads")
     co = None
     maxf, maxg = [], []
     for k in range(4):
@@ -85,7 +93,7 @@ def test_rmat26_first_epochs_match_oracle(big, oracle):
         co = ref["c"]
         maxf.append(ref["max_f"][-1])
         maxg.append(ref["max_g"][-1])
-        print(f"oracle epoch {k} done: tau={ref['tau']} reason={ref['reason']}", flush=True)
+        say(request, f"oracle epoch {k} done: tau={ref['tau']} reason={ref['reason']}")
     assert not any(stops[:3])
     assert tau == ref["tau"]
     assert np.array_equal(c, co)
